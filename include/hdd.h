@@ -1,0 +1,214 @@
+/*
+ * hdd.h -- C ABI of the MI355X hierarchical domain decomposition (HDD)
+ * partial inverse for -div(kappa(x, Z) grad u) = f on the unit square with
+ * P1 finite elements and zero Dirichlet data (problem statement, eq.
+ * elliptic; notation of Section 2.1).
+ *
+ * The library builds, for many parameter samples Z at once, the HDD tree
+ * bottom-up ("Leaves to Root", Section 3.4): leaf assembly (Section 3.1,
+ * eq. coefA and eq. coefc), elimination of every subdomain's interface by the
+ * Schur complement (Section 2.4, eq. SchurMinus1 / eq. SchurC1; merge of two
+ * sons, Section 3.2-3.3, eq. block_equation4 and eq. gamma), keeping the maps
+ * Phi of every node in factored form.  Queries then run "Root to Leaves"
+ * only along the paths they need (Section 5.3) and apply the measurement
+ * operators of Section 1.2 (point values; integral / mean over a subdomain,
+ * eq. mean) and the Gaussian likelihood L(z) = prod pi_eps(y_i - S_i(z)).
+ *
+ * Conventions (all entry points):
+ *  - Every call returns an int status: HDD_OK (0) or a negative HDD_E* code;
+ *    no exception crosses the ABI.  hdd_strerror() names a code.
+ *  - Mesh: N interior nodes per side, Nc = N + 1 cells, h = 1/Nc; Nc must be
+ *    leaf * 2^p and leaf must be 2 * 2^q.  Cell (i, j) is split along its
+ *    SW-NE diagonal into T- (index 0) and T+ (index 1).
+ *  - kappa: float64 [n_samples][Nc][Nc][2], per triangle, [j][i][T-/T+],
+ *    strictly positive and finite.  f: float64 [N+2][N+2] nodal, [j][i]
+ *    (boundary entries are read by the leaf assembly but multiply zero data).
+ *  - Pointer kind: arguments documented "(mem)" are host pointers when the
+ *    call's `mem` argument is HDD_MEM_HOST and device pointers (HBM) when it
+ *    is HDD_MEM_DEVICE.  Other pointers are host pointers.  Inputs are read
+ *    during the call only (device inputs: before the call's work on the
+ *    handle's stream completes); outputs are caller-allocated.
+ *  - Work is issued on the handle's stream.  Calls that return host data
+ *    synchronize that stream; device-output calls do not.
+ *  - A handle is not thread safe; calls on one handle are ordered.
+ */
+#ifndef HDD_H_
+#define HDD_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define HDD_OK 0
+#define HDD_EINVAL (-1)         /* bad argument, shape or non-positive/non-finite kappa */
+#define HDD_ENOMEM (-2)         /* workspace too small / device allocation failed */
+#define HDD_ENOTSPD (-3)        /* non-positive pivot in an interface factorization; see hdd_last_node */
+#define HDD_ENOTCONVERGED (-4)  /* iterative refinement did not reach refine_tol in max_refine sweeps */
+#define HDD_EDEVICE (-5)        /* HIP runtime error */
+#define HDD_ESTATE (-6)         /* call out of order (e.g. query before build) */
+
+/* precision modes */
+#define HDD_FP64 0          /* every level factored in float64 */
+#define HDD_FP32_REFINE 1   /* float32 levels (matrix-core Schur updates), the top
+                               fp64_top_levels levels in float64, then float64
+                               iterative refinement of the full field against the
+                               assembled operator */
+
+/* pointer kinds */
+#define HDD_MEM_HOST 0
+#define HDD_MEM_DEVICE 1
+
+/* option flags */
+#define HDD_FLAG_NO_MFMA 1        /* use the plain FMA Schur update (cross-check) */
+#define HDD_FLAG_KEEP_DIRICHLET 2 /* plan only: keep outer-boundary nodes in every Gamma */
+
+typedef struct hdd_opts {
+  int32_t n;               /* N, interior nodes per side */
+  int32_t leaf;            /* leaf size in cells (tree granularity); default 2 * 2^q <= Nc */
+  int32_t precision;       /* HDD_FP64 or HDD_FP32_REFINE */
+  int32_t fp64_top_levels; /* HDD_FP32_REFINE: levels (from the root) kept in float64; default 2 */
+  int32_t max_refine;      /* refinement sweeps allowed (HDD_FP32_REFINE default 6; HDD_FP64 default 0) */
+  int32_t flags;           /* HDD_FLAG_* */
+  double refine_tol;       /* stop when max|du| <= refine_tol * max|u| (default 1e-12) */
+  int32_t reserved[8];     /* must be zero */
+} hdd_opts;
+
+typedef struct hdd_tree* hdd_handle;
+
+/* Fill *opts with defaults for mesh size n and the given precision. */
+int hdd_default_opts(int32_t n, int32_t precision, hdd_opts* opts);
+
+/* Bytes of device workspace a handle for max_samples samples needs. */
+int hdd_workspace_size(const hdd_opts* opts, int32_t max_samples, size_t* bytes);
+
+/*
+ * Create a handle: plan the tree (Section 2.1) and lay out device memory for
+ * up to max_samples parameter samples.
+ *   stream     hipStream_t to issue all work on (NULL: a stream the handle owns)
+ *   workspace  device buffer of at least hdd_workspace_size() bytes, owned by
+ *              the caller and kept alive until hdd_destroy (NULL: the handle
+ *              allocates and owns it)
+ * Errors: HDD_EINVAL (options), HDD_ENOMEM (workspace too small or
+ * allocation failure), HDD_EDEVICE.
+ */
+int hdd_create(const hdd_opts* opts, int32_t max_samples, void* stream, void* workspace, size_t workspace_bytes,
+               hdd_handle* out);
+
+/*
+ * Leaves to Root for n_samples (<= max_samples) samples: assemble every leaf,
+ * eliminate every interface, keep all factors (Section 3.4).
+ *   kappa  (mem) float64 [n_samples][Nc][Nc][2]
+ *   f      (mem) float64 [N+2][N+2], shared by all samples
+ *   g      must be NULL (zero Dirichlet data)
+ * Invalidates earlier query results.  Errors: HDD_EINVAL (shape, g != NULL,
+ * kappa <= 0 or non-finite: detected on the device and reported by the next
+ * synchronizing call), HDD_ENOTSPD (reported by the next synchronizing call),
+ * HDD_EDEVICE.
+ */
+int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double* f, const double* g, int32_t mem);
+
+/*
+ * Point values u_h(x) for all built samples (measurement example b,
+ * Section 1.2), by P1 interpolation in the triangle that holds x.  Runs Root
+ * to Leaves only on the nodes whose interfaces bound the micro-blocks that
+ * hold the points (Section 5.3), unless the full field is already solved
+ * (always the case in HDD_FP32_REFINE mode, whose refinement needs it).
+ *   xy     host float64 [n_pts][2] in [0,1]^2
+ *   u_out  (mem) float64 [n_samples][n_pts]
+ */
+int hdd_query_points(hdd_handle h, int32_t n_pts, const double* xy, double* u_out, int32_t mem);
+
+/*
+ * u on the root interface gamma_Omega, the vertical midline x = 1/2
+ * (setup (a) of Fig. HDDidea): u_out (mem) float64 [n_samples][N], *len = N.
+ */
+int hdd_query_interface(hdd_handle h, double* u_out, int32_t* len, int32_t mem);
+
+/*
+ * Mean of u over the cell-aligned rectangle rect = {x0, x1, y0, y1} (eq. mean;
+ * measurement example a divided by |R|): out (mem) float64 [n_samples].
+ * Solves only the subtree nodes that touch the rectangle and their ancestors.
+ */
+int hdd_query_mean(hdd_handle h, const double rect[4], double* out, int32_t mem);
+
+/*
+ * Log-likelihood of observations y at sites xy for every built sample:
+ *   out[s] = -sum_i (y_i - u_s(x_i))^2 / (2 sigma^2)
+ *            [- n_y log(sigma sqrt(2 pi)) if normalized]
+ * (the likelihood L(z) = prod_i pi_eps(y_i - S_i(z)) of Section 1.2 with
+ * Gaussian noise).  xy: host float64 [n_y][2]; y (mem) float64 [n_y];
+ * out (mem) float64 [n_samples].
+ */
+int hdd_loglik(hdd_handle h, int32_t n_y, const double* xy, const double* y, double sigma, int32_t normalized,
+               double* out, int32_t mem);
+
+/* Root to Leaves on every node (Section 3.4), plus refinement in
+ * HDD_FP32_REFINE mode.  Errors: HDD_ENOTCONVERGED (values still usable). */
+int hdd_solve_full(hdd_handle h);
+
+/* The nodal field of one sample, u_out (mem) float64 [N+2][N+2]; requires
+ * hdd_solve_full. */
+int hdd_get_solution(hdd_handle h, int32_t sample, double* u_out, int32_t mem);
+
+/* Last refinement correction max|du| / max|u| per sample (0 if none ran):
+ * rel_est host float64 [n_samples]; *sweeps = refinement sweeps done. */
+int hdd_error_estimate(hdd_handle h, double* rel_est, int32_t* sweeps);
+
+/* Wait for the handle's stream and report deferred device-side errors. */
+int hdd_sync(hdd_handle h);
+
+/* Global node index + 1 of the first failing interface factorization, 0 if none. */
+int hdd_last_node(hdd_handle h);
+
+int hdd_destroy(hdd_handle h);
+const char* hdd_strerror(int code);
+
+/* ---- inspection (tests, benchmark) ---- */
+
+/* Plan summary: out[0] levels, out[1] nodes, out[2] depth of the leaves,
+ * out[3] depth of the micro-blocks, out[4] per-sample frame elements,
+ * out[5] algorithmic build flops per sample (sum over nodes of
+ * g^3/3 + g^2 G + g G^2).  Host-only; needs no GPU. */
+int hdd_plan_summary(const hdd_opts* opts, int64_t out[6]);
+
+/* One node of the plan: info[0] x0, info[1] y0, info[2] w, info[3] h (cells),
+ * info[4] |gamma|, info[5] |Gamma|; ids (may be NULL, else room for
+ * |gamma|+|Gamma|) receives global node ids (j*(Nc+1)+i) of [gamma ; Gamma].
+ * Host-only; needs no GPU. */
+int hdd_plan_node(const hdd_opts* opts, int32_t depth, int32_t index, int32_t info[6], int32_t* ids);
+
+/* Per-level plan: out[0] nodes, out[1] |gamma|, out[2] max U = |gamma|+max|Gamma|,
+ * out[3] 1 if the level is float64 in this precision mode.  Host-only. */
+int hdd_plan_level(const hdd_opts* opts, int32_t depth, int32_t out[4]);
+
+/* Schur complement data of one built node: S (host float64 [|Gamma|+1]^2,
+ * row-major, full symmetric, last row/column = condensed load g_omega and
+ * its transpose, corner undefined) and ids (host, |Gamma| global node ids).
+ * After the build S is the Schur complement S_omega = Psi^g_omega on the
+ * node's boundary (Section 2.4).  Synchronizes. */
+int hdd_debug_node_schur(hdd_handle h, int32_t sample, int32_t depth, int32_t index, double* S, int32_t* ids);
+
+/* Timing of kernel classes with HIP events around every launch of the class
+ * on the handle's stream.  kind: 0 Schur update (rank-k, matrix cores),
+ * 1 interface factorization (diagonal + row solves), 2 extend-add,
+ * 3 leaf assembly, 4 top-down, 5 forward pass, 6 residual.
+ * hdd_timing_enable(h, mask): bit k enables kind k (0 disables and clears).
+ * hdd_timing_get: total milliseconds, number of launches and summed
+ * algorithmic flops of the timed launches (Schur update: 2 K per lower-
+ * triangle output element; 0 for other kinds).  Synchronizes. */
+int hdd_timing_enable(hdd_handle h, int32_t mask);
+int hdd_timing_get(hdd_handle h, int32_t kind, double* ms, int64_t* launches, double* flops);
+
+/* Matrix-core lane-layout self check: dtype 0 (f32 32x32x2) writes 32*32,
+ * dtype 1 (f64 16x16x4) writes 16*16 products C = A B^T of fixed integer
+ * patterns into out (host).  Needs a GPU. */
+int hdd_mfma_selftest(int32_t dtype, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDD_H_ */

@@ -1,0 +1,768 @@
+// C ABI of the HDD library (declarations and documentation in include/hdd.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hdd.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using hdd::DevLevel;
+using hdd::DevNode;
+using hdd::Plan;
+
+namespace {
+
+constexpr int kKinds = 7;
+enum Kind { K_SYRK = 0, K_FACTOR = 1, K_EXTEND = 2, K_ASSEMBLE = 3, K_TOPDOWN = 4, K_FORWARD = 5, K_RESIDUAL = 6 };
+
+int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+
+bool refinement_possible(const hdd_opts& o) { return o.precision == HDD_FP32_REFINE || o.max_refine > 0; }
+
+bool level_double(const hdd_opts& o, int depth) {
+  return o.precision == HDD_FP64 || depth < o.fp64_top_levels;
+}
+
+int validate_opts(const hdd_opts* o) {
+  if (!o) return HDD_EINVAL;
+  if (o->precision != HDD_FP64 && o->precision != HDD_FP32_REFINE) return HDD_EINVAL;
+  if (o->fp64_top_levels < 0 || o->max_refine < 0 || !(o->refine_tol >= 0.0)) return HDD_EINVAL;
+  for (int i = 0; i < 8; ++i)
+    if (o->reserved[i] != 0) return HDD_EINVAL;
+  return HDD_OK;
+}
+
+bool make_plan(const hdd_opts& o, Plan& p) {
+  hdd::PlanOptions po;
+  po.n = o.n;
+  po.leaf = o.leaf;
+  po.micro = 2;
+  po.keep_dirichlet = (o.flags & HDD_FLAG_KEEP_DIRICHLET) != 0;
+  return hdd::build_plan(po, p);
+}
+
+// Byte offsets of everything the handle keeps in its device workspace.
+struct Layout {
+  std::vector<int64_t> frames, nodes, maps, ids, vec;
+  int64_t kappa, f, u, d, r, info, bad, maxbits, qout, qxy, qy, lists, iota;
+  int64_t max_q;
+  int64_t total;
+};
+
+Layout make_layout(const Plan& p, const hdd_opts& o, int ms) {
+  Layout L;
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t at = off;
+    off += align256(std::max<int64_t>(bytes, 0));
+    return at;
+  };
+  const int nd = int(p.levels.size());
+  L.frames.resize(nd); L.nodes.resize(nd); L.maps.resize(nd); L.ids.resize(nd); L.vec.resize(nd);
+  const bool refine = refinement_possible(o);
+  int64_t total_nodes = 0, max_nodes = 0;
+  for (int d = 0; d < nd; ++d) {
+    const auto& lv = p.levels[d];
+    const int64_t esz = level_double(o, d) ? 8 : 4;
+    L.frames[d] = take(lv.frame_elems * esz * ms);
+    L.nodes[d] = take(int64_t(lv.nodes.size()) * int64_t(sizeof(DevNode)));
+    L.maps[d] = take(int64_t(lv.maps.size()) * 4);
+    L.ids[d] = take(int64_t(lv.ids.size()) * 4);
+    L.vec[d] = refine ? take(int64_t(lv.ids.size()) * 8 * ms) : -1;
+    total_nodes += int64_t(lv.nodes.size());
+    max_nodes = std::max<int64_t>(max_nodes, int64_t(lv.nodes.size()));
+  }
+  const int64_t nc = p.nc;
+  const int64_t nn = (nc + 1) * (nc + 1);
+  L.max_q = std::max<int64_t>(4096, nc);
+  L.kappa = take(int64_t(ms) * nc * nc * 2 * 8);
+  L.f = take(nn * 8);
+  L.u = take(int64_t(ms) * nn * 8);
+  L.d = refine ? take(int64_t(ms) * nn * 8) : -1;
+  L.r = refine ? take(int64_t(ms) * nn * 8) : -1;
+  L.info = take(int64_t(ms) * 4);
+  L.bad = take(int64_t(ms) * 4);
+  L.maxbits = take(int64_t(ms) * 16);
+  L.qout = take(int64_t(ms) * L.max_q * 8);
+  L.qxy = take(L.max_q * 16);
+  L.qy = take(L.max_q * 8);
+  L.lists = take(total_nodes * 4);
+  L.iota = take(max_nodes * 4);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct hdd_tree {
+  hdd_opts opt{};
+  Plan plan;
+  Layout lay;
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  int max_samples = 0, n_samples = 0;
+  char* ws = nullptr;
+  bool own_ws = false;
+  std::vector<DevLevel> lev;
+  std::vector<int64_t> lev_list_off;  // offset (in ints) of each level's node list
+  long long nn = 0;
+  double *kappa = nullptr, *f = nullptr, *u = nullptr, *d = nullptr, *r = nullptr;
+  int *info = nullptr, *bad = nullptr;
+  unsigned long long* maxbits = nullptr;
+  double *qout = nullptr, *qxy = nullptr, *qy = nullptr;
+  int *lists = nullptr, *iota = nullptr;
+  int* pinned_lists = nullptr;
+  hipEvent_t lists_done = nullptr;
+  bool built = false, full = false;
+  std::vector<std::vector<uint8_t>> solved;
+  std::vector<double> est;
+  int sweeps = 0;
+  int last_node = 0;
+  int deferred = HDD_OK;
+  // timing
+  int timing_mask = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct Rec { int kind; hipEvent_t a, b; double flops; };
+  std::vector<Rec> recs;
+};
+
+namespace {
+
+int hip_status(hipError_t e) { return e == hipSuccess ? HDD_OK : HDD_EDEVICE; }
+
+#define HDD_TRY(expr)                      \
+  do {                                     \
+    const int _st = (expr);                \
+    if (_st != HDD_OK) return _st;         \
+  } while (0)
+#define HIP_TRY(expr) HDD_TRY(hip_status(expr))
+
+hipEvent_t next_event(hdd_tree* h) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_used++];
+}
+
+// Runs `launch` and, when the kind is being timed, brackets it with events.
+template <typename F>
+int timed(hdd_tree* h, int kind, double flops, F&& launch) {
+  if (!(h->timing_mask & (1 << kind))) return hip_status(launch());
+  hipEvent_t a = next_event(h), b = next_event(h);
+  if (!a || !b) return HDD_EDEVICE;
+  HIP_TRY(hipEventRecord(a, h->st));
+  HIP_TRY(launch());
+  HIP_TRY(hipEventRecord(b, h->st));
+  h->recs.push_back({kind, a, b, flops});
+  return HDD_OK;
+}
+
+// lower-triangle elements (i, j) with r0 <= i <= U, c0 <= j < c1e, j <= i
+double lower_count(int r0, int U, int c0, int c1e) {
+  double n = 0;
+  for (int i = r0; i <= U; ++i) {
+    const int hi = std::min(c1e - 1, i);
+    if (hi >= c0) n += hi - c0 + 1;
+  }
+  return n;
+}
+
+double syrk_flops(const hdd_tree* h, int d, int k0, int k1, int r0, int c0, int c1) {
+  double tot = 0;
+  for (const auto& nd : h->plan.levels[d].nodes) {
+    const int U = nd.U();
+    tot += lower_count(r0, U, c0, c1 < 0 ? U + 1 : c1);
+  }
+  return tot * 2.0 * (k1 - k0) * h->n_samples;
+}
+
+int check_deferred(hdd_tree* h) {
+  HIP_TRY(hipStreamSynchronize(h->st));
+  if (!h->built) return h->deferred;
+  std::vector<int> info(h->n_samples), bad(h->n_samples);
+  HIP_TRY(hipMemcpy(info.data(), h->info, sizeof(int) * h->n_samples, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(bad.data(), h->bad, sizeof(int) * h->n_samples, hipMemcpyDeviceToHost));
+  for (int s = 0; s < h->n_samples; ++s)
+    if (bad[s]) return HDD_EINVAL;
+  for (int s = 0; s < h->n_samples; ++s)
+    if (info[s]) {
+      h->last_node = info[s];
+      return HDD_ENOTSPD;
+    }
+  return h->deferred;
+}
+
+int run_topdown_level(hdd_tree* h, int d, const int* list_dev, int n_list, double* target, bool from_vec) {
+  const DevLevel& L = h->lev[d];
+  return timed(h, K_TOPDOWN, 0.0, [&] {
+    return hdd::launch_topdown(L, list_dev, n_list, h->n_samples, target, h->nn, from_vec, h->st);
+  });
+}
+
+int full_topdown(hdd_tree* h, double* target, bool from_vec) {
+  for (size_t d = 0; d < h->lev.size(); ++d)
+    HDD_TRY(run_topdown_level(h, int(d), h->iota, h->lev[d].n_nodes, target, from_vec));
+  return HDD_OK;
+}
+
+int ensure_full(hdd_tree* h) {
+  if (h->full) return HDD_OK;
+  HDD_TRY(full_topdown(h, h->u, false));
+  for (auto& v : h->solved) std::fill(v.begin(), v.end(), 1);
+  h->full = true;
+  h->sweeps = 0;
+  std::fill(h->est.begin(), h->est.end(), 0.0);
+  const int max_it = h->opt.max_refine;
+  if (max_it <= 0 || h->d == nullptr) return HDD_OK;
+  const int D = int(h->lev.size()) - 1;
+  const int nc = h->plan.nc;
+  const int ns = h->n_samples;
+  std::vector<unsigned long long> mb(2 * ns);
+  bool converged = false;
+  for (int it = 0; it < max_it; ++it) {
+    HDD_TRY(timed(h, K_RESIDUAL, 0.0, [&] { return hdd::launch_residual(nc, ns, h->kappa, h->f, h->u, h->r, h->st); }));
+    for (int d = D; d >= 0; --d) {
+      const DevLevel* child = d < D ? &h->lev[d + 1] : nullptr;
+      HDD_TRY(timed(h, K_FORWARD, 0.0, [&] {
+        return hdd::launch_forward(h->lev[d], child, ns, h->r, h->nn, nc, h->plan.opt.micro, h->st);
+      }));
+    }
+    HIP_TRY(hdd::launch_fill(h->d, (long long)ns * h->nn, 0.0, h->st));
+    HDD_TRY(full_topdown(h, h->d, true));
+    HIP_TRY(hipMemsetAsync(h->maxbits, 0, sizeof(unsigned long long) * 2 * ns, h->st));
+    HIP_TRY(hdd::launch_axpy_maxabs(nc, ns, h->u, h->d, h->maxbits, h->st));
+    HIP_TRY(hipMemcpyAsync(mb.data(), h->maxbits, sizeof(unsigned long long) * 2 * ns, hipMemcpyDeviceToHost, h->st));
+    HIP_TRY(hipStreamSynchronize(h->st));
+    h->sweeps = it + 1;
+    double worst = 0.0;
+    for (int s = 0; s < ns; ++s) {
+      double md, mu;
+      std::memcpy(&md, &mb[2 * s], 8);
+      std::memcpy(&mu, &mb[2 * s + 1], 8);
+      h->est[s] = mu > 0 ? md / mu : md;
+      worst = std::max(worst, h->est[s]);
+    }
+    if (worst <= h->opt.refine_tol) {
+      converged = true;
+      break;
+    }
+  }
+  if (!converged) h->deferred = HDD_ENOTCONVERGED;
+  return HDD_OK;
+}
+
+// Solve, root first, the nodes marked in `need` that are not solved yet.
+int partial_topdown(hdd_tree* h, const std::vector<std::vector<uint8_t>>& need) {
+  HIP_TRY(hipEventSynchronize(h->lists_done));
+  int64_t total = 0;
+  std::vector<int> counts(h->lev.size(), 0);
+  for (size_t d = 0; d < h->lev.size(); ++d) {
+    int* dst = h->pinned_lists + h->lev_list_off[d];
+    int c = 0;
+    for (size_t k = 0; k < need[d].size(); ++k)
+      if (need[d][k] && !h->solved[d][k]) dst[c++] = int(k);
+    counts[d] = c;
+    total += c;
+  }
+  if (total == 0) return HDD_OK;
+  HIP_TRY(hipMemcpyAsync(h->lists, h->pinned_lists, sizeof(int) * (h->lev_list_off.back() + h->lev.back().n_nodes),
+                         hipMemcpyHostToDevice, h->st));
+  HIP_TRY(hipEventRecord(h->lists_done, h->st));
+  for (size_t d = 0; d < h->lev.size(); ++d) {
+    if (!counts[d]) continue;
+    HDD_TRY(run_topdown_level(h, int(d), h->lists + h->lev_list_off[d], counts[d], h->u, false));
+    for (size_t k = 0; k < need[d].size(); ++k)
+      if (need[d][k]) h->solved[d][k] = 1;
+  }
+  return HDD_OK;
+}
+
+// Mark the path root -> micro-block holding cell (ci, cj).
+void mark_cell_path(const hdd_tree* h, int ci, int cj, std::vector<std::vector<uint8_t>>& need) {
+  int k = 0;
+  for (size_t d = 0; d < h->plan.levels.size(); ++d) {
+    const auto& nd = h->plan.levels[d].nodes[k];
+    need[d][k] = 1;
+    if (nd.micro) break;
+    int s;
+    if (nd.vertical) s = ci >= nd.x0 + nd.w / 2 ? 1 : 0;
+    else s = cj >= nd.y0 + nd.h / 2 ? 1 : 0;
+    k = 2 * k + s;
+  }
+}
+
+std::vector<std::vector<uint8_t>> empty_need(const hdd_tree* h) {
+  std::vector<std::vector<uint8_t>> need(h->lev.size());
+  for (size_t d = 0; d < h->lev.size(); ++d) need[d].assign(h->lev[d].n_nodes, 0);
+  return need;
+}
+
+int prepare_values(hdd_tree* h, const std::vector<std::vector<uint8_t>>& need) {
+  if (h->full) return HDD_OK;
+  if (h->opt.max_refine > 0) return ensure_full(h);
+  return partial_topdown(h, need);
+}
+
+int copy_out(hdd_tree* h, double* dst, const double* src_dev, size_t n, int mem) {
+  if (mem == HDD_MEM_DEVICE) return hip_status(hipMemcpyAsync(dst, src_dev, n * 8, hipMemcpyDeviceToDevice, h->st));
+  HIP_TRY(hipMemcpyAsync(dst, src_dev, n * 8, hipMemcpyDeviceToHost, h->st));
+  return check_deferred(h);
+}
+
+}  // namespace
+
+extern "C" {
+
+int hdd_default_opts(int32_t n, int32_t precision, hdd_opts* o) {
+  if (!o || n < 1) return HDD_EINVAL;
+  std::memset(o, 0, sizeof(*o));
+  o->n = n;
+  const int nc = n + 1;
+  int leaf = 32;
+  while (leaf > 2 && (nc % leaf != 0 || leaf > nc)) leaf >>= 1;
+  o->leaf = leaf;
+  o->precision = precision;
+  o->fp64_top_levels = 2;
+  o->max_refine = precision == HDD_FP32_REFINE ? 6 : 0;
+  o->refine_tol = 1e-12;
+  return validate_opts(o);
+}
+
+int hdd_workspace_size(const hdd_opts* o, int32_t max_samples, size_t* bytes) {
+  HDD_TRY(validate_opts(o));
+  if (max_samples < 1 || !bytes) return HDD_EINVAL;
+  Plan p;
+  if (!make_plan(*o, p)) return HDD_EINVAL;
+  *bytes = size_t(make_layout(p, *o, max_samples).total);
+  return HDD_OK;
+}
+
+int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* workspace, size_t workspace_bytes,
+               hdd_handle* out) {
+  HDD_TRY(validate_opts(o));
+  if (max_samples < 1 || !out) return HDD_EINVAL;
+  hdd_tree* h = new (std::nothrow) hdd_tree();
+  if (!h) return HDD_ENOMEM;
+  h->opt = *o;
+  if (!make_plan(*o, h->plan)) {
+    delete h;
+    return HDD_EINVAL;
+  }
+  h->max_samples = max_samples;
+  h->lay = make_layout(h->plan, *o, max_samples);
+  auto fail = [&](int code) {
+    hdd_destroy(h);
+    return code;
+  };
+  if (hipGetDevice(&h->device) != hipSuccess) return fail(HDD_EDEVICE);
+  if (stream) {
+    h->st = static_cast<hipStream_t>(stream);
+  } else {
+    if (hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking) != hipSuccess) return fail(HDD_EDEVICE);
+    h->own_stream = true;
+  }
+  if (workspace) {
+    if (workspace_bytes < size_t(h->lay.total)) return fail(HDD_ENOMEM);
+    h->ws = static_cast<char*>(workspace);
+  } else {
+    if (hipMalloc(&h->ws, size_t(h->lay.total)) != hipSuccess) {
+      h->ws = nullptr;
+      return fail(HDD_ENOMEM);
+    }
+    h->own_ws = true;
+  }
+  const Layout& L = h->lay;
+  const int nd = int(h->plan.levels.size());
+  h->lev.resize(nd);
+  h->lev_list_off.resize(nd);
+  h->solved.resize(nd);
+  int64_t list_off = 0, node_base = 0;
+  for (int d = 0; d < nd; ++d) {
+    const auto& pl = h->plan.levels[d];
+    std::vector<DevNode> dn(pl.nodes.size());
+    for (size_t k = 0; k < pl.nodes.size(); ++k) {
+      const auto& p = pl.nodes[k];
+      dn[k].frame_off = p.frame_off;
+      dn[k].map_off = p.map_off;
+      dn[k].U = p.U();
+      dn[k].bnd = int(p.bnd.size());
+      dn[k].ld = p.ld;
+      dn[k].ids_off = int(p.ids_off);
+      dn[k].x0 = p.x0;
+      dn[k].y0 = p.y0;
+    }
+    DevLevel& lv = h->lev[d];
+    lv.frames = h->ws + L.frames[d];
+    lv.stride = pl.frame_elems;
+    lv.nodes = reinterpret_cast<const DevNode*>(h->ws + L.nodes[d]);
+    lv.maps = reinterpret_cast<const int*>(h->ws + L.maps[d]);
+    lv.ids = reinterpret_cast<const int*>(h->ws + L.ids[d]);
+    lv.vec = L.vec[d] >= 0 ? reinterpret_cast<double*>(h->ws + L.vec[d]) : nullptr;
+    lv.vec_stride = (long long)pl.ids.size();
+    lv.n_nodes = int(pl.nodes.size());
+    lv.gam = pl.gam;
+    lv.max_U = pl.max_U;
+    lv.is_double = level_double(*o, d) ? 1 : 0;
+    lv.depth = d;
+    lv.node_base = int(node_base);
+    node_base += lv.n_nodes;
+    if (hipMemcpy(h->ws + L.nodes[d], dn.data(), dn.size() * sizeof(DevNode), hipMemcpyHostToDevice) != hipSuccess ||
+        (!pl.maps.empty() &&
+         hipMemcpy(h->ws + L.maps[d], pl.maps.data(), pl.maps.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(h->ws + L.ids[d], pl.ids.data(), pl.ids.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(HDD_EDEVICE);
+    h->lev_list_off[d] = list_off;
+    list_off += lv.n_nodes;
+    h->solved[d].assign(lv.n_nodes, 0);
+  }
+  h->nn = (long long)(h->plan.nc + 1) * (h->plan.nc + 1);
+  h->kappa = reinterpret_cast<double*>(h->ws + L.kappa);
+  h->f = reinterpret_cast<double*>(h->ws + L.f);
+  h->u = reinterpret_cast<double*>(h->ws + L.u);
+  h->d = L.d >= 0 ? reinterpret_cast<double*>(h->ws + L.d) : nullptr;
+  h->r = L.r >= 0 ? reinterpret_cast<double*>(h->ws + L.r) : nullptr;
+  h->info = reinterpret_cast<int*>(h->ws + L.info);
+  h->bad = reinterpret_cast<int*>(h->ws + L.bad);
+  h->maxbits = reinterpret_cast<unsigned long long*>(h->ws + L.maxbits);
+  h->qout = reinterpret_cast<double*>(h->ws + L.qout);
+  h->qxy = reinterpret_cast<double*>(h->ws + L.qxy);
+  h->qy = reinterpret_cast<double*>(h->ws + L.qy);
+  h->lists = reinterpret_cast<int*>(h->ws + L.lists);
+  h->iota = reinterpret_cast<int*>(h->ws + L.iota);
+  if (hipHostMalloc(&h->pinned_lists, sizeof(int) * size_t(std::max<int64_t>(list_off, 1))) != hipSuccess) {
+    h->pinned_lists = nullptr;
+    return fail(HDD_ENOMEM);
+  }
+  {
+    int64_t mx = 0;
+    for (auto& lv : h->lev) mx = std::max<int64_t>(mx, lv.n_nodes);
+    std::vector<int> io(mx);
+    for (int64_t k = 0; k < mx; ++k) io[k] = int(k);
+    if (hipMemcpy(h->iota, io.data(), io.size() * 4, hipMemcpyHostToDevice) != hipSuccess) return fail(HDD_EDEVICE);
+  }
+  if (hipEventCreateWithFlags(&h->lists_done, hipEventDisableTiming) != hipSuccess) {
+    h->lists_done = nullptr;
+    return fail(HDD_EDEVICE);
+  }
+  if (hipEventRecord(h->lists_done, h->st) != hipSuccess) return fail(HDD_EDEVICE);
+  *out = h;
+  return HDD_OK;
+}
+
+int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double* f, const double* g, int32_t mem) {
+  if (!h || !kappa || !f || g != nullptr || n_samples < 1 || n_samples > h->max_samples) return HDD_EINVAL;
+  if (mem != HDD_MEM_HOST && mem != HDD_MEM_DEVICE) return HDD_EINVAL;
+  const int nc = h->plan.nc;
+  const size_t kbytes = size_t(n_samples) * nc * nc * 2 * 8;
+  const size_t fbytes = size_t(h->nn) * 8;
+  if (mem == HDD_MEM_HOST) {
+    for (size_t i = 0; i < kbytes / 8; ++i)
+      if (!(kappa[i] > 0.0) || !std::isfinite(kappa[i])) return HDD_EINVAL;
+    HIP_TRY(hipMemcpyAsync(h->kappa, kappa, kbytes, hipMemcpyHostToDevice, h->st));
+    HIP_TRY(hipMemcpyAsync(h->f, f, fbytes, hipMemcpyHostToDevice, h->st));
+  } else {
+    HIP_TRY(hipMemcpyAsync(h->kappa, kappa, kbytes, hipMemcpyDeviceToDevice, h->st));
+    HIP_TRY(hipMemcpyAsync(h->f, f, fbytes, hipMemcpyDeviceToDevice, h->st));
+  }
+  h->n_samples = n_samples;
+  h->built = false;
+  h->full = false;
+  h->deferred = HDD_OK;
+  h->last_node = 0;
+  h->est.assign(n_samples, 0.0);
+  h->sweeps = 0;
+  for (auto& v : h->solved) std::fill(v.begin(), v.end(), 0);
+  HIP_TRY(hipMemsetAsync(h->info, 0, sizeof(int) * n_samples, h->st));
+  HIP_TRY(hipMemsetAsync(h->bad, 0, sizeof(int) * n_samples, h->st));
+  const int D = int(h->lev.size()) - 1;
+  const bool mfma = !(h->opt.flags & HDD_FLAG_NO_MFMA);
+  auto eliminate = [&](int d) -> int {
+    const DevLevel& L = h->lev[d];
+    const int g = L.gam;
+    for (int k0 = 0; k0 < g; k0 += hdd::kPanelNB) {
+      const int kb = std::min(hdd::kPanelNB, g - k0);
+      HDD_TRY(timed(h, K_FACTOR, 0.0, [&] { return hdd::launch_panel(L, k0, kb, n_samples, h->info, h->st); }));
+      if (k0 + kb < g) {
+        const double fl = (h->timing_mask & 1) ? syrk_flops(h, d, k0, k0 + kb, k0 + kb, k0 + kb, g) : 0.0;
+        HDD_TRY(timed(h, K_SYRK, fl, [&] {
+          return hdd::launch_syrk(L, k0, k0 + kb, k0 + kb, k0 + kb, g, n_samples, mfma, h->st);
+        }));
+      }
+    }
+    if (L.max_U > g) {  // Schur update of Gamma (and the boundary load row)
+      const double fl = (h->timing_mask & 1) ? syrk_flops(h, d, 0, g, g, g, -1) : 0.0;
+      HDD_TRY(timed(h, K_SYRK, fl, [&] { return hdd::launch_syrk(L, 0, g, g, g, -1, n_samples, mfma, h->st); }));
+    }
+    return HDD_OK;
+  };
+  HDD_TRY(timed(h, K_ASSEMBLE, 0.0, [&] {
+    return hdd::launch_assemble_micro(h->lev[D], n_samples, nc, h->kappa, h->f, h->bad, h->st);
+  }));
+  HDD_TRY(eliminate(D));
+  for (int d = D - 1; d >= 0; --d) {
+    HDD_TRY(timed(h, K_EXTEND, 0.0, [&] { return hdd::launch_extend_add(h->lev[d], h->lev[d + 1], n_samples, h->st); }));
+    HDD_TRY(eliminate(d));
+  }
+  HIP_TRY(hdd::launch_fill(h->u, (long long)n_samples * h->nn, 0.0, h->st));
+  h->built = true;
+  return HDD_OK;
+}
+
+int hdd_query_points(hdd_handle h, int32_t n_pts, const double* xy, double* u_out, int32_t mem) {
+  if (!h || n_pts < 1 || !xy || !u_out || n_pts > h->lay.max_q) return HDD_EINVAL;
+  if (!h->built) return HDD_ESTATE;
+  const int nc = h->plan.nc;
+  auto need = empty_need(h);
+  for (int p = 0; p < n_pts; ++p) {
+    const double x = xy[2 * p], y = xy[2 * p + 1];
+    if (!(x >= 0.0 && x <= 1.0 && y >= 0.0 && y <= 1.0)) return HDD_EINVAL;
+    const int ci = std::min(int(std::floor(x * nc)), nc - 1), cj = std::min(int(std::floor(y * nc)), nc - 1);
+    mark_cell_path(h, ci, cj, need);
+  }
+  HDD_TRY(prepare_values(h, need));
+  HIP_TRY(hipMemcpyAsync(h->qxy, xy, size_t(n_pts) * 16, hipMemcpyHostToDevice, h->st));
+  double* dst = mem == HDD_MEM_DEVICE ? u_out : h->qout;
+  HIP_TRY(hdd::launch_points(nc, h->n_samples, n_pts, h->qxy, h->u, dst, h->st));
+  if (mem == HDD_MEM_DEVICE) return HDD_OK;
+  return copy_out(h, u_out, h->qout, size_t(n_pts) * h->n_samples, HDD_MEM_HOST);
+}
+
+int hdd_query_interface(hdd_handle h, double* u_out, int32_t* len, int32_t mem) {
+  if (!h || !u_out) return HDD_EINVAL;
+  if (!h->built) return HDD_ESTATE;
+  auto need = empty_need(h);
+  need[0][0] = 1;
+  HDD_TRY(prepare_values(h, need));
+  const int n = h->plan.nc - 1;
+  if (len) *len = n;
+  double* dst = mem == HDD_MEM_DEVICE ? u_out : h->qout;
+  HIP_TRY(hdd::launch_interface(h->plan.nc, h->n_samples, h->u, dst, h->st));
+  if (mem == HDD_MEM_DEVICE) return HDD_OK;
+  return copy_out(h, u_out, h->qout, size_t(n) * h->n_samples, HDD_MEM_HOST);
+}
+
+int hdd_query_mean(hdd_handle h, const double rect[4], double* out, int32_t mem) {
+  if (!h || !rect || !out) return HDD_EINVAL;
+  if (!h->built) return HDD_ESTATE;
+  const int nc = h->plan.nc;
+  int b[4];
+  for (int q = 0; q < 4; ++q) {
+    const double v = rect[q] * nc;
+    b[q] = int(std::lround(v));
+    if (!(rect[q] >= 0.0 && rect[q] <= 1.0) || std::fabs(v - b[q]) > 1e-9) return HDD_EINVAL;
+  }
+  if (b[1] <= b[0] || b[3] <= b[2]) return HDD_EINVAL;
+  auto need = empty_need(h);
+  const int m = h->plan.opt.micro;
+  for (int cj = b[2]; cj < b[3]; ++cj)
+    for (int ci = b[0]; ci < b[1]; ++ci)
+      if (ci % m == 0 || ci == b[0])
+        if (cj % m == 0 || cj == b[2]) mark_cell_path(h, ci, cj, need);
+  HDD_TRY(prepare_values(h, need));
+  double* dst = mem == HDD_MEM_DEVICE ? out : h->qout;
+  HIP_TRY(hdd::launch_mean(nc, h->n_samples, b[0], b[1], b[2], b[3], h->u, dst, h->st));
+  if (mem == HDD_MEM_DEVICE) return HDD_OK;
+  return copy_out(h, out, h->qout, size_t(h->n_samples), HDD_MEM_HOST);
+}
+
+int hdd_loglik(hdd_handle h, int32_t n_y, const double* xy, const double* y, double sigma, int32_t normalized,
+               double* out, int32_t mem) {
+  if (!h || n_y < 1 || !xy || !y || !out || !(sigma > 0.0) || n_y >= h->lay.max_q) return HDD_EINVAL;
+  if (!h->built) return HDD_ESTATE;
+  HDD_TRY(hdd_query_points(h, n_y, xy, h->qout, HDD_MEM_DEVICE));
+  const double* ydev = y;
+  if (mem == HDD_MEM_HOST) {
+    HIP_TRY(hipMemcpyAsync(h->qy, y, size_t(n_y) * 8, hipMemcpyHostToDevice, h->st));
+    ydev = h->qy;
+  }
+  double* dst = mem == HDD_MEM_DEVICE ? out : h->qout + size_t(n_y) * h->n_samples;
+  HIP_TRY(hdd::launch_loglik(h->n_samples, n_y, h->qout, ydev, sigma, normalized, dst, h->st));
+  if (mem == HDD_MEM_DEVICE) return HDD_OK;
+  return copy_out(h, out, dst, size_t(h->n_samples), HDD_MEM_HOST);
+}
+
+int hdd_solve_full(hdd_handle h) {
+  if (!h) return HDD_EINVAL;
+  if (!h->built) return HDD_ESTATE;
+  HDD_TRY(ensure_full(h));
+  return check_deferred(h);
+}
+
+int hdd_get_solution(hdd_handle h, int32_t sample, double* u_out, int32_t mem) {
+  if (!h || !u_out || sample < 0 || sample >= h->n_samples) return HDD_EINVAL;
+  if (!h->built || !h->full) return HDD_ESTATE;
+  return copy_out(h, u_out, h->u + (long long)sample * h->nn, size_t(h->nn), mem);
+}
+
+int hdd_error_estimate(hdd_handle h, double* rel_est, int32_t* sweeps) {
+  if (!h || !rel_est) return HDD_EINVAL;
+  for (int s = 0; s < h->n_samples; ++s) rel_est[s] = h->est.empty() ? 0.0 : h->est[s];
+  if (sweeps) *sweeps = h->sweeps;
+  return HDD_OK;
+}
+
+int hdd_sync(hdd_handle h) {
+  if (!h) return HDD_EINVAL;
+  return check_deferred(h);
+}
+
+int hdd_last_node(hdd_handle h) { return h ? h->last_node : 0; }
+
+int hdd_destroy(hdd_handle h) {
+  if (!h) return HDD_OK;
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+  if (h->lists_done) (void)hipEventDestroy(h->lists_done);
+  if (h->pinned_lists) (void)hipHostFree(h->pinned_lists);
+  if (h->own_ws && h->ws) (void)hipFree(h->ws);
+  if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
+  delete h;
+  return HDD_OK;
+}
+
+const char* hdd_strerror(int code) {
+  switch (code) {
+    case HDD_OK: return "ok";
+    case HDD_EINVAL: return "invalid argument";
+    case HDD_ENOMEM: return "out of device memory / workspace too small";
+    case HDD_ENOTSPD: return "interface block not positive definite";
+    case HDD_ENOTCONVERGED: return "iterative refinement did not converge";
+    case HDD_EDEVICE: return "HIP runtime error";
+    case HDD_ESTATE: return "call out of order";
+    default: return "unknown error";
+  }
+}
+
+int hdd_plan_summary(const hdd_opts* o, int64_t out[6]) {
+  HDD_TRY(validate_opts(o));
+  if (!out) return HDD_EINVAL;
+  Plan p;
+  if (!make_plan(*o, p)) return HDD_EINVAL;
+  int64_t nodes = 0, elems = 0;
+  double flops = 0;
+  for (const auto& L : p.levels) {
+    nodes += int64_t(L.nodes.size());
+    elems += L.frame_elems;
+    for (const auto& nd : L.nodes) {
+      const double g = double(nd.gam.size()), G = double(nd.bnd.size());
+      flops += g * g * g / 3.0 + g * g * G + g * G * G;
+    }
+  }
+  out[0] = int64_t(p.levels.size());
+  out[1] = nodes;
+  out[2] = p.depth_leaf;
+  out[3] = p.depth_micro;
+  out[4] = elems;
+  out[5] = int64_t(flops);
+  return HDD_OK;
+}
+
+int hdd_plan_node(const hdd_opts* o, int32_t depth, int32_t index, int32_t info[6], int32_t* ids) {
+  HDD_TRY(validate_opts(o));
+  if (!info) return HDD_EINVAL;
+  Plan p;
+  if (!make_plan(*o, p)) return HDD_EINVAL;
+  if (depth < 0 || depth >= int(p.levels.size())) return HDD_EINVAL;
+  const auto& L = p.levels[depth];
+  if (index < 0 || index >= int(L.nodes.size())) return HDD_EINVAL;
+  const auto& nd = L.nodes[index];
+  info[0] = nd.x0; info[1] = nd.y0; info[2] = nd.w; info[3] = nd.h;
+  info[4] = int(nd.gam.size()); info[5] = int(nd.bnd.size());
+  if (ids) {
+    std::copy(nd.gam.begin(), nd.gam.end(), ids);
+    std::copy(nd.bnd.begin(), nd.bnd.end(), ids + nd.gam.size());
+  }
+  return HDD_OK;
+}
+
+int hdd_plan_level(const hdd_opts* o, int32_t depth, int32_t out[4]) {
+  HDD_TRY(validate_opts(o));
+  if (!out) return HDD_EINVAL;
+  Plan p;
+  if (!make_plan(*o, p)) return HDD_EINVAL;
+  if (depth < 0 || depth >= int(p.levels.size())) return HDD_EINVAL;
+  const auto& L = p.levels[depth];
+  out[0] = int(L.nodes.size());
+  out[1] = L.gam;
+  out[2] = L.max_U;
+  out[3] = level_double(*o, depth) ? 1 : 0;
+  return HDD_OK;
+}
+
+int hdd_debug_node_schur(hdd_handle h, int32_t sample, int32_t depth, int32_t index, double* S, int32_t* ids) {
+  if (!h || !S || !ids) return HDD_EINVAL;
+  if (!h->built) return HDD_ESTATE;
+  if (sample < 0 || sample >= h->n_samples || depth < 0 || depth >= int(h->lev.size())) return HDD_EINVAL;
+  const auto& pl = h->plan.levels[depth];
+  if (index < 0 || index >= int(pl.nodes.size())) return HDD_EINVAL;
+  HDD_TRY(check_deferred(h));
+  const auto& nd = pl.nodes[index];
+  const int U = nd.U(), g = int(nd.gam.size()), G = int(nd.bnd.size()), ld = nd.ld;
+  const bool dbl = h->lev[depth].is_double != 0;
+  const size_t esz = dbl ? 8 : 4;
+  std::vector<char> buf(size_t(U + 1) * ld * esz);
+  const char* src = static_cast<const char*>(h->lev[depth].frames) +
+                    (size_t(sample) * h->lev[depth].stride + size_t(nd.frame_off)) * esz;
+  HIP_TRY(hipMemcpy(buf.data(), src, buf.size(), hipMemcpyDeviceToHost));
+  auto at = [&](int r, int c) -> double {
+    if (r < c) std::swap(r, c);
+    const size_t k = size_t(r) * ld + c;
+    return dbl ? reinterpret_cast<const double*>(buf.data())[k] : double(reinterpret_cast<const float*>(buf.data())[k]);
+  };
+  for (int a = 0; a <= G; ++a)
+    for (int b = 0; b <= G; ++b) S[size_t(a) * (G + 1) + b] = at(g + a, g + b);
+  std::copy(nd.bnd.begin(), nd.bnd.end(), ids);
+  (void)U;
+  return HDD_OK;
+}
+
+int hdd_timing_enable(hdd_handle h, int32_t mask) {
+  if (!h) return HDD_EINVAL;
+  HIP_TRY(hipStreamSynchronize(h->st));
+  h->timing_mask = mask;
+  h->recs.clear();
+  h->ev_used = 0;
+  return HDD_OK;
+}
+
+int hdd_timing_get(hdd_handle h, int32_t kind, double* ms, int64_t* launches, double* flops) {
+  if (!h || kind < 0 || kind >= kKinds) return HDD_EINVAL;
+  HIP_TRY(hipStreamSynchronize(h->st));
+  double tot = 0, fl = 0;
+  int64_t n = 0;
+  for (const auto& r : h->recs) {
+    if (r.kind != kind) continue;
+    float t = 0;
+    HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+    tot += t;
+    fl += r.flops;
+    ++n;
+  }
+  if (ms) *ms = tot;
+  if (launches) *launches = n;
+  if (flops) *flops = fl;
+  return HDD_OK;
+}
+
+int hdd_mfma_selftest(int32_t dtype, double* out) {
+  if (!out || (dtype != 0 && dtype != 1)) return HDD_EINVAL;
+  const size_t n = dtype == 0 ? 32 * 32 : 16 * 16;
+  double* dev = nullptr;
+  HIP_TRY(hipMalloc(&dev, n * 8));
+  hipError_t e = hdd::launch_mfma_selftest(dtype, dev, nullptr);
+  if (e == hipSuccess) e = hipMemcpy(out, dev, n * 8, hipMemcpyDeviceToHost);
+  (void)hipFree(dev);
+  return hip_status(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+// Device-side data structures and helpers shared by the HDD kernels.
+//
+// Frame layout (one per tree node and parameter sample): a dense row-major
+// (U+1) x ld block whose rows and columns are ordered [gamma ; Gamma ; rhs].
+// Only the lower triangle is meaningful.  After the elimination of a node the
+// frame holds, in place:
+//   rows/cols [0, g)          L, the Cholesky factor of the interface block
+//   rows [g, U), cols [0, g)  P = S_Gamma,gamma L^-T
+//   row U, cols [0, g)        z = L^-1 (condensed interface load)
+//   rows/cols [g, U]          S_omega (Schur complement on Gamma) and, in row
+//                             U, the condensed boundary load g_omega
+// which is the retained map Phi of the node (Section 2.4: Phi^g = -A22^-1 A21,
+// Phi^f = A22^-1 F2, here kept in factored form) and the map Psi passed to
+// the father (Psi^g = A11 - A12 A22^-1 A21, Psi^f = F1 - A12 A22^-1 F2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hdd {
+
+struct DevNode {
+  long long frame_off;  // elements within the level's per-sample block
+  long long map_off;    // into the level's map array (2 * (U+1) ints), -1 at micro level
+  int U;                // |gamma| + |Gamma|
+  int bnd;              // |Gamma|
+  int ld;               // frame leading dimension
+  int ids_off;          // into the level's id array ([gamma ; Gamma] global node ids)
+  int x0, y0;           // lower-left cell of the node's rectangle
+};
+
+struct DevLevel {
+  void* frames;          // float* or double*
+  long long stride;      // per-sample elements of this level
+  const DevNode* nodes;
+  const int* maps;
+  const int* ids;
+  double* vec;           // forward-pass vectors [sample][sum U] (refinement)
+  long long vec_stride;  // per-sample elements of vec
+  int n_nodes;
+  int gam;
+  int max_U;
+  int is_double;
+  int depth;
+  int node_base;         // global index of this level's first node (for error reports)
+};
+
+template <typename T> __device__ __forceinline__ T* frame_ptr(const DevLevel& L, int node, int s) {
+  return reinterpret_cast<T*>(L.frames) + (long long)s * L.stride + L.nodes[node].frame_off;
+}
+
+__device__ __forceinline__ int tri_row(long long e) {
+  // row r of the lower-triangle element with flat index e (row-major lower order)
+  int r = int((sqrt(8.0 * double(e) + 1.0) - 1.0) * 0.5);
+  while ((long long)(r + 1) * (r + 2) / 2 <= e) ++r;
+  while ((long long)r * (r + 1) / 2 > e) --r;
+  return r;
+}
+
+}  // namespace hdd

@@ -1,0 +1,41 @@
+// Host-side launchers of the HDD kernels (all launches are asynchronous on
+// the given stream; they return the launch status only).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace hdd {
+
+constexpr int kPanelNB = 32;  // panel width of the interface factorization
+
+// Leaves to Root
+hipError_t launch_assemble_micro(const DevLevel& L, int n_samples, int nc, const double* kappa, const double* f,
+                                 int* bad, hipStream_t st);
+hipError_t launch_extend_add(const DevLevel& F, const DevLevel& S, int n_samples, hipStream_t st);
+hipError_t launch_panel(const DevLevel& L, int k0, int kb, int n_samples, int* info, hipStream_t st);
+hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, int n_samples, bool mfma,
+                       hipStream_t st);
+
+// Root to Leaves and right-hand-side propagation
+hipError_t launch_topdown(const DevLevel& L, const int* list, int n_list, int n_samples, double* u,
+                          long long ustride, bool z_from_vec, hipStream_t st);
+hipError_t launch_forward(const DevLevel& L, const DevLevel* child, int n_samples, const double* r,
+                          long long rstride, int nc, int micro, hipStream_t st);
+
+// Full-field and readout kernels (FP64)
+hipError_t launch_fill(double* p, long long n, double v, hipStream_t st);
+hipError_t launch_residual(int nc, int n_samples, const double* kappa, const double* f, const double* u,
+                           double* r, hipStream_t st);
+hipError_t launch_axpy_maxabs(int nc, int n_samples, double* u, const double* d, unsigned long long* maxbits,
+                              hipStream_t st);
+hipError_t launch_points(int nc, int n_samples, int n_pts, const double* xy, const double* u, double* out,
+                         hipStream_t st);
+hipError_t launch_interface(int nc, int n_samples, const double* u, double* out, hipStream_t st);
+hipError_t launch_mean(int nc, int n_samples, int i0, int i1, int j0, int j1, const double* u, double* out,
+                       hipStream_t st);
+hipError_t launch_loglik(int n_samples, int n_y, const double* hu, const double* y, double sigma, int normalized,
+                         double* out, hipStream_t st);
+hipError_t launch_mfma_selftest(int dtype, double* out, hipStream_t st);
+
+}  // namespace hdd

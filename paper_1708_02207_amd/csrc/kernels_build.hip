@@ -1,0 +1,459 @@
+// HDD "Leaves to Root" kernels (Section 3.1-3.4): micro-block assembly, the
+// extend-add of two sons' Schur complements into the father's frame, and the
+// elimination of the father's interface by a partial Cholesky factorization
+// of its frame (panel factorization + triangular solve, then a symmetric
+// rank-k update on the MFMA matrix cores).
+#include <algorithm>
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace hdd {
+
+// ---------------------------------------------------------------------------
+// Micro-block assembly (Section 3.1).  One thread per (micro-block, sample).
+// The micro-block is 2 x 2 cells: 9 mesh nodes, 8 triangles.  Frame order:
+// [centre ; 8 boundary nodes counter-clockwise from the lower-left ; rhs].
+// Element matrices follow eq. coefA through the barycentric gradients of the
+// triangle (integer vertex coordinates in units of h, so |det| = 1 and
+// K_ij = kappa (g_i . g_j) / 2 exactly); the load follows the vertex rule of
+// eq. coefc: every triangle adds |t| f(x_i) / 3 to each of its vertices.
+// ---------------------------------------------------------------------------
+__constant__ int c_micro2_local[3][3] = {  // [b][a] -> frame index of local node (a, b)
+    {1, 2, 3},
+    {8, 0, 4},
+    {7, 6, 5}};
+
+template <typename T>
+__global__ void k_assemble_micro2(DevLevel L, int n_samples, int nc, const double* __restrict__ kappa,
+                                  const double* __restrict__ f, int* __restrict__ bad) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)L.n_nodes * n_samples) return;
+  const int node = int(t / n_samples);
+  const int s = int(t % n_samples);
+  const DevNode nd = L.nodes[node];
+  const double h = 1.0 / nc;
+  const double area = 0.5 * h * h;
+  double A[10][10];
+#pragma unroll
+  for (int r = 0; r < 10; ++r)
+#pragma unroll
+    for (int c = 0; c < 10; ++c) A[r][c] = 0.0;
+  const double* ks = kappa + (long long)s * nc * nc * 2;
+  bool ok = true;
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) {
+#pragma unroll
+    for (int ca = 0; ca < 2; ++ca) {
+#pragma unroll
+      for (int tri = 0; tri < 2; ++tri) {
+        // T-: (0,0),(1,0),(1,1); T+: (0,0),(1,1),(0,1) relative to the cell corner
+        const int vx[3] = {ca, ca + 1, tri == 0 ? ca + 1 : ca};
+        const int vy[3] = {cb, tri == 0 ? cb : cb + 1, cb + 1};
+        const double kap = ks[((long long)(nd.y0 + cb) * nc + (nd.x0 + ca)) * 2 + tri];
+        ok = ok && (kap > 0.0) && (kap < 1.0e300);
+        const double det = double((vx[1] - vx[0]) * (vy[2] - vy[0]) - (vx[2] - vx[0]) * (vy[1] - vy[0]));
+        const double gx[3] = {double(vy[1] - vy[2]), double(vy[2] - vy[0]), double(vy[0] - vy[1])};
+        const double gy[3] = {double(vx[2] - vx[1]), double(vx[0] - vx[2]), double(vx[1] - vx[0])};
+        const double scale = kap / (2.0 * fabs(det));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int ia = c_micro2_local[vy[a]][vx[a]];
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            const int ib = c_micro2_local[vy[b]][vx[b]];
+            A[ia][ib] += scale * (gx[a] * gx[b] + gy[a] * gy[b]);
+          }
+          const double fv = f[(long long)(nd.y0 + vy[a]) * (nc + 1) + (nd.x0 + vx[a])];
+          A[9][ia] += area * fv / 3.0;
+        }
+      }
+    }
+  }
+  if (!ok && bad) atomicCAS(bad + s, 0, 1);
+  T* F = frame_ptr<T>(L, node, s);
+  const int ld = nd.ld;
+#pragma unroll
+  for (int r = 0; r < 10; ++r)
+#pragma unroll
+    for (int c = 0; c <= r; ++c) F[r * ld + c] = T(A[r][c]);
+}
+
+// ---------------------------------------------------------------------------
+// Extend-add (eq. Psi_sum and the block system eq. block_equation4): the
+// father's frame is the sum of both sons' [Gamma;rhs] blocks embedded in the
+// father's [gamma;Gamma;rhs] ordering.  Gather form: every lower-triangle
+// element (r, c) of the father reads at most one element of each son.
+// grid.x = (node, sample) pair, grid.y strides over the lower triangle.
+// ---------------------------------------------------------------------------
+template <typename Ts, typename Tf>
+__global__ void k_extend_add(DevLevel F, DevLevel S, int n_samples) {
+  const int pair = blockIdx.x;
+  const int node = pair / n_samples;
+  const int s = pair % n_samples;
+  const DevNode nd = F.nodes[node];
+  const int n = nd.U + 1;
+  const long long total = (long long)n * (n + 1) / 2;
+  const int* mA = F.maps + nd.map_off;
+  const int* mB = mA + n;
+  const int sonA = 2 * node, sonB = 2 * node + 1;
+  const DevNode na = S.nodes[sonA], nb = S.nodes[sonB];
+  const int ga = na.U - na.bnd, gb = nb.U - nb.bnd;
+  const Ts* SA = frame_ptr<Ts>(S, sonA, s) + (long long)ga * na.ld + ga;
+  const Ts* SB = frame_ptr<Ts>(S, sonB, s) + (long long)gb * nb.ld + gb;
+  Tf* out = frame_ptr<Tf>(F, node, s);
+  for (long long e = (long long)blockIdx.y * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.y * blockDim.x) {
+    const int r = tri_row(e);
+    const int c = int(e - (long long)r * (r + 1) / 2);
+    Tf v = Tf(0);
+    const int ar = mA[r], ac = mA[c];
+    if (ar >= 0 && ac >= 0) v += Tf(ar >= ac ? SA[(long long)ar * na.ld + ac] : SA[(long long)ac * na.ld + ar]);
+    const int br = mB[r], bc = mB[c];
+    if (br >= 0 && bc >= 0) v += Tf(br >= bc ? SB[(long long)br * nb.ld + bc] : SB[(long long)bc * nb.ld + br]);
+    out[(long long)r * nd.ld + c] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Panel step of the partial Cholesky (the elimination of eq. SchurMinus1 on
+// the interface block; the paper's M = -(sum of the sons' interface blocks)
+// of eq. gamma is factored as -M = L L^T, which is positive definite).
+//  k_potrf_diag: one workgroup per (node, sample) factors the kb x kb
+//    diagonal block at (k0, k0) in LDS and writes L_kk back.  A non-positive
+//    or non-finite pivot is recorded in info[sample] and replaced by 1 so that
+//    no NaN spreads.
+//  k_trsm_rows: solves X L_kk^T = A[r, k0:k0+kb] for every row r below the
+//    block (interface rows, boundary rows and the rhs row), one row per thread.
+// ---------------------------------------------------------------------------
+template <typename T, int NB>
+__global__ void __launch_bounds__(256) k_potrf_diag(DevLevel L, int k0, int kb, int n_samples, int* info) {
+  __shared__ T D[NB][NB + 1];
+  __shared__ int bad_pivot;
+  const int pair = blockIdx.x;
+  const int node = pair / n_samples;
+  const int s = pair % n_samples;
+  const DevNode nd = L.nodes[node];
+  T* F = frame_ptr<T>(L, node, s);
+  const int ld = nd.ld;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad_pivot = 0;
+  for (int e = tid; e < kb * kb; e += blockDim.x) {
+    const int i = e / kb, j = e % kb;
+    if (j <= i) D[i][j] = F[(long long)(k0 + i) * ld + (k0 + j)];
+  }
+  __syncthreads();
+  for (int j = 0; j < kb; ++j) {
+    if (tid == 0) {
+      T d = D[j][j];
+      if (!(d > T(0)) || !(d < T(1e300))) {
+        if (!bad_pivot) bad_pivot = k0 + j + 1;
+        d = T(1);
+      }
+      D[j][j] = sqrt(d);
+    }
+    __syncthreads();
+    const T djj = D[j][j];
+    for (int i = j + 1 + tid; i < kb; i += blockDim.x) D[i][j] /= djj;
+    __syncthreads();
+    const int m = kb - j - 1;
+    for (int e = tid; e < m * m; e += blockDim.x) {
+      const int i = j + 1 + e / m, k = j + 1 + e % m;
+      if (k <= i) D[i][k] -= D[i][j] * D[k][j];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < kb * kb; e += blockDim.x) {
+    const int i = e / kb, j = e % kb;
+    if (j <= i) F[(long long)(k0 + i) * ld + (k0 + j)] = D[i][j];
+  }
+  if (tid == 0 && bad_pivot && info) atomicCAS(info + s, 0, L.node_base + node + 1);
+}
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(256) k_trsm_rows(DevLevel L, int k0, int kb, int n_samples) {
+  __shared__ T D[NB][NB + 1];
+  const int pair = blockIdx.x;
+  const int node = pair / n_samples;
+  const int s = pair % n_samples;
+  const DevNode nd = L.nodes[node];
+  const int r = k0 + kb + blockIdx.y * blockDim.x + threadIdx.x;
+  if (k0 + kb + blockIdx.y * blockDim.x > nd.U) return;  // whole block idle
+  T* F = frame_ptr<T>(L, node, s);
+  const int ld = nd.ld;
+  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
+    const int i = e / NB, j = e % NB;
+    T v = T(0);
+    if (i < kb && j < kb) {
+      if (j <= i) v = F[(long long)(k0 + i) * ld + (k0 + j)];
+    } else if (i == j) {
+      v = T(1);
+    }
+    D[i][j] = v;
+  }
+  __syncthreads();
+  if (r > nd.U) return;
+  T* row = F + (long long)r * ld + k0;
+  T x[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) x[j] = (j < kb) ? row[j] : T(0);
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    T v = x[j];
+#pragma unroll
+    for (int l = 0; l < j; ++l) v -= x[l] * D[j][l];
+    x[j] = v / D[j][j];
+  }
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+    if (j < kb) row[j] = x[j];
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric rank-k update of a lower-triangular region of the frame:
+//   C[i][j] -= sum_{k in [k0,k1)} F[i][k] F[j][k],   r0 <= i <= U,
+//   c0 <= j < c1 (c1 < 0: U+1), j <= i.
+// Used for the trailing update inside the interface (K = one panel) and for
+// the Schur update S_omega = S~ - P P^T (K = |gamma|), i.e. Psi^g of
+// Section 2.4, together with the boundary load g_omega = g~ - P z (rhs row).
+// 64 x 64 output tile per workgroup of 256 threads (4 waves, 32 x 32 each).
+// ---------------------------------------------------------------------------
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct SyrkCfg;
+template <> struct SyrkCfg<float> { static constexpr int KC = 32; };
+template <> struct SyrkCfg<double> { static constexpr int KC = 16; };
+
+struct SyrkArgs {
+  int k0, k1, r0, c0, c1;
+  int tiles_c;  // number of tile columns
+};
+
+template <typename T>
+__device__ __forceinline__ void syrk_load_chunk(T (*As)[SyrkCfg<T>::KC + 1], T (*Bs)[SyrkCfg<T>::KC + 1],
+                                                const T* F, int ld, int U, int rowA0, int rowB0, int kbeg,
+                                                int k1) {
+  constexpr int KC = SyrkCfg<T>::KC;
+  constexpr int PER = 64 * KC / 256;  // elements per thread per matrix
+  const int tid = threadIdx.x;
+  const int row = tid / (KC / PER);
+  const int col0 = (tid % (KC / PER)) * PER;
+  const int ra = rowA0 + row, rb = rowB0 + row;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int k = kbeg + col0 + q;
+    const bool kin = k < k1;
+    As[row][col0 + q] = (kin && ra <= U) ? F[(long long)ra * ld + k] : T(0);
+    Bs[row][col0 + q] = (kin && rb <= U) ? F[(long long)rb * ld + k] : T(0);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void syrk_store(T* F, int ld, int U, int i, int j, const SyrkArgs& a, int c1e, T v) {
+  if (i <= U && i >= a.r0 && j >= a.c0 && j < c1e && j <= i) F[(long long)i * ld + j] -= v;
+}
+
+__global__ void __launch_bounds__(256) k_syrk_mfma_f32(DevLevel L, SyrkArgs a, int n_samples) {
+  constexpr int KC = SyrkCfg<float>::KC;
+  __shared__ float As[64][KC + 1];
+  __shared__ float Bs[64][KC + 1];
+  const int pair = blockIdx.x;
+  const int node = pair / n_samples, s = pair % n_samples;
+  const DevNode nd = L.nodes[node];
+  const int U = nd.U;
+  const int c1e = a.c1 < 0 ? U + 1 : a.c1;
+  const int ti = blockIdx.y / a.tiles_c, tj = blockIdx.y % a.tiles_c;
+  const int i0 = a.r0 + ti * 64, j0 = a.c0 + tj * 64;
+  if (i0 > U || j0 >= c1e || i0 + 63 < j0) return;
+  float* F = frame_ptr<float>(L, node, s);
+  const int ld = nd.ld;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  floatx16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  for (int kb = a.k0; kb < a.k1; kb += KC) {
+    __syncthreads();
+    syrk_load_chunk<float>(As, Bs, F, ld, U, i0, j0, kb, a.k1);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 2) {
+      const float av = As[wr * 32 + (lane & 31)][kk + (lane >> 5)];
+      const float bv = Bs[wc * 32 + (lane & 31)][kk + (lane >> 5)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int i = i0 + wr * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+    const int j = j0 + wc * 32 + (lane & 31);
+    syrk_store<float>(F, ld, U, i, j, a, c1e, acc[v]);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, int n_samples) {
+  constexpr int KC = SyrkCfg<double>::KC;
+  __shared__ double As[64][KC + 1];
+  __shared__ double Bs[64][KC + 1];
+  const int pair = blockIdx.x;
+  const int node = pair / n_samples, s = pair % n_samples;
+  const DevNode nd = L.nodes[node];
+  const int U = nd.U;
+  const int c1e = a.c1 < 0 ? U + 1 : a.c1;
+  const int ti = blockIdx.y / a.tiles_c, tj = blockIdx.y % a.tiles_c;
+  const int i0 = a.r0 + ti * 64, j0 = a.c0 + tj * 64;
+  if (i0 > U || j0 >= c1e || i0 + 63 < j0) return;
+  double* F = frame_ptr<double>(L, node, s);
+  const int ld = nd.ld;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  doublex4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[x][y][v] = 0.0;
+  for (int kb = a.k0; kb < a.k1; kb += KC) {
+    __syncthreads();
+    syrk_load_chunk<double>(As, Bs, F, ld, U, i0, j0, kb, a.k1);
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) av[x] = As[wr * 32 + x * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y] = Bs[wc * 32 + y * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wr * 32 + x * 16 + (lane >> 4) * 4 + v;
+        const int j = j0 + wc * 32 + y * 16 + (lane & 15);
+        syrk_store<double>(F, ld, U, i, j, a, c1e, acc[x][y][v]);
+      }
+}
+
+// Plain FMA version of the same update (no matrix cores), kept as a
+// cross-check of the MFMA lane layouts.
+template <typename T>
+__global__ void __launch_bounds__(256) k_syrk_simple(DevLevel L, SyrkArgs a, int n_samples) {
+  constexpr int KC = SyrkCfg<T>::KC;
+  __shared__ T As[64][KC + 1];
+  __shared__ T Bs[64][KC + 1];
+  const int pair = blockIdx.x;
+  const int node = pair / n_samples, s = pair % n_samples;
+  const DevNode nd = L.nodes[node];
+  const int U = nd.U;
+  const int c1e = a.c1 < 0 ? U + 1 : a.c1;
+  const int ti = blockIdx.y / a.tiles_c, tj = blockIdx.y % a.tiles_c;
+  const int i0 = a.r0 + ti * 64, j0 = a.c0 + tj * 64;
+  if (i0 > U || j0 >= c1e || i0 + 63 < j0) return;
+  T* F = frame_ptr<T>(L, node, s);
+  const int ld = nd.ld;
+  const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
+  T acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = T(0);
+  for (int kb = a.k0; kb < a.k1; kb += KC) {
+    __syncthreads();
+    syrk_load_chunk<T>(As, Bs, F, ld, U, i0, j0, kb, a.k1);
+    __syncthreads();
+    for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] += As[tr + 16 * x][kk] * Bs[tc + 16 * y][kk];
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) syrk_store<T>(F, ld, U, i0 + tr + 16 * x, j0 + tc + 16 * y, a, c1e, acc[x][y]);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+static int ceil_div(long long a, long long b) { return int((a + b - 1) / b); }
+
+hipError_t launch_assemble_micro(const DevLevel& L, int n_samples, int nc, const double* kappa, const double* f,
+                                 int* bad, hipStream_t st) {
+  const long long n = (long long)L.n_nodes * n_samples;
+  dim3 grid(ceil_div(n, 128)), block(128);
+  if (L.is_double)
+    hipLaunchKernelGGL(k_assemble_micro2<double>, grid, block, 0, st, L, n_samples, nc, kappa, f, bad);
+  else
+    hipLaunchKernelGGL(k_assemble_micro2<float>, grid, block, 0, st, L, n_samples, nc, kappa, f, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_extend_add(const DevLevel& F, const DevLevel& S, int n_samples, hipStream_t st) {
+  const long long n = (long long)F.max_U + 1;
+  const long long tri = n * (n + 1) / 2;
+  dim3 grid(F.n_nodes * n_samples, std::max(1, std::min(ceil_div(tri, 256 * 8), 4096))), block(256);
+  if (F.is_double && S.is_double)
+    hipLaunchKernelGGL((k_extend_add<double, double>), grid, block, 0, st, F, S, n_samples);
+  else if (F.is_double)
+    hipLaunchKernelGGL((k_extend_add<float, double>), grid, block, 0, st, F, S, n_samples);
+  else if (!S.is_double)
+    hipLaunchKernelGGL((k_extend_add<float, float>), grid, block, 0, st, F, S, n_samples);
+  else
+    return hipErrorInvalidValue;  // a double son under a float father is never planned
+  return hipGetLastError();
+}
+
+hipError_t launch_panel(const DevLevel& L, int k0, int kb, int n_samples, int* info, hipStream_t st) {
+  dim3 g1(L.n_nodes * n_samples), block(256);
+  if (L.is_double)
+    hipLaunchKernelGGL((k_potrf_diag<double, kPanelNB>), g1, block, 0, st, L, k0, kb, n_samples, info);
+  else
+    hipLaunchKernelGGL((k_potrf_diag<float, kPanelNB>), g1, block, 0, st, L, k0, kb, n_samples, info);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int rows = L.max_U + 1 - (k0 + kb);
+  if (rows <= 0) return hipSuccess;
+  dim3 g2(L.n_nodes * n_samples, ceil_div(rows, 256));
+  if (L.is_double)
+    hipLaunchKernelGGL((k_trsm_rows<double, kPanelNB>), g2, block, 0, st, L, k0, kb, n_samples);
+  else
+    hipLaunchKernelGGL((k_trsm_rows<float, kPanelNB>), g2, block, 0, st, L, k0, kb, n_samples);
+  return hipGetLastError();
+}
+
+hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, int n_samples, bool mfma,
+                       hipStream_t st) {
+  if (k1 <= k0) return hipSuccess;
+  SyrkArgs a{k0, k1, r0, c0, c1, 0};
+  const int rows = L.max_U + 1 - r0;
+  const int cols = (c1 < 0 ? L.max_U + 1 : c1) - c0;
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const int tr = ceil_div(rows, 64);
+  a.tiles_c = ceil_div(cols, 64);
+  dim3 grid(L.n_nodes * n_samples, tr * a.tiles_c), block(256);
+  if (L.is_double) {
+    if (mfma)
+      hipLaunchKernelGGL(k_syrk_mfma_f64, grid, block, 0, st, L, a, n_samples);
+    else
+      hipLaunchKernelGGL(k_syrk_simple<double>, grid, block, 0, st, L, a, n_samples);
+  } else {
+    if (mfma)
+      hipLaunchKernelGGL(k_syrk_mfma_f32, grid, block, 0, st, L, a, n_samples);
+    else
+      hipLaunchKernelGGL(k_syrk_simple<float>, grid, block, 0, st, L, a, n_samples);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace hdd

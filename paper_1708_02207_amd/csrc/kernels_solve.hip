@@ -1,0 +1,470 @@
+// HDD "Root to Leaves" kernels (Section 3.4) and the measurement operators.
+//
+// Top-down per node (eq. SchurC1, second line, with the retained factors):
+//   u_gamma = L^-T (z - P^T u_Gamma),
+// where u_Gamma is gathered from the values its ancestors already wrote into
+// the nodal field (the data d_omega built from the father, Root-to-Leaves
+// step 3).  The forward pass propagates a new right-hand side bottom-up with
+// the same factors (z = L^-1 g~_gamma, g_omega = g~_Gamma - P z), which is
+// what the iterative refinement of the FP32 path needs.
+#include <algorithm>
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace hdd {
+
+static int ceil_div(long long a, long long b) { return int((a + b - 1) / b); }
+
+template <typename T> __device__ __forceinline__ double ldd(const T* p) { return double(*p); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Top-down solve of the nodes in `list` (indices within the level) for all
+// samples.  grid.x = list entry * n_samples + sample.  Dynamic LDS holds
+// r[gamma] and u_Gamma[max |Gamma|]; a 64 x 65 diagonal block is static.
+// ---------------------------------------------------------------------------
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS) k_topdown(DevLevel L, const int* __restrict__ list, int n_samples,
+                                                double* __restrict__ u, long long ustride, int z_from_vec) {
+  extern __shared__ double dyn[];
+  __shared__ double LD[64][65];
+  const int e = blockIdx.x;
+  const int node = list[e / n_samples];
+  const int s = e % n_samples;
+  const DevNode nd = L.nodes[node];
+  const int g = L.gam, G = nd.bnd, U = nd.U, ld = nd.ld;
+  const T* F = frame_ptr<T>(L, node, s);
+  const int* ids = L.ids + nd.ids_off;
+  double* us = u + (long long)s * ustride;
+  double* r = dyn;
+  double* ub = dyn + g;
+  const int tid = threadIdx.x;
+  const double* vz = z_from_vec ? L.vec + (long long)s * L.vec_stride + nd.ids_off : nullptr;
+  for (int i = tid; i < g; i += BS) r[i] = z_from_vec ? vz[i] : ldd(F + (long long)U * ld + i);
+  for (int j = tid; j < G; j += BS) ub[j] = us[ids[g + j]];
+  __syncthreads();
+  // r -= P^T u_Gamma, P[j][i] = F[(g + j) * ld + i]
+  for (int i = tid; i < g; i += BS) {
+    double acc = 0.0;
+    const T* col = F + (long long)g * ld + i;
+    for (int j = 0; j < G; ++j) acc += ldd(col + (long long)j * ld) * ub[j];
+    r[i] -= acc;
+  }
+  __syncthreads();
+  // back substitution L^T x = r in blocks of 64 rows from the bottom
+  for (int b1 = g; b1 > 0; b1 -= 64) {
+    const int b0 = b1 > 64 ? b1 - 64 : 0;
+    const int nb = b1 - b0;
+    for (int q = tid; q < nb * nb; q += BS) {
+      const int i = q / nb, j = q % nb;
+      LD[i][j] = (j <= i) ? ldd(F + (long long)(b0 + i) * ld + (b0 + j)) : 0.0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double v = tid < nb ? r[b0 + tid] : 0.0;
+      for (int jj = nb - 1; jj >= 0; --jj) {
+        const double xj = __shfl(v, jj) / LD[jj][jj];
+        if (tid == jj) v = xj;
+        else if (tid < jj) v -= LD[jj][tid] * xj;
+      }
+      if (tid < nb) r[b0 + tid] = v;
+    }
+    __syncthreads();
+    for (int i = tid; i < b0; i += BS) {
+      double acc = 0.0;
+      for (int k = b0; k < b1; ++k) acc += ldd(F + (long long)k * ld + i) * r[k];
+      r[i] -= acc;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < g; i += BS) us[ids[i]] = r[i];
+}
+
+// ---------------------------------------------------------------------------
+// Forward (bottom-up) propagation of a right-hand side for all nodes of a
+// level.  At the micro level the load is taken from the nodal residual r by
+// ownership (node (i,j) belongs to the micro-block that contains cell (i,j)),
+// which splits every global entry exactly once among the micro-blocks; above,
+// the load is the extend-add of the sons' condensed loads.
+// vec[node] = [z (gamma) ; g_omega (Gamma)].
+// ---------------------------------------------------------------------------
+template <typename T, int BS>
+__global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int has_child, int n_samples,
+                                                const double* __restrict__ res, long long rstride, int nc,
+                                                int micro) {
+  extern __shared__ double gt[];
+  __shared__ double LD[64][65];
+  const int e = blockIdx.x;
+  const int node = e / n_samples;
+  const int s = e % n_samples;
+  const DevNode nd = L.nodes[node];
+  const int g = L.gam, G = nd.bnd, U = nd.U, ld = nd.ld;
+  const T* F = frame_ptr<T>(L, node, s);
+  const int* ids = L.ids + nd.ids_off;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr int NW = BS / 64;
+  if (!has_child) {
+    const double* rs = res + (long long)s * rstride;
+    for (int t = tid; t < U; t += BS) {
+      const int id = ids[t];
+      const int i = id % (nc + 1), j = id / (nc + 1);
+      const bool own = i >= nd.x0 && i < nd.x0 + micro && j >= nd.y0 && j < nd.y0 + micro;
+      gt[t] = own ? rs[id] : 0.0;
+    }
+  } else {
+    const int* mA = L.maps + nd.map_off;
+    const int* mB = mA + (U + 1);
+    const DevNode na = C.nodes[2 * node], nb = C.nodes[2 * node + 1];
+    const double* va = C.vec + (long long)s * C.vec_stride + na.ids_off + (na.U - na.bnd);
+    const double* vb = C.vec + (long long)s * C.vec_stride + nb.ids_off + (nb.U - nb.bnd);
+    for (int t = tid; t < U; t += BS) {
+      double v = 0.0;
+      const int a = mA[t], b = mB[t];
+      if (a >= 0) v += va[a];
+      if (b >= 0) v += vb[b];
+      gt[t] = v;
+    }
+  }
+  __syncthreads();
+  // forward substitution L z = gt[0:g] in blocks of 64
+  for (int b0 = 0; b0 < g; b0 += 64) {
+    const int b1 = b0 + 64 < g ? b0 + 64 : g;
+    const int nb = b1 - b0;
+    for (int q = tid; q < nb * nb; q += BS) {
+      const int i = q / nb, j = q % nb;
+      LD[i][j] = (j <= i) ? ldd(F + (long long)(b0 + i) * ld + (b0 + j)) : 0.0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      double v = tid < nb ? gt[b0 + tid] : 0.0;
+      for (int jj = 0; jj < nb; ++jj) {
+        const double zj = __shfl(v, jj) / LD[jj][jj];
+        if (tid == jj) v = zj;
+        else if (tid > jj) v -= LD[tid][jj] * zj;
+      }
+      if (tid < nb) gt[b0 + tid] = v;
+    }
+    __syncthreads();
+    // rows below the block: one wave per row, lanes over the block columns
+    for (int i = b1 + wv; i < g; i += NW) {
+      double p = lane < nb ? ldd(F + (long long)i * ld + b0 + lane) * gt[b0 + lane] : 0.0;
+      p = wave_sum(p);
+      if (lane == 0) gt[i] -= p;
+    }
+    __syncthreads();
+  }
+  // g_omega[j] = gt[g + j] - sum_i P[j][i] z_i : one wave per row j
+  double* out = L.vec + (long long)s * L.vec_stride + nd.ids_off;
+  for (int j = wv; j < G; j += NW) {
+    double p = 0.0;
+    const T* row = F + (long long)(g + j) * ld;
+    for (int i = lane; i < g; i += 64) p += ldd(row + i) * gt[i];
+    p = wave_sum(p);
+    if (lane == 0) out[g + j] = gt[g + j] - p;
+  }
+  for (int i = tid; i < g; i += BS) out[i] = gt[i];
+}
+
+// ---------------------------------------------------------------------------
+// Full-field kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill(double* p, long long n, double v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Residual r = b - A u at every interior node, FP64, assembled on the fly
+// from the six triangles around the node with the element matrices of
+// eq. coefA and the vertex-rule load of eq. coefc.  Zero on the boundary.
+__global__ void k_residual(int nc, int n_samples, const double* __restrict__ kappa, const double* __restrict__ f,
+                           const double* __restrict__ u, double* __restrict__ r) {
+  const long long nn = (long long)(nc + 1) * (nc + 1);
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nn * n_samples) return;
+  const int s = int(t / nn);
+  const int id = int(t % nn);
+  const int i = id % (nc + 1), j = id / (nc + 1);
+  double* rs = r + (long long)s * nn;
+  if (i == 0 || j == 0 || i == nc || j == nc) {
+    rs[id] = 0.0;
+    return;
+  }
+  const double* us = u + (long long)s * nn;
+  const double* ks = kappa + (long long)s * nc * nc * 2;
+  const double h = 1.0 / nc;
+  const double area = 0.5 * h * h;
+  double au = 0.0, b = 0.0;
+#pragma unroll
+  for (int cc = 0; cc < 4; ++cc) {
+    const int ca = i - (cc == 1 || cc == 2 ? 1 : 0);
+    const int cb = j - (cc >= 2 ? 1 : 0);
+#pragma unroll
+    for (int tri = 0; tri < 2; ++tri) {
+      const int vx[3] = {ca, ca + 1, tri == 0 ? ca + 1 : ca};
+      const int vy[3] = {cb, tri == 0 ? cb : cb + 1, cb + 1};
+      int a = -1;
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        if (vx[q] == i && vy[q] == j) a = q;
+      if (a < 0) continue;
+      const double kap = ks[((long long)cb * nc + ca) * 2 + tri];
+      const double det = double((vx[1] - vx[0]) * (vy[2] - vy[0]) - (vx[2] - vx[0]) * (vy[1] - vy[0]));
+      const double gx[3] = {double(vy[1] - vy[2]), double(vy[2] - vy[0]), double(vy[0] - vy[1])};
+      const double gy[3] = {double(vx[2] - vx[1]), double(vx[0] - vx[2]), double(vx[1] - vx[0])};
+      const double scale = kap / (2.0 * fabs(det));
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        au += scale * (gx[a] * gx[q] + gy[a] * gy[q]) * us[(long long)vy[q] * (nc + 1) + vx[q]];
+      b += area * f[id] / 3.0;
+    }
+  }
+  rs[id] = b - au;
+}
+
+__device__ __forceinline__ void atomic_max_abs(unsigned long long* p, double v) {
+  atomicMax(p, (unsigned long long)__double_as_longlong(fabs(v)));
+}
+
+// u += d and per-sample max |d|, max |u| (as ordered bit patterns of
+// non-negative doubles, so the maximum is exact and order independent).
+__global__ void k_axpy_maxabs(int nc, int n_samples, double* __restrict__ u, const double* __restrict__ d,
+                              unsigned long long* __restrict__ maxbits) {
+  const long long nn = (long long)(nc + 1) * (nc + 1);
+  const int s = blockIdx.y;
+  double md = 0.0, mu = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += (long long)gridDim.x * blockDim.x) {
+    const double dv = d[(long long)s * nn + i];
+    const double nv = u[(long long)s * nn + i] + dv;
+    u[(long long)s * nn + i] = nv;
+    md = fmax(md, fabs(dv));
+    mu = fmax(mu, fabs(nv));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    md = fmax(md, __shfl_xor(md, o));
+    mu = fmax(mu, __shfl_xor(mu, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomic_max_abs(maxbits + 2 * s, md);
+    atomic_max_abs(maxbits + 2 * s + 1, mu);
+  }
+}
+
+// P1 interpolation at points (measurement "u in a few points", Section 1.2).
+__global__ void k_points(int nc, int n_samples, int n_pts, const double* __restrict__ xy, const double* __restrict__ u,
+                         double* __restrict__ out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n_pts * n_samples) return;
+  const int s = int(t / n_pts), p = int(t % n_pts);
+  const long long nn = (long long)(nc + 1) * (nc + 1);
+  const double* us = u + (long long)s * nn;
+  const double x = xy[2 * p] * nc, y = xy[2 * p + 1] * nc;
+  int ci = int(floor(x)), cj = int(floor(y));
+  ci = ci < 0 ? 0 : (ci > nc - 1 ? nc - 1 : ci);
+  cj = cj < 0 ? 0 : (cj > nc - 1 ? nc - 1 : cj);
+  const double fx = x - ci, fy = y - cj;
+  const double u00 = us[(long long)cj * (nc + 1) + ci];
+  const double u11 = us[(long long)(cj + 1) * (nc + 1) + ci + 1];
+  double v;
+  if (fx >= fy) v = (1.0 - fx) * u00 + (fx - fy) * us[(long long)cj * (nc + 1) + ci + 1] + fy * u11;
+  else v = (1.0 - fy) * u00 + fx * u11 + (fy - fx) * us[(long long)(cj + 1) * (nc + 1) + ci];
+  out[t] = v;
+}
+
+__global__ void k_interface(int nc, int n_samples, const double* __restrict__ u, double* __restrict__ out) {
+  const int n = nc - 1;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)n * n_samples) return;
+  const int s = int(t / n), j = int(t % n) + 1;
+  out[t] = u[(long long)s * (nc + 1) * (nc + 1) + (long long)j * (nc + 1) + nc / 2];
+}
+
+// eq. mean: sum over triangles of (|t|/3)(u1+u2+u3) / |R|, one block per
+// sample, fixed reduction order.
+__global__ void __launch_bounds__(256) k_mean(int nc, int i0, int i1, int j0, int j1, const double* __restrict__ u,
+                                              double* __restrict__ out) {
+  __shared__ double part[256];
+  const int s = blockIdx.x;
+  const double* us = u + (long long)s * (nc + 1) * (nc + 1);
+  const double h = 1.0 / nc;
+  const double at = 0.5 * h * h;
+  const int w = i1 - i0;
+  const long long ncell = (long long)w * (j1 - j0);
+  double acc = 0.0;
+  for (long long c = threadIdx.x; c < ncell; c += 256) {
+    const int i = i0 + int(c % w), j = j0 + int(c / w);
+    const double a = us[(long long)j * (nc + 1) + i], b = us[(long long)j * (nc + 1) + i + 1];
+    const double cc = us[(long long)(j + 1) * (nc + 1) + i + 1], d = us[(long long)(j + 1) * (nc + 1) + i];
+    acc += at / 3.0 * (a + b + cc) + at / 3.0 * (a + cc + d);
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[s] = part[0] / (double(ncell) * h * h);
+}
+
+// Gaussian log-likelihood (product of noise densities, Section 1.2):
+// -sum (y - Hu)^2 / (2 sigma^2), optionally - n_y log(sigma sqrt(2 pi)).
+__global__ void __launch_bounds__(256) k_loglik(int n_y, const double* __restrict__ hu, const double* __restrict__ y,
+                                                double sigma, int normalized, double* __restrict__ out) {
+  __shared__ double part[256];
+  const int s = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n_y; i += 256) {
+    const double r = y[i] - hu[(long long)s * n_y + i];
+    acc += r * r;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double v = -part[0] / (2.0 * sigma * sigma);
+    if (normalized) v -= n_y * log(sigma * sqrt(2.0 * M_PI));
+    out[s] = v;
+  }
+}
+
+// Matrix-core layout check: C = A B^T for A, B = fixed 32 x 8 / 16 x 8
+// patterns through the same builtins and fragment mapping as the Schur
+// update.  out: 32*32 (f32) or 16*16 (f64) doubles.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+__global__ void k_mfma_selftest(int dtype, double* out) {
+  const int lane = threadIdx.x;
+  if (dtype == 0) {
+    floatx16 acc;
+    for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+    for (int kk = 0; kk < 8; kk += 2) {
+      const int i = lane & 31, k = kk + (lane >> 5);
+      const float a = float((i * 7 + k * 3) % 11) - 5.f;
+      const float b = float((i * 5 + k * 2) % 13) - 6.f;
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+    }
+    for (int v = 0; v < 16; ++v) {
+      const int i = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3), j = lane & 31;
+      out[i * 32 + j] = acc[v];
+    }
+  } else {
+    doublex4 acc;
+    for (int v = 0; v < 4; ++v) acc[v] = 0.0;
+    for (int kk = 0; kk < 8; kk += 4) {
+      const int i = lane & 15, k = kk + (lane >> 4);
+      const double a = double((i * 7 + k * 3) % 11) - 5.0;
+      const double b = double((i * 5 + k * 2) % 13) - 6.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    for (int v = 0; v < 4; ++v) {
+      const int i = (lane >> 4) * 4 + v, j = lane & 15;
+      out[i * 16 + j] = acc[v];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_topdown(const DevLevel& L, const int* list, int n_list, int n_samples, double* u, long long ustride,
+                          bool z_from_vec, hipStream_t st) {
+  if (n_list <= 0) return hipSuccess;
+  const size_t lds = sizeof(double) * size_t(L.gam + L.max_U - L.gam + 1);
+  dim3 grid(n_list * n_samples);
+  if (L.gam <= 64) {
+    if (L.is_double)
+      hipLaunchKernelGGL((k_topdown<double, 64>), grid, dim3(64), lds, st, L, list, n_samples, u, ustride, z_from_vec ? 1 : 0);
+    else
+      hipLaunchKernelGGL((k_topdown<float, 64>), grid, dim3(64), lds, st, L, list, n_samples, u, ustride, z_from_vec ? 1 : 0);
+  } else {
+    if (L.is_double)
+      hipLaunchKernelGGL((k_topdown<double, 256>), grid, dim3(256), lds, st, L, list, n_samples, u, ustride, z_from_vec ? 1 : 0);
+    else
+      hipLaunchKernelGGL((k_topdown<float, 256>), grid, dim3(256), lds, st, L, list, n_samples, u, ustride, z_from_vec ? 1 : 0);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const DevLevel& L, const DevLevel* child, int n_samples, const double* r, long long rstride,
+                          int nc, int micro, hipStream_t st) {
+  const size_t lds = sizeof(double) * size_t(L.max_U + 1);
+  dim3 grid(L.n_nodes * n_samples);
+  const DevLevel C = child ? *child : L;
+  const int hc = child ? 1 : 0;
+  if (L.gam <= 64) {
+    if (L.is_double)
+      hipLaunchKernelGGL((k_forward<double, 64>), grid, dim3(64), lds, st, L, C, hc, n_samples, r, rstride, nc, micro);
+    else
+      hipLaunchKernelGGL((k_forward<float, 64>), grid, dim3(64), lds, st, L, C, hc, n_samples, r, rstride, nc, micro);
+  } else {
+    if (L.is_double)
+      hipLaunchKernelGGL((k_forward<double, 256>), grid, dim3(256), lds, st, L, C, hc, n_samples, r, rstride, nc, micro);
+    else
+      hipLaunchKernelGGL((k_forward<float, 256>), grid, dim3(256), lds, st, L, C, hc, n_samples, r, rstride, nc, micro);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* p, long long n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid(std::max(1, std::min(ceil_div(n, 256), 65536))), block(256);
+  hipLaunchKernelGGL(k_fill, grid, block, 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(int nc, int n_samples, const double* kappa, const double* f, const double* u, double* r,
+                           hipStream_t st) {
+  const long long n = (long long)(nc + 1) * (nc + 1) * n_samples;
+  hipLaunchKernelGGL(k_residual, dim3(ceil_div(n, 256)), dim3(256), 0, st, nc, n_samples, kappa, f, u, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_maxabs(int nc, int n_samples, double* u, const double* d, unsigned long long* maxbits,
+                              hipStream_t st) {
+  const long long nn = (long long)(nc + 1) * (nc + 1);
+  dim3 grid(std::max(1, std::min(ceil_div(nn, 256), 1024)), n_samples);
+  hipLaunchKernelGGL(k_axpy_maxabs, grid, dim3(256), 0, st, nc, n_samples, u, d, maxbits);
+  return hipGetLastError();
+}
+
+hipError_t launch_points(int nc, int n_samples, int n_pts, const double* xy, const double* u, double* out,
+                         hipStream_t st) {
+  const long long n = (long long)n_pts * n_samples;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_points, dim3(ceil_div(n, 128)), dim3(128), 0, st, nc, n_samples, n_pts, xy, u, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_interface(int nc, int n_samples, const double* u, double* out, hipStream_t st) {
+  const long long n = (long long)(nc - 1) * n_samples;
+  hipLaunchKernelGGL(k_interface, dim3(ceil_div(n, 256)), dim3(256), 0, st, nc, n_samples, u, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mean(int nc, int n_samples, int i0, int i1, int j0, int j1, const double* u, double* out,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_mean, dim3(n_samples), dim3(256), 0, st, nc, i0, i1, j0, j1, u, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_loglik(int n_samples, int n_y, const double* hu, const double* y, double sigma, int normalized,
+                         double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_loglik, dim3(n_samples), dim3(256), 0, st, n_y, hu, y, sigma, normalized, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mfma_selftest(int dtype, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_mfma_selftest, dim3(1), dim3(64), 0, st, dtype, out);
+  return hipGetLastError();
+}
+
+}  // namespace hdd

@@ -1,0 +1,300 @@
+"""Python binding of the HDD C ABI (include/hdd.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library libhdd.so built in-tree.  PyTorch provides device memory (the
+workspace, device inputs/outputs) and streams.  Importing this module fails
+loudly if the library is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhdd.so")
+
+HDD_OK = 0
+HDD_EINVAL = -1
+HDD_ENOMEM = -2
+HDD_ENOTSPD = -3
+HDD_ENOTCONVERGED = -4
+HDD_EDEVICE = -5
+HDD_ESTATE = -6
+HDD_FP64 = 0
+HDD_FP32_REFINE = 1
+HDD_MEM_HOST = 0
+HDD_MEM_DEVICE = 1
+HDD_FLAG_NO_MFMA = 1
+HDD_FLAG_KEEP_DIRICHLET = 2
+
+EXPORTED = [
+    "hdd_default_opts", "hdd_workspace_size", "hdd_create", "hdd_build", "hdd_query_points",
+    "hdd_query_interface", "hdd_query_mean", "hdd_loglik", "hdd_solve_full", "hdd_get_solution",
+    "hdd_error_estimate", "hdd_sync", "hdd_last_node", "hdd_destroy", "hdd_strerror",
+    "hdd_plan_summary", "hdd_plan_node", "hdd_plan_level", "hdd_debug_node_schur",
+    "hdd_timing_enable", "hdd_timing_get", "hdd_mfma_selftest",
+]
+
+
+class HddOpts(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("leaf", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("fp64_top_levels", ctypes.c_int32), ("max_refine", ctypes.c_int32), ("flags", ctypes.c_int32),
+        ("refine_tol", ctypes.c_double), ("reserved", ctypes.c_int32 * 8),
+    ]
+
+
+class HddError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HDD HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    popts = ctypes.POINTER(HddOpts)
+    sig = {
+        "hdd_default_opts": [i32, i32, popts],
+        "hdd_workspace_size": [popts, i32, ctypes.POINTER(ctypes.c_size_t)],
+        "hdd_create": [popts, i32, P, P, ctypes.c_size_t, ctypes.POINTER(P)],
+        "hdd_build": [P, i32, P, P, P, i32],
+        "hdd_query_points": [P, i32, P, P, i32],
+        "hdd_query_interface": [P, P, ctypes.POINTER(i32), i32],
+        "hdd_query_mean": [P, P, P, i32],
+        "hdd_loglik": [P, i32, P, P, dbl, i32, P, i32],
+        "hdd_solve_full": [P],
+        "hdd_get_solution": [P, i32, P, i32],
+        "hdd_error_estimate": [P, P, ctypes.POINTER(i32)],
+        "hdd_sync": [P],
+        "hdd_last_node": [P],
+        "hdd_destroy": [P],
+        "hdd_strerror": [ctypes.c_int],
+        "hdd_plan_summary": [popts, P],
+        "hdd_plan_node": [popts, i32, i32, P, P],
+        "hdd_plan_level": [popts, i32, P],
+        "hdd_debug_node_schur": [P, i32, i32, i32, P, P],
+        "hdd_timing_enable": [P, i32],
+        "hdd_timing_get": [P, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl)],
+        "hdd_mfma_selftest": [i32, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name == "hdd_strerror" else ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def strerror(code: int) -> str:
+    return _lib.hdd_strerror(int(code)).decode()
+
+
+def _check(code: int, where: str):
+    if code != HDD_OK:
+        raise HddError(code, where)
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def hdd_default_opts(n: int, precision: int = HDD_FP64, **overrides) -> HddOpts:
+    o = HddOpts()
+    _check(_lib.hdd_default_opts(int(n), int(precision), ctypes.byref(o)), "hdd_default_opts")
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def hdd_workspace_size(opts: HddOpts, max_samples: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(_lib.hdd_workspace_size(ctypes.byref(opts), int(max_samples), ctypes.byref(b)), "hdd_workspace_size")
+    return b.value
+
+
+def hdd_plan_summary(opts: HddOpts) -> dict:
+    out = np.zeros(6, dtype=np.int64)
+    _check(_lib.hdd_plan_summary(ctypes.byref(opts), _np_ptr(out)), "hdd_plan_summary")
+    keys = ["levels", "nodes", "depth_leaf", "depth_micro", "frame_elems", "flops"]
+    return dict(zip(keys, (int(v) for v in out)))
+
+
+def hdd_plan_node(opts: HddOpts, depth: int, index: int):
+    info = np.zeros(6, dtype=np.int32)
+    _check(_lib.hdd_plan_node(ctypes.byref(opts), int(depth), int(index), _np_ptr(info), None), "hdd_plan_node")
+    ids = np.zeros(int(info[4] + info[5]), dtype=np.int32)
+    _check(_lib.hdd_plan_node(ctypes.byref(opts), int(depth), int(index), _np_ptr(info), _np_ptr(ids)),
+           "hdd_plan_node")
+    return dict(x0=int(info[0]), y0=int(info[1]), w=int(info[2]), h=int(info[3]),
+                gam=int(info[4]), bnd=int(info[5]), ids=ids)
+
+
+def hdd_plan_level(opts: HddOpts, depth: int) -> dict:
+    out = np.zeros(4, dtype=np.int32)
+    _check(_lib.hdd_plan_level(ctypes.byref(opts), int(depth), _np_ptr(out)), "hdd_plan_level")
+    return dict(nodes=int(out[0]), gam=int(out[1]), max_U=int(out[2]), fp64=bool(out[3]))
+
+
+def hdd_mfma_selftest(dtype: int) -> np.ndarray:
+    n = 32 if dtype == 0 else 16
+    out = np.zeros(n * n)
+    _check(_lib.hdd_mfma_selftest(int(dtype), _np_ptr(out)), "hdd_mfma_selftest")
+    return out.reshape(n, n)
+
+
+def _is_torch_cuda(x) -> bool:
+    return hasattr(x, "is_cuda") and bool(x.is_cuda)
+
+
+def _ptr(x):
+    """(pointer, mem kind) of a numpy array or a torch CUDA tensor."""
+    if _is_torch_cuda(x):
+        assert x.is_contiguous()
+        return ctypes.c_void_p(x.data_ptr()), HDD_MEM_DEVICE
+    return _np_ptr(x), HDD_MEM_HOST
+
+
+class HDD:
+    """One handle: a planned tree with device memory for up to max_samples samples."""
+
+    def __init__(self, opts: HddOpts, max_samples: int, stream=None, workspace: str = "torch"):
+        import torch
+
+        self.opts = opts
+        self.n = opts.n
+        self.nc = opts.n + 1
+        self.max_samples = int(max_samples)
+        self.n_samples = 0
+        self._ws = None
+        wptr, wbytes = None, 0
+        if workspace == "torch":
+            wbytes = hdd_workspace_size(opts, max_samples)
+            self._ws = torch.empty(wbytes, dtype=torch.uint8, device="cuda")
+            wptr = ctypes.c_void_p(self._ws.data_ptr())
+        sptr = None
+        if stream is not None:
+            sptr = ctypes.c_void_p(stream.cuda_stream)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(_lib.hdd_create(ctypes.byref(opts), self.max_samples, sptr, wptr, ctypes.c_size_t(wbytes),
+                               ctypes.byref(h)), "hdd_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.hdd_destroy(self.h)
+            self.h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- Leaves to Root -----------------------------------------------------
+    def build(self, kappa, f):
+        if not _is_torch_cuda(kappa):
+            kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+            f = np.ascontiguousarray(f, dtype=np.float64)
+        ns = int(kappa.shape[0])
+        assert tuple(kappa.shape[1:]) == (self.nc, self.nc, 2) and tuple(f.shape) == (self.nc + 1, self.nc + 1)
+        kp, mem = _ptr(kappa)
+        fp, mem2 = _ptr(f)
+        assert mem == mem2
+        self._keep = (kappa, f)
+        _check(_lib.hdd_build(self.h, ns, kp, fp, None, mem), "hdd_build")
+        self.n_samples = ns
+
+    # -- queries ----------------------------------------------------------------
+    def query_points(self, xy, out=None) -> np.ndarray:
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        if out is None:
+            res = np.zeros((self.n_samples, len(xy)))
+            _check(_lib.hdd_query_points(self.h, len(xy), _np_ptr(xy), _np_ptr(res), HDD_MEM_HOST),
+                   "hdd_query_points")
+            return res
+        op, mem = _ptr(out)
+        _check(_lib.hdd_query_points(self.h, len(xy), _np_ptr(xy), op, mem), "hdd_query_points")
+        return out
+
+    def query_interface(self) -> np.ndarray:
+        res = np.zeros((self.n_samples, self.n))
+        ln = ctypes.c_int32(0)
+        _check(_lib.hdd_query_interface(self.h, _np_ptr(res), ctypes.byref(ln), HDD_MEM_HOST), "hdd_query_interface")
+        assert ln.value == self.n
+        return res
+
+    def query_mean(self, rect: Sequence[float]) -> np.ndarray:
+        r = np.ascontiguousarray(rect, dtype=np.float64)
+        res = np.zeros(self.n_samples)
+        _check(_lib.hdd_query_mean(self.h, _np_ptr(r), _np_ptr(res), HDD_MEM_HOST), "hdd_query_mean")
+        return res
+
+    def loglik(self, xy, y, sigma: float, normalized: bool = False, out=None):
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        if out is None:
+            y = np.ascontiguousarray(y, dtype=np.float64)
+            res = np.zeros(self.n_samples)
+            _check(_lib.hdd_loglik(self.h, len(xy), _np_ptr(xy), _np_ptr(y), float(sigma), int(normalized),
+                                   _np_ptr(res), HDD_MEM_HOST), "hdd_loglik")
+            return res
+        yp, mem = _ptr(y)
+        op, mem2 = _ptr(out)
+        assert mem == mem2 == HDD_MEM_DEVICE
+        _check(_lib.hdd_loglik(self.h, len(xy), _np_ptr(xy), yp, float(sigma), int(normalized), op, mem),
+               "hdd_loglik")
+        return out
+
+    def solve_full(self, check: bool = True) -> int:
+        code = _lib.hdd_solve_full(self.h)
+        if check:
+            _check(code, "hdd_solve_full")
+        return code
+
+    def solution(self, sample: int) -> np.ndarray:
+        u = np.zeros((self.nc + 1, self.nc + 1))
+        _check(_lib.hdd_get_solution(self.h, int(sample), _np_ptr(u), HDD_MEM_HOST), "hdd_get_solution")
+        return u
+
+    def error_estimate(self):
+        est = np.zeros(max(self.n_samples, 1))
+        sw = ctypes.c_int32(0)
+        _check(_lib.hdd_error_estimate(self.h, _np_ptr(est), ctypes.byref(sw)), "hdd_error_estimate")
+        return est[: self.n_samples], sw.value
+
+    def sync(self) -> int:
+        return _lib.hdd_sync(self.h)
+
+    def last_node(self) -> int:
+        return _lib.hdd_last_node(self.h)
+
+    def node_schur(self, sample: int, depth: int, index: int):
+        info = hdd_plan_node(self.opts, depth, index)
+        G = info["bnd"]
+        S = np.zeros((G + 1, G + 1))
+        ids = np.zeros(G, dtype=np.int32)
+        _check(_lib.hdd_debug_node_schur(self.h, int(sample), int(depth), int(index), _np_ptr(S), _np_ptr(ids)),
+               "hdd_debug_node_schur")
+        return S[:G, :G], S[G, :G], ids
+
+    # -- timing -------------------------------------------------------------------
+    def timing_enable(self, mask: int):
+        _check(_lib.hdd_timing_enable(self.h, int(mask)), "hdd_timing_enable")
+
+    def timing_get(self, kind: int):
+        ms = ctypes.c_double(0)
+        n = ctypes.c_int64(0)
+        fl = ctypes.c_double(0)
+        _check(_lib.hdd_timing_get(self.h, int(kind), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)),
+               "hdd_timing_get")
+        return ms.value, n.value, fl.value

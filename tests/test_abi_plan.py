@@ -1,0 +1,113 @@
+"""C-ABI library loads, exports every declared symbol, and its host-side tree
+plan reproduces the index sets the paper prints (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def H():
+    from paper_1708_02207_amd import hdd
+    return hdd
+
+
+def test_exports_every_declared_symbol(H):
+    hdr = open(os.path.join(ROOT, "include", "hdd.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|const char\*)\s+(hdd_\w+)\s*\(", hdr, re.M))
+    assert declared, "no declarations parsed"
+    lib = ctypes.CDLL(H.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(H.EXPORTED)
+
+
+def test_strerror(H):
+    assert H.strerror(0) == "ok"
+    assert "positive definite" in H.strerror(H.HDD_ENOTSPD)
+
+
+def test_bad_options(H):
+    o = H.hdd_default_opts(63)
+    o.n = 62  # 63 cells: not leaf * 2^p
+    with pytest.raises(H.HddError):
+        H.hdd_plan_summary(o)
+    o = H.hdd_default_opts(63)
+    o.reserved[0] = 1
+    with pytest.raises(H.HddError):
+        H.hdd_plan_summary(o)
+
+
+def test_appendix_index_sets(H):
+    """Appendix A: two sons with 384 boundary nodes each (128 x 64 cells) give a
+    father boundary of 512 nodes and a son-union frame of 639 = 512 + 127
+    (Dirichlet nodes kept, as in the paper's index sets)."""
+    o = H.hdd_default_opts(255, leaf=16, flags=H.HDD_FLAG_KEEP_DIRICHLET)
+    # depth 2 of a 256^2 grid: 128 x 128 squares; their sons are 64 x 128
+    node = H.hdd_plan_node(o, 2, 0)
+    assert (node["w"], node["h"]) == (128, 128)
+    assert node["bnd"] == 512 and node["gam"] == 127 and node["bnd"] + node["gam"] == 639
+    for s in (0, 1):
+        son = H.hdd_plan_node(o, 3, s)
+        assert son["w"] * son["h"] == 128 * 64 and son["bnd"] == 384
+
+
+def test_fig_hrhs_index_sets(H):
+    """Fig. Hrhs: a 64 x 64-cell subdomain has |I(d omega)| = 256 and |I(omega)| = 65^2 = 4225."""
+    o = H.hdd_default_opts(255, leaf=16, flags=H.HDD_FLAG_KEEP_DIRICHLET)
+    node = H.hdd_plan_node(o, 4, 5)
+    assert (node["w"], node["h"]) == (64, 64) and node["bnd"] == 256
+    assert (node["w"] + 1) * (node["h"] + 1) == 4225
+
+
+def test_tree_geometry(H):
+    """Root cut is the vertical midline; leaves tile the square exactly once;
+    interfaces exclude the cut's endpoints (eq. gamma_def); Dirichlet nodes
+    are dropped from Gamma above the micro level."""
+    o = H.hdd_default_opts(63, leaf=8)
+    nc = 64
+    s = H.hdd_plan_summary(o)
+    root = H.hdd_plan_node(o, 0, 0)
+    assert root["gam"] == 63 and root["bnd"] == 0
+    ids = root["ids"]
+    assert all(i % (nc + 1) == 32 for i in ids)
+    assert sorted(i // (nc + 1) for i in ids) == list(range(1, 64))
+    cover = np.zeros((nc, nc), dtype=int)
+    dm = s["depth_micro"]
+    lv = H.hdd_plan_level(o, dm)
+    for k in range(lv["nodes"]):
+        nd = H.hdd_plan_node(o, dm, k)
+        cover[nd["y0"]:nd["y0"] + nd["h"], nd["x0"]:nd["x0"] + nd["w"]] += 1
+    assert (cover == 1).all()
+    # every interior mesh node is on exactly one interface (I(Omega) = union of I(gamma))
+    seen = np.zeros((nc + 1) ** 2, dtype=int)
+    for d in range(s["levels"]):
+        for k in range(H.hdd_plan_level(o, d)["nodes"]):
+            nd = H.hdd_plan_node(o, d, k)
+            seen[nd["ids"][: nd["gam"]]] += 1
+            if d < dm:
+                for i in nd["ids"][nd["gam"]:]:
+                    x, y = i % (nc + 1), i // (nc + 1)
+                    assert 0 < x < nc and 0 < y < nc
+    inner = np.array([(i % (nc + 1)) not in (0, nc) and (i // (nc + 1)) not in (0, nc) for i in range((nc + 1) ** 2)])
+    assert (seen[inner] == 1).all() and (seen[~inner] == 0).all()
+
+
+def test_plan_flops_match_dense_count(H):
+    """Build flops sum_nodes g^3/3 + g^2 G + g G^2 at 1023^2 (about 2.1e10)."""
+    o = H.hdd_default_opts(1023, leaf=32)
+    s = H.hdd_plan_summary(o)
+    assert 2.0e10 < s["flops"] < 2.2e10
+    assert s["levels"] == 19 and s["depth_leaf"] == 10
+
+
+def test_precision_levels(H):
+    o = H.hdd_default_opts(255, H.HDD_FP32_REFINE, leaf=16)
+    assert H.hdd_plan_level(o, 0)["fp64"] and H.hdd_plan_level(o, 1)["fp64"]
+    assert not H.hdd_plan_level(o, 2)["fp64"]
+    o = H.hdd_default_opts(255, H.HDD_FP64, leaf=16)
+    assert all(H.hdd_plan_level(o, d)["fp64"] for d in range(H.hdd_plan_summary(o)["levels"]))
