@@ -1,0 +1,218 @@
+"""Benchmark: likelihood evaluations per second at 1023^2 interior nodes.
+
+One step = the whole hot path over one batch of parameter samples resident in
+HBM: Leaves to Root for every sample (leaf assembly, extend-add, interface
+factorization, matrix-core Schur updates), Root to Leaves, float64
+refinement of the float32 factors against the assembled operator, and the
+measurements of the 1023^2 workload (64 point values, the root midline
+interface, the mean over [0.25,0.5]^2) with the Gaussian log-likelihood of
+the 64 observations.  value = batch * steps / timed seconds.
+
+Prints one JSON line (see the keys below).  --gpus N > 1 exits: this build
+runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "hbm_gbs": 8000.0}
+KIND = {"syrk32": 0, "factor": 1, "extend": 2, "assemble": 3, "topdown": 4, "forward": 5, "residual": 6,
+        "syrk64": 7}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--config", default="c2_1023")
+    ap.add_argument("--precision", default="fp32_refine", choices=["fp32_refine", "fp64"])
+    ap.add_argument("--no-comparator", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile-steps", type=int, default=1, help="extra steps with per-kernel event timing")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, seconds: float):
+    """Oracle banded-Cholesky factorization of the first columns of the same
+    1023^2 operator on one host core, scaled to the full factorization
+    (every column away from the end costs the same), as evals/s."""
+    from oracle import oracle as O
+
+    n = w.n
+    ncols_total = n * n
+    probe = 2000
+    t = O.factor_prefix_seconds(n, w.kappa[0], probe)
+    ncols = int(min(ncols_total, max(probe, probe * seconds / max(t, 1e-6))))
+    t = O.factor_prefix_seconds(n, w.kappa[0], ncols)
+    t_full = t * ncols_total / ncols
+    return {"value": 1.0 / t_full, "unit": "likelihood evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"banded Cholesky of the first {ncols} of {ncols_total} columns of the 1023^2 operator "
+                      f"(sample 0), {t:.1f} s, scaled by column count to {t_full:.0f} s per solve; "
+                      f"triangular solves and refinement (O(N^3)) not included",
+            "host": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+
+    from paper_1708_02207_amd import hdd as H
+    from workload import make_workload
+
+    w = make_workload(a.config, n_samples=a.batch)
+    gold_path = os.path.join(ROOT, "tests", "golden", f"{a.config}.json")
+    gold = json.load(open(gold_path)) if os.path.exists(gold_path) else None
+    y = np.array(gold["y"]) if gold else np.zeros(len(w.points))
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    kd = torch.from_numpy(w.kappa).to(dev)
+    fd = torch.from_numpy(w.f).to(dev)
+    yd = torch.from_numpy(y).to(dev)
+    prec = H.HDD_FP32_REFINE if a.precision == "fp32_refine" else H.HDD_FP64
+    opts = H.hdd_default_opts(w.n, prec, leaf=w.leaf)
+    t = H.HDD(opts, a.batch, stream=stream)
+    B = a.batch
+    ll = torch.empty(B, dtype=torch.float64, device=dev)
+    pts = torch.empty(B * len(w.points), dtype=torch.float64, device=dev)
+    iface = torch.empty(B * w.n, dtype=torch.float64, device=dev)
+    mean = torch.empty(B, dtype=torch.float64, device=dev)
+    rect = np.array(w.mean_rect if w.mean_rect else (0.25, 0.5, 0.25, 0.5))
+
+    def step():
+        t.build(kd, fd)
+        t.loglik(w.points, yd, w.sigma_y, False, out=ll)
+        t.query_points(w.points, out=pts)
+        H._check(H._lib.hdd_query_interface(t.h, H.ctypes.c_void_p(iface.data_ptr()), None, H.HDD_MEM_DEVICE),
+                 "hdd_query_interface")
+        H._check(H._lib.hdd_query_mean(t.h, H._np_ptr(rect), H.ctypes.c_void_p(mean.data_ptr()), H.HDD_MEM_DEVICE),
+                 "hdd_query_mean")
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        s0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - s0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    code = t.sync()
+    est, sweeps = t.error_estimate()
+
+    # accuracy of this run's outputs against the stored oracle values
+    err = None
+    if gold:
+        P = pts.cpu().numpy().reshape(B, -1)
+        I = iface.cpu().numpy().reshape(B, -1)
+        M = mean.cpu().numpy()
+        errs = []
+        for g in gold["samples"]:
+            s = g["sample"]
+            if s >= B:
+                continue
+            r = lambda v, ref: float(np.abs(np.asarray(v) - np.asarray(ref)).max() / np.abs(np.asarray(ref)).max())
+            errs.append(r(P[s], g["points"]))
+            if "interface" in g:
+                errs.append(r(I[s], g["interface"]))
+            if "mean" in g:
+                errs.append(r([M[s]], [g["mean"]]))
+        err = max(errs) if errs else None
+
+    # per-kernel event timing over extra profiled steps
+    t.timing_enable(0xFF)
+    for _ in range(a.profile_steps):
+        step()
+    kern = {}
+    for name, k in KIND.items():
+        ms, n, fl = t.timing_get(k)
+        kern[name] = {"ms": ms / max(a.profile_steps, 1), "launches": n // max(a.profile_steps, 1),
+                      "tflops": (fl / (ms * 1e-3) / 1e12) if ms > 0 and fl > 0 else None}
+    t.timing_enable(0)
+    syrk_key = "syrk32" if prec == H.HDD_FP32_REFINE else "syrk64"
+    peak = PEAK["fp32_mfma"] if syrk_key == "syrk32" else PEAK["fp64_mfma"]
+    ach = kern[syrk_key]["tflops"] or 0.0
+    roofline = {"bound": "mfma", "kernel": f"Schur update (rank-k, {syrk_key})", "achieved": ach, "peak": peak,
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                "per_launch_avg_ms": kern[syrk_key]["ms"] / max(kern[syrk_key]["launches"], 1)}
+    t.close()
+    del t
+
+    comparator = None
+    if not a.no_comparator:
+        o64 = H.hdd_default_opts(w.n, H.HDD_FP64, leaf=w.leaf)
+        c = H.HDD(o64, 1, stream=stream)
+        k1 = kd[:1].contiguous()
+        ll1 = torch.empty(1, dtype=torch.float64, device=dev)
+
+        def cstep():
+            c.build(k1, fd)
+            c.solve_full()
+            c.loglik(w.points, yd, w.sigma_y, False, out=ll1)
+
+        cstep()
+        torch.cuda.synchronize()
+        cs = max(2, a.steps // 2)
+        c0 = time.perf_counter()
+        for _ in range(cs):
+            cstep()
+        torch.cuda.synchronize()
+        cdt = time.perf_counter() - c0
+        comparator = {"name": "FP64 HDD full solve, one sample at a time (build + full Root to Leaves)",
+                      "value": cs / cdt, "unit": "likelihood evals/s", "ms_per_eval": 1e3 * cdt / cs}
+        c.close()
+
+    cpu = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
+
+    lat_ms = sorted(1e3 * x for x in lat)
+    out = {
+        "metric": "likelihood evals/s at 1023^2 (HDD vs full GPU solve) at 1e-8 rel err; p50/p99 ms",
+        "value": B * a.steps / dt,
+        "unit": "likelihood evals/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * dt / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == H.HDD_FP32_REFINE else "f64",
+        "data": "synthetic (seeded log-normal kappa, no dataset)",
+        "config": {"workload": f"{a.config}: {w.n}^2 interior nodes, {w.leaf}x{w.leaf} leaves, log-normal kappa "
+                               f"(var {w.spec['var']}, corr {w.spec['corr']}, {w.spec['n_z']} modes), f=1; "
+                               f"64 points + midline + mean[0.25,0.5]^2 + loglik",
+                   "global_batch": B, "precision": a.precision, "parallelism": "1 GPU"},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                       "note": "per step (a batch of evaluations)"},
+        "accuracy": {"max_rel_err_vs_oracle": err, "refine_sweeps": sweeps,
+                     "max_refine_estimate": float(np.max(est)) if len(est) else None, "status": H.strerror(code)},
+        "roofline": roofline,
+        "kernels_ms_per_step": {k: v["ms"] for k, v in kern.items()},
+        "kernels_tflops": {k: v["tflops"] for k, v in kern.items() if v["tflops"]},
+        "comparator": comparator,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -192,10 +192,16 @@ int hdd_plan_level(const hdd_opts* opts, int32_t depth, int32_t out[4]);
  * node's boundary (Section 2.4).  Synchronizes. */
 int hdd_debug_node_schur(hdd_handle h, int32_t sample, int32_t depth, int32_t index, double* S, int32_t* ids);
 
+/* Raw frame of one built node (lower triangle, [gamma ; Gamma ; rhs] order,
+ * upper triangle returned as zeros): out host float64 [(U+1)^2] with room for
+ * the largest frame of the level; *U_out = U.  Synchronizes. */
+int hdd_debug_frame(hdd_handle h, int32_t sample, int32_t depth, int32_t index, double* out, int32_t* U_out);
+
 /* Timing of kernel classes with HIP events around every launch of the class
- * on the handle's stream.  kind: 0 Schur update (rank-k, matrix cores),
- * 1 interface factorization (diagonal + row solves), 2 extend-add,
- * 3 leaf assembly, 4 top-down, 5 forward pass, 6 residual.
+ * on the handle's stream.  kind: 0 Schur update (rank-k, matrix cores) on
+ * float32 levels, 1 interface factorization (diagonal + row solves),
+ * 2 extend-add, 3 leaf assembly, 4 top-down, 5 forward pass, 6 residual,
+ * 7 Schur update on float64 levels.
  * hdd_timing_enable(h, mask): bit k enables kind k (0 disables and clears).
  * hdd_timing_get: total milliseconds, number of launches and summed
  * algorithmic flops of the timed launches (Schur update: 2 K per lower-

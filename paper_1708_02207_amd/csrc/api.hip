@@ -18,8 +18,10 @@ using hdd::Plan;
 
 namespace {
 
-constexpr int kKinds = 7;
-enum Kind { K_SYRK = 0, K_FACTOR = 1, K_EXTEND = 2, K_ASSEMBLE = 3, K_TOPDOWN = 4, K_FORWARD = 5, K_RESIDUAL = 6 };
+constexpr int kKinds = 8;
+enum Kind {
+  K_SYRK = 0, K_FACTOR = 1, K_EXTEND = 2, K_ASSEMBLE = 3, K_TOPDOWN = 4, K_FORWARD = 5, K_RESIDUAL = 6, K_SYRK64 = 7
+};
 
 int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
@@ -489,19 +491,20 @@ int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double
   auto eliminate = [&](int d) -> int {
     const DevLevel& L = h->lev[d];
     const int g = L.gam;
+    const int syrk_kind = L.is_double ? K_SYRK64 : K_SYRK;
     for (int k0 = 0; k0 < g; k0 += hdd::kPanelNB) {
       const int kb = std::min(hdd::kPanelNB, g - k0);
       HDD_TRY(timed(h, K_FACTOR, 0.0, [&] { return hdd::launch_panel(L, k0, kb, n_samples, h->info, h->st); }));
       if (k0 + kb < g) {
-        const double fl = (h->timing_mask & 1) ? syrk_flops(h, d, k0, k0 + kb, k0 + kb, k0 + kb, g) : 0.0;
-        HDD_TRY(timed(h, K_SYRK, fl, [&] {
+        const double fl = h->timing_mask ? syrk_flops(h, d, k0, k0 + kb, k0 + kb, k0 + kb, g) : 0.0;
+        HDD_TRY(timed(h, syrk_kind, fl, [&] {
           return hdd::launch_syrk(L, k0, k0 + kb, k0 + kb, k0 + kb, g, n_samples, mfma, h->st);
         }));
       }
     }
     if (L.max_U > g) {  // Schur update of Gamma (and the boundary load row)
-      const double fl = (h->timing_mask & 1) ? syrk_flops(h, d, 0, g, g, g, -1) : 0.0;
-      HDD_TRY(timed(h, K_SYRK, fl, [&] { return hdd::launch_syrk(L, 0, g, g, g, -1, n_samples, mfma, h->st); }));
+      const double fl = h->timing_mask ? syrk_flops(h, d, 0, g, g, g, -1) : 0.0;
+      HDD_TRY(timed(h, syrk_kind, fl, [&] { return hdd::launch_syrk(L, 0, g, g, g, -1, n_samples, mfma, h->st); }));
     }
     return HDD_OK;
   };
@@ -705,7 +708,7 @@ int hdd_debug_node_schur(hdd_handle h, int32_t sample, int32_t depth, int32_t in
   if (sample < 0 || sample >= h->n_samples || depth < 0 || depth >= int(h->lev.size())) return HDD_EINVAL;
   const auto& pl = h->plan.levels[depth];
   if (index < 0 || index >= int(pl.nodes.size())) return HDD_EINVAL;
-  HDD_TRY(check_deferred(h));
+  HIP_TRY(hipStreamSynchronize(h->st));  // read back even after a failed pivot (diagnostics)
   const auto& nd = pl.nodes[index];
   const int U = nd.U(), g = int(nd.gam.size()), G = int(nd.bnd.size()), ld = nd.ld;
   const bool dbl = h->lev[depth].is_double != 0;
@@ -723,6 +726,32 @@ int hdd_debug_node_schur(hdd_handle h, int32_t sample, int32_t depth, int32_t in
     for (int b = 0; b <= G; ++b) S[size_t(a) * (G + 1) + b] = at(g + a, g + b);
   std::copy(nd.bnd.begin(), nd.bnd.end(), ids);
   (void)U;
+  return HDD_OK;
+}
+
+int hdd_debug_frame(hdd_handle h, int32_t sample, int32_t depth, int32_t index, double* out, int32_t* U_out) {
+  if (!h || !out || !U_out) return HDD_EINVAL;
+  if (!h->built) return HDD_ESTATE;
+  if (sample < 0 || sample >= h->n_samples || depth < 0 || depth >= int(h->lev.size())) return HDD_EINVAL;
+  const auto& pl = h->plan.levels[depth];
+  if (index < 0 || index >= int(pl.nodes.size())) return HDD_EINVAL;
+  HIP_TRY(hipStreamSynchronize(h->st));
+  const auto& nd = pl.nodes[index];
+  const int n = nd.U() + 1, ld = nd.ld;
+  const bool dbl = h->lev[depth].is_double != 0;
+  const size_t esz = dbl ? 8 : 4;
+  std::vector<char> buf(size_t(n) * ld * esz);
+  const char* src = static_cast<const char*>(h->lev[depth].frames) +
+                    (size_t(sample) * h->lev[depth].stride + size_t(nd.frame_off)) * esz;
+  HIP_TRY(hipMemcpy(buf.data(), src, buf.size(), hipMemcpyDeviceToHost));
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < n; ++c) {
+      const size_t k = size_t(r) * ld + c;
+      out[size_t(r) * n + c] = (c <= r) ? (dbl ? reinterpret_cast<const double*>(buf.data())[k]
+                                                  : double(reinterpret_cast<const float*>(buf.data())[k]))
+                                          : 0.0;
+    }
+  *U_out = n - 1;
   return HDD_OK;
 }
 

@@ -124,7 +124,8 @@ __global__ void k_extend_add(DevLevel F, DevLevel S, int n_samples) {
 //    or non-finite pivot is recorded in info[sample] and replaced by 1 so that
 //    no NaN spreads.
 //  k_trsm_rows: solves X L_kk^T = A[r, k0:k0+kb] for every row r below the
-//    block (interface rows, boundary rows and the rhs row), one row per thread.
+//    block (interface rows, boundary rows and the rhs row), one row per
+//    thread, with rows and L_kk staged in LDS.
 // ---------------------------------------------------------------------------
 template <typename T, int NB>
 __global__ void __launch_bounds__(256) k_potrf_diag(DevLevel L, int k0, int kb, int n_samples, int* info) {
@@ -171,42 +172,42 @@ __global__ void __launch_bounds__(256) k_potrf_diag(DevLevel L, int k0, int kb, 
 }
 
 template <typename T, int NB>
-__global__ void __launch_bounds__(256) k_trsm_rows(DevLevel L, int k0, int kb, int n_samples) {
+__global__ void __launch_bounds__(64) k_trsm_rows(DevLevel L, int k0, int kb, int n_samples) {
+  // 64 rows per workgroup (one wave); rows and the factored diagonal block
+  // are staged in LDS, every access stays inside [k0, k0 + kb).
   __shared__ T D[NB][NB + 1];
+  __shared__ T X[64][NB + 1];
   const int pair = blockIdx.x;
   const int node = pair / n_samples;
   const int s = pair % n_samples;
   const DevNode nd = L.nodes[node];
-  const int r = k0 + kb + blockIdx.y * blockDim.x + threadIdx.x;
-  if (k0 + kb + blockIdx.y * blockDim.x > nd.U) return;  // whole block idle
+  const int r0 = k0 + kb + blockIdx.y * 64;
+  if (r0 > nd.U) return;  // whole block idle (uniform)
+  const int nrows = min(64, nd.U + 1 - r0);
   T* F = frame_ptr<T>(L, node, s);
   const int ld = nd.ld;
-  for (int e = threadIdx.x; e < NB * NB; e += blockDim.x) {
-    const int i = e / NB, j = e % NB;
-    T v = T(0);
-    if (i < kb && j < kb) {
-      if (j <= i) v = F[(long long)(k0 + i) * ld + (k0 + j)];
-    } else if (i == j) {
-      v = T(1);
-    }
-    D[i][j] = v;
+  const int t = threadIdx.x;
+  for (int e = t; e < kb * kb; e += 64) {
+    const int i = e / kb, j = e % kb;
+    D[i][j] = (j <= i) ? F[(long long)(k0 + i) * ld + (k0 + j)] : T(0);
+  }
+  for (int e = t; e < nrows * kb; e += 64) {
+    const int i = e / kb, j = e % kb;
+    X[i][j] = F[(long long)(r0 + i) * ld + (k0 + j)];
   }
   __syncthreads();
-  if (r > nd.U) return;
-  T* row = F + (long long)r * ld + k0;
-  T x[NB];
-#pragma unroll
-  for (int j = 0; j < NB; ++j) x[j] = (j < kb) ? row[j] : T(0);
-#pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    T v = x[j];
-#pragma unroll
-    for (int l = 0; l < j; ++l) v -= x[l] * D[j][l];
-    x[j] = v / D[j][j];
+  if (t < nrows) {
+    for (int j = 0; j < kb; ++j) {
+      T v = X[t][j];
+      for (int l = 0; l < j; ++l) v -= X[t][l] * D[j][l];
+      X[t][j] = v / D[j][j];
+    }
   }
-#pragma unroll
-  for (int j = 0; j < NB; ++j)
-    if (j < kb) row[j] = x[j];
+  __syncthreads();
+  for (int e = t; e < nrows * kb; e += 64) {
+    const int i = e / kb, j = e % kb;
+    F[(long long)(r0 + i) * ld + (k0 + j)] = X[i][j];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -338,7 +339,7 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = i0 + wr * 32 + x * 16 + (lane >> 4) * 4 + v;
+        const int i = i0 + wr * 32 + x * 16 + 4 * v + (lane >> 4);  // f64 16x16x4: row 4v + lane/16
         const int j = j0 + wc * 32 + y * 16 + (lane & 15);
         syrk_store<double>(F, ld, U, i, j, a, c1e, acc[x][y][v]);
       }
@@ -424,11 +425,11 @@ hipError_t launch_panel(const DevLevel& L, int k0, int kb, int n_samples, int* i
   if (e != hipSuccess) return e;
   const int rows = L.max_U + 1 - (k0 + kb);
   if (rows <= 0) return hipSuccess;
-  dim3 g2(L.n_nodes * n_samples, ceil_div(rows, 256));
+  dim3 g2(L.n_nodes * n_samples, ceil_div(rows, 64));
   if (L.is_double)
-    hipLaunchKernelGGL((k_trsm_rows<double, kPanelNB>), g2, block, 0, st, L, k0, kb, n_samples);
+    hipLaunchKernelGGL((k_trsm_rows<double, kPanelNB>), g2, dim3(64), 0, st, L, k0, kb, n_samples);
   else
-    hipLaunchKernelGGL((k_trsm_rows<float, kPanelNB>), g2, block, 0, st, L, k0, kb, n_samples);
+    hipLaunchKernelGGL((k_trsm_rows<float, kPanelNB>), g2, dim3(64), 0, st, L, k0, kb, n_samples);
   return hipGetLastError();
 }
 

@@ -366,7 +366,7 @@ __global__ void k_mfma_selftest(int dtype, double* out) {
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
     for (int v = 0; v < 4; ++v) {
-      const int i = (lane >> 4) * 4 + v, j = lane & 15;
+      const int i = 4 * v + (lane >> 4), j = lane & 15;
       out[i * 16 + j] = acc[v];
     }
   }

@@ -35,7 +35,7 @@ EXPORTED = [
     "hdd_query_interface", "hdd_query_mean", "hdd_loglik", "hdd_solve_full", "hdd_get_solution",
     "hdd_error_estimate", "hdd_sync", "hdd_last_node", "hdd_destroy", "hdd_strerror",
     "hdd_plan_summary", "hdd_plan_node", "hdd_plan_level", "hdd_debug_node_schur",
-    "hdd_timing_enable", "hdd_timing_get", "hdd_mfma_selftest",
+    "hdd_timing_enable", "hdd_timing_get", "hdd_mfma_selftest", "hdd_debug_frame",
 ]
 
 
@@ -48,9 +48,11 @@ class HddOpts(ctypes.Structure):
 
 
 class HddError(RuntimeError):
-    def __init__(self, code: int, where: str):
+    def __init__(self, code: int, where: str, node: int = 0):
         self.code = code
-        super().__init__(f"{where}: {strerror(code)} ({code})")
+        self.node = node
+        extra = f", first failing node {node - 1}" if node else ""
+        super().__init__(f"{where}: {strerror(code)} ({code}{extra})")
 
 
 def _load() -> ctypes.CDLL:
@@ -83,6 +85,7 @@ def _load() -> ctypes.CDLL:
         "hdd_timing_enable": [P, i32],
         "hdd_timing_get": [P, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl)],
         "hdd_mfma_selftest": [i32, P],
+        "hdd_debug_frame": [P, i32, i32, i32, P, ctypes.POINTER(i32)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -286,6 +289,15 @@ class HDD:
         _check(_lib.hdd_debug_node_schur(self.h, int(sample), int(depth), int(index), _np_ptr(S), _np_ptr(ids)),
                "hdd_debug_node_schur")
         return S[:G, :G], S[G, :G], ids
+
+    def frame(self, sample: int, depth: int, index: int) -> np.ndarray:
+        mx = hdd_plan_level(self.opts, depth)["max_U"] + 1
+        out = np.zeros(mx * mx)
+        U = ctypes.c_int32(0)
+        _check(_lib.hdd_debug_frame(self.h, int(sample), int(depth), int(index), _np_ptr(out), ctypes.byref(U)),
+               "hdd_debug_frame")
+        n = U.value + 1
+        return out[: n * n].reshape(n, n)
 
     # -- timing -------------------------------------------------------------------
     def timing_enable(self, mask: int):
