@@ -132,7 +132,8 @@ struct hdd_tree {
   int timing_mask = 0;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  struct Rec { int kind; hipEvent_t a, b; double flops; };
+  struct Rec { int kind, level; hipEvent_t a, b; double flops; };
+  int cur_level = -1;  // level of the launches being recorded
   std::vector<Rec> recs;
 };
 
@@ -165,7 +166,7 @@ int timed(hdd_tree* h, int kind, double flops, F&& launch) {
   HIP_TRY(hipEventRecord(a, h->st));
   HIP_TRY(launch());
   HIP_TRY(hipEventRecord(b, h->st));
-  h->recs.push_back({kind, a, b, flops});
+  h->recs.push_back({kind, h->cur_level, a, b, flops});
   return HDD_OK;
 }
 
@@ -206,6 +207,7 @@ int check_deferred(hdd_tree* h) {
 
 int run_topdown_level(hdd_tree* h, int d, const int* list_dev, int n_list, double* target, bool from_vec) {
   const DevLevel& L = h->lev[d];
+  h->cur_level = d;
   return timed(h, K_TOPDOWN, 0.0, [&] {
     return hdd::launch_topdown(L, list_dev, n_list, h->n_samples, target, h->nn, from_vec, h->st);
   });
@@ -232,9 +234,11 @@ int ensure_full(hdd_tree* h) {
   std::vector<unsigned long long> mb(2 * ns);
   bool converged = false;
   for (int it = 0; it < max_it; ++it) {
+    h->cur_level = -1;
     HDD_TRY(timed(h, K_RESIDUAL, 0.0, [&] { return hdd::launch_residual(nc, ns, h->kappa, h->f, h->u, h->r, h->st); }));
     for (int d = D; d >= 0; --d) {
       const DevLevel* child = d < D ? &h->lev[d + 1] : nullptr;
+      h->cur_level = d;
       HDD_TRY(timed(h, K_FORWARD, 0.0, [&] {
         return hdd::launch_forward(h->lev[d], child, ns, h->r, h->nn, nc, h->plan.opt.micro, h->st);
       }));
@@ -489,6 +493,7 @@ int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double
   const int D = int(h->lev.size()) - 1;
   const bool mfma = !(h->opt.flags & HDD_FLAG_NO_MFMA);
   auto eliminate = [&](int d) -> int {
+    h->cur_level = d;
     const DevLevel& L = h->lev[d];
     const int g = L.gam;
     const int syrk_kind = L.is_double ? K_SYRK64 : K_SYRK;
@@ -508,11 +513,13 @@ int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double
     }
     return HDD_OK;
   };
+  h->cur_level = D;
   HDD_TRY(timed(h, K_ASSEMBLE, 0.0, [&] {
     return hdd::launch_assemble_micro(h->lev[D], n_samples, nc, h->kappa, h->f, h->bad, h->st);
   }));
   HDD_TRY(eliminate(D));
   for (int d = D - 1; d >= 0; --d) {
+    h->cur_level = d;
     HDD_TRY(timed(h, K_EXTEND, 0.0, [&] { return hdd::launch_extend_add(h->lev[d], h->lev[d + 1], n_samples, h->st); }));
     HDD_TRY(eliminate(d));
   }
@@ -765,12 +772,16 @@ int hdd_timing_enable(hdd_handle h, int32_t mask) {
 }
 
 int hdd_timing_get(hdd_handle h, int32_t kind, double* ms, int64_t* launches, double* flops) {
+  return hdd_timing_get_level(h, kind, -1, ms, launches, flops);
+}
+
+int hdd_timing_get_level(hdd_handle h, int32_t kind, int32_t level, double* ms, int64_t* launches, double* flops) {
   if (!h || kind < 0 || kind >= kKinds) return HDD_EINVAL;
   HIP_TRY(hipStreamSynchronize(h->st));
   double tot = 0, fl = 0;
   int64_t n = 0;
   for (const auto& r : h->recs) {
-    if (r.kind != kind) continue;
+    if (r.kind != kind || (level >= 0 && r.level != level)) continue;
     float t = 0;
     HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
     tot += t;

@@ -36,6 +36,7 @@ EXPORTED = [
     "hdd_error_estimate", "hdd_sync", "hdd_last_node", "hdd_destroy", "hdd_strerror",
     "hdd_plan_summary", "hdd_plan_node", "hdd_plan_level", "hdd_debug_node_schur",
     "hdd_timing_enable", "hdd_timing_get", "hdd_mfma_selftest", "hdd_debug_frame",
+    "hdd_timing_get_level",
 ]
 
 
@@ -86,6 +87,7 @@ def _load() -> ctypes.CDLL:
         "hdd_timing_get": [P, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl)],
         "hdd_mfma_selftest": [i32, P],
         "hdd_debug_frame": [P, i32, i32, i32, P, ctypes.POINTER(i32)],
+        "hdd_timing_get_level": [P, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -303,10 +305,10 @@ class HDD:
     def timing_enable(self, mask: int):
         _check(_lib.hdd_timing_enable(self.h, int(mask)), "hdd_timing_enable")
 
-    def timing_get(self, kind: int):
+    def timing_get(self, kind: int, level: int = -1):
         ms = ctypes.c_double(0)
         n = ctypes.c_int64(0)
         fl = ctypes.c_double(0)
-        _check(_lib.hdd_timing_get(self.h, int(kind), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)),
-               "hdd_timing_get")
+        _check(_lib.hdd_timing_get_level(self.h, int(kind), int(level), ctypes.byref(ms), ctypes.byref(n),
+                                         ctypes.byref(fl)), "hdd_timing_get_level")
         return ms.value, n.value, fl.value
