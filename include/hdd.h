@@ -169,13 +169,15 @@ const char* hdd_strerror(int code);
 
 /* ---- inspection (tests, benchmark) ---- */
 
-/* Plan summary: out[0] levels, out[1] nodes, out[2] depth of the leaves,
- * out[3] depth of the micro-blocks, out[4] per-sample frame elements,
- * out[5] algorithmic build flops per sample (sum over nodes of
- * g^3/3 + g^2 G + g G^2).  Host-only; needs no GPU. */
+/* Plan summary: out[0] global tree levels (root .. blocks), out[1] global
+ * nodes, out[2] depth of the leaves, out[3] depth of the blocks (s x s cells,
+ * s = min(16, leaf), whose interior is eliminated in LDS), out[4] per-sample
+ * stored factor elements, out[5] algorithmic build flops per sample (sum over
+ * every node of the tree down to 2 x 2-cell micro-blocks, outer Dirichlet
+ * nodes dropped, of g^3/3 + g^2 G + g G^2).  Host-only; needs no GPU. */
 int hdd_plan_summary(const hdd_opts* opts, int64_t out[6]);
 
-/* One node of the plan: info[0] x0, info[1] y0, info[2] w, info[3] h (cells),
+/* One node of the global plan (depth <= depth of the blocks): info[0] x0, info[1] y0, info[2] w, info[3] h (cells),
  * info[4] |gamma|, info[5] |Gamma|; ids (may be NULL, else room for
  * |gamma|+|Gamma|) receives global node ids (j*(Nc+1)+i) of [gamma ; Gamma].
  * Host-only; needs no GPU. */

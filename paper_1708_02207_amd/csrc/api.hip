@@ -44,7 +44,7 @@ bool make_plan(const hdd_opts& o, Plan& p) {
   hdd::PlanOptions po;
   po.n = o.n;
   po.leaf = o.leaf;
-  po.micro = 2;
+  po.block = 16;
   po.keep_dirichlet = (o.flags & HDD_FLAG_KEEP_DIRICHLET) != 0;
   return hdd::build_plan(po, p);
 }
@@ -53,6 +53,7 @@ bool make_plan(const hdd_opts& o, Plan& p) {
 struct Layout {
   std::vector<int64_t> frames, nodes, maps, ids, vec;
   int64_t kappa, f, u, d, r, info, bad, maxbits, qout, qxy, qy, lists, iota;
+  int64_t cst, bvec, tmaps, tlids, tmicro, origin;
   int64_t max_q;
   int64_t total;
 };
@@ -96,6 +97,15 @@ Layout make_layout(const Plan& p, const hdd_opts& o, int ms) {
   L.qy = take(L.max_q * 8);
   L.lists = take(total_nodes * 4);
   L.iota = take(max_nodes * 4);
+  const auto& T = p.sub;
+  const int64_t nb = int64_t(p.levels.back().nodes.size());
+  const int64_t besz = level_double(o, int(p.levels.size()) - 1) ? 8 : 4;
+  L.cst = take(int64_t(ms) * nb * T.cst_size * besz);
+  L.bvec = refine ? take(int64_t(ms) * nb * T.vec_size * 8) : -1;
+  L.tmaps = take(int64_t(T.maps.size()) * 4);
+  L.tlids = take(int64_t(T.lids.size()) * 4);
+  L.tmicro = take(int64_t(T.micro_xy.size()) * 4);
+  L.origin = take(nb * 8);
   L.total = off;
   return L;
 }
@@ -113,6 +123,7 @@ struct hdd_tree {
   char* ws = nullptr;
   bool own_ws = false;
   std::vector<DevLevel> lev;
+  hdd::DevBlocks blk{};
   std::vector<int64_t> lev_list_off;  // offset (in ints) of each level's node list
   long long nn = 0;
   double *kappa = nullptr, *f = nullptr, *u = nullptr, *d = nullptr, *r = nullptr;
@@ -213,10 +224,18 @@ int run_topdown_level(hdd_tree* h, int d, const int* list_dev, int n_list, doubl
   });
 }
 
+int run_block_topdown(hdd_tree* h, const int* list_dev, int n_list, double* target, bool from_vec) {
+  h->cur_level = int(h->lev.size()) - 1;
+  return timed(h, K_TOPDOWN, 0.0, [&] {
+    return hdd::launch_block_topdown(h->blk, list_dev, n_list, h->n_samples, h->plan.nc, target, h->nn, from_vec,
+                                     h->st);
+  });
+}
+
 int full_topdown(hdd_tree* h, double* target, bool from_vec) {
-  for (size_t d = 0; d < h->lev.size(); ++d)
-    HDD_TRY(run_topdown_level(h, int(d), h->iota, h->lev[d].n_nodes, target, from_vec));
-  return HDD_OK;
+  const int DB = int(h->lev.size()) - 1;
+  for (int d = 0; d < DB; ++d) HDD_TRY(run_topdown_level(h, d, h->iota, h->lev[d].n_nodes, target, from_vec));
+  return run_block_topdown(h, h->iota, h->blk.nb, target, from_vec);
 }
 
 int ensure_full(hdd_tree* h) {
@@ -236,12 +255,11 @@ int ensure_full(hdd_tree* h) {
   for (int it = 0; it < max_it; ++it) {
     h->cur_level = -1;
     HDD_TRY(timed(h, K_RESIDUAL, 0.0, [&] { return hdd::launch_residual(nc, ns, h->kappa, h->f, h->u, h->r, h->st); }));
-    for (int d = D; d >= 0; --d) {
-      const DevLevel* child = d < D ? &h->lev[d + 1] : nullptr;
+    h->cur_level = D;
+    HDD_TRY(timed(h, K_FORWARD, 0.0, [&] { return hdd::launch_block_forward(h->blk, ns, nc, h->r, h->nn, h->st); }));
+    for (int d = D - 1; d >= 0; --d) {
       h->cur_level = d;
-      HDD_TRY(timed(h, K_FORWARD, 0.0, [&] {
-        return hdd::launch_forward(h->lev[d], child, ns, h->r, h->nn, nc, h->plan.opt.micro, h->st);
-      }));
+      HDD_TRY(timed(h, K_FORWARD, 0.0, [&] { return hdd::launch_forward(h->lev[d], h->lev[d + 1], ns, h->st); }));
     }
     HIP_TRY(hdd::launch_fill(h->d, (long long)ns * h->nn, 0.0, h->st));
     HDD_TRY(full_topdown(h, h->d, true));
@@ -284,22 +302,26 @@ int partial_topdown(hdd_tree* h, const std::vector<std::vector<uint8_t>>& need) 
   HIP_TRY(hipMemcpyAsync(h->lists, h->pinned_lists, sizeof(int) * (h->lev_list_off.back() + h->lev.back().n_nodes),
                          hipMemcpyHostToDevice, h->st));
   HIP_TRY(hipEventRecord(h->lists_done, h->st));
+  const size_t DB = h->lev.size() - 1;
   for (size_t d = 0; d < h->lev.size(); ++d) {
     if (!counts[d]) continue;
-    HDD_TRY(run_topdown_level(h, int(d), h->lists + h->lev_list_off[d], counts[d], h->u, false));
+    if (d < DB)
+      HDD_TRY(run_topdown_level(h, int(d), h->lists + h->lev_list_off[d], counts[d], h->u, false));
+    else
+      HDD_TRY(run_block_topdown(h, h->lists + h->lev_list_off[d], counts[d], h->u, false));
     for (size_t k = 0; k < need[d].size(); ++k)
       if (need[d][k]) h->solved[d][k] = 1;
   }
   return HDD_OK;
 }
 
-// Mark the path root -> micro-block holding cell (ci, cj).
+// Mark the path root -> block holding cell (ci, cj).
 void mark_cell_path(const hdd_tree* h, int ci, int cj, std::vector<std::vector<uint8_t>>& need) {
   int k = 0;
   for (size_t d = 0; d < h->plan.levels.size(); ++d) {
     const auto& nd = h->plan.levels[d].nodes[k];
     need[d][k] = 1;
-    if (nd.micro) break;
+    if (nd.block) break;
     int s;
     if (nd.vertical) s = ci >= nd.x0 + nd.w / 2 ? 1 : 0;
     else s = cj >= nd.y0 + nd.h / 2 ? 1 : 0;
@@ -431,6 +453,46 @@ int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* works
     list_off += lv.n_nodes;
     h->solved[d].assign(lv.n_nodes, 0);
   }
+  {
+    const auto& T = h->plan.sub;
+    if (int(T.lv.size()) > hdd::kMaxSubLevels) return fail(HDD_EINVAL);
+    hdd::DevBlocks& B = h->blk;
+    B.nlev = int(T.lv.size());
+    for (int k = 0; k < B.nlev; ++k) {
+      const auto& sl = T.lv[k];
+      B.lv[k] = hdd::DevSubLevel{sl.n, sl.gam, sl.bnd, sl.U, sl.fsz, sl.cst_off, sl.vec_off, sl.map_off, sl.lid_off};
+    }
+    B.s = T.s;
+    B.nb = h->lev.back().n_nodes;
+    B.cst_size = T.cst_size;
+    B.vec_size = T.vec_size;
+    B.max_buf = T.max_buf;
+    B.max_gam_nodes = T.max_gam_nodes;
+    B.max_bnd_nodes = T.max_bnd_nodes;
+    B.maps = reinterpret_cast<const int*>(h->ws + L.tmaps);
+    B.lids = reinterpret_cast<const int*>(h->ws + L.tlids);
+    B.micro_xy = reinterpret_cast<const int*>(h->ws + L.tmicro);
+    B.origin = reinterpret_cast<const int*>(h->ws + L.origin);
+    B.cst = h->ws + L.cst;
+    B.cst_stride = (long long)B.nb * T.cst_size;
+    B.vec = L.bvec >= 0 ? reinterpret_cast<double*>(h->ws + L.bvec) : nullptr;
+    B.vec_stride = (long long)B.nb * T.vec_size;
+    B.top = h->lev.back();
+    std::vector<int> org;
+    for (const auto& nd : h->plan.levels.back().nodes) {
+      org.push_back(nd.x0);
+      org.push_back(nd.y0);
+    }
+    if ((!T.maps.empty() &&
+         hipMemcpy(h->ws + L.tmaps, T.maps.data(), T.maps.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(h->ws + L.tlids, T.lids.data(), T.lids.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->ws + L.tmicro, T.micro_xy.data(), T.micro_xy.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->ws + L.origin, org.data(), org.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(HDD_EDEVICE);
+    const bool bdbl = B.top.is_double != 0;
+    const size_t lds = hdd::block_build_lds(B, bdbl);
+    if (lds > 160 * 1024) return fail(HDD_EINVAL);
+  }
   h->nn = (long long)(h->plan.nc + 1) * (h->plan.nc + 1);
   h->kappa = reinterpret_cast<double*>(h->ws + L.kappa);
   h->f = reinterpret_cast<double*>(h->ws + L.f);
@@ -515,9 +577,8 @@ int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double
   };
   h->cur_level = D;
   HDD_TRY(timed(h, K_ASSEMBLE, 0.0, [&] {
-    return hdd::launch_assemble_micro(h->lev[D], n_samples, nc, h->kappa, h->f, h->bad, h->st);
+    return hdd::launch_block_build(h->blk, n_samples, nc, h->kappa, h->f, h->bad, h->info, h->st);
   }));
-  HDD_TRY(eliminate(D));
   for (int d = D - 1; d >= 0; --d) {
     h->cur_level = d;
     HDD_TRY(timed(h, K_EXTEND, 0.0, [&] { return hdd::launch_extend_add(h->lev[d], h->lev[d + 1], n_samples, h->st); }));
@@ -573,7 +634,7 @@ int hdd_query_mean(hdd_handle h, const double rect[4], double* out, int32_t mem)
   }
   if (b[1] <= b[0] || b[3] <= b[2]) return HDD_EINVAL;
   auto need = empty_need(h);
-  const int m = h->plan.opt.micro;
+  const int m = h->plan.sub.s;
   for (int cj = b[2]; cj < b[3]; ++cj)
     for (int ci = b[0]; ci < b[1]; ++ci)
       if (ci % m == 0 || ci == b[0])
@@ -659,21 +720,17 @@ int hdd_plan_summary(const hdd_opts* o, int64_t out[6]) {
   Plan p;
   if (!make_plan(*o, p)) return HDD_EINVAL;
   int64_t nodes = 0, elems = 0;
-  double flops = 0;
   for (const auto& L : p.levels) {
     nodes += int64_t(L.nodes.size());
     elems += L.frame_elems;
-    for (const auto& nd : L.nodes) {
-      const double g = double(nd.gam.size()), G = double(nd.bnd.size());
-      flops += g * g * g / 3.0 + g * g * G + g * G * G;
-    }
   }
+  elems += int64_t(p.levels.back().nodes.size()) * p.sub.cst_size;
   out[0] = int64_t(p.levels.size());
   out[1] = nodes;
   out[2] = p.depth_leaf;
-  out[3] = p.depth_micro;
+  out[3] = p.depth_block;
   out[4] = elems;
-  out[5] = int64_t(flops);
+  out[5] = int64_t(hdd::algorithmic_flops(o->n));
   return HDD_OK;
 }
 

@@ -44,6 +44,35 @@ struct DevLevel {
   int node_base;         // global index of this level's first node (for error reports)
 };
 
+// One level of the shared s x s block sub-tree (level 0 = the block).
+struct DevSubLevel {
+  int n, gam, bnd, U, fsz, cst_off, vec_off, map_off, lid_off;
+};
+constexpr int kMaxSubLevels = 12;
+
+// Everything the block kernels need: the sub-tree template, the compact
+// stores and the global level of the blocks.
+struct DevBlocks {
+  DevSubLevel lv[kMaxSubLevels];
+  int nlev;           // sub-tree levels
+  int s;              // cells per block side
+  int nb;             // blocks per sample
+  int cst_size;       // compact elements per block
+  int vec_size;       // z values per block
+  int max_buf;        // LDS frame elements per buffer
+  int max_gam_nodes;  // max n * gam over levels
+  int max_bnd_nodes;  // max n * U over levels
+  const int* maps;
+  const int* lids;
+  const int* micro_xy;
+  const int* origin;  // [nb][2] lower-left cell of every block
+  void* cst;          // [sample][block][cst_size], float or double
+  long long cst_stride;
+  double* vec;        // [sample][block][vec_size]
+  long long vec_stride;
+  DevLevel top;       // the global level made of the blocks
+};
+
 template <typename T> __device__ __forceinline__ T* frame_ptr(const DevLevel& L, int node, int s) {
   return reinterpret_cast<T*>(L.frames) + (long long)s * L.stride + L.nodes[node].frame_off;
 }

@@ -10,18 +10,24 @@ namespace hdd {
 constexpr int kPanelNB = 32;  // panel width of the interface factorization
 
 // Leaves to Root
-hipError_t launch_assemble_micro(const DevLevel& L, int n_samples, int nc, const double* kappa, const double* f,
-                                 int* bad, hipStream_t st);
 hipError_t launch_extend_add(const DevLevel& F, const DevLevel& S, int n_samples, hipStream_t st);
 hipError_t launch_panel(const DevLevel& L, int k0, int kb, int n_samples, int* info, hipStream_t st);
 hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, int n_samples, bool mfma,
                        hipStream_t st);
 
+// Blocks (in-LDS nested dissection of the leaf interior)
+size_t block_build_lds(const DevBlocks& B, bool dbl);
+hipError_t launch_block_build(const DevBlocks& B, int n_samples, int nc, const double* kappa, const double* f,
+                              int* bad, int* info, hipStream_t st);
+hipError_t launch_block_topdown(const DevBlocks& B, const int* list, int n_list, int n_samples, int nc, double* u,
+                                long long ustride, bool from_vec, hipStream_t st);
+hipError_t launch_block_forward(const DevBlocks& B, int n_samples, int nc, const double* r, long long rstride,
+                                hipStream_t st);
+
 // Root to Leaves and right-hand-side propagation
 hipError_t launch_topdown(const DevLevel& L, const int* list, int n_list, int n_samples, double* u,
                           long long ustride, bool z_from_vec, hipStream_t st);
-hipError_t launch_forward(const DevLevel& L, const DevLevel* child, int n_samples, const double* r,
-                          long long rstride, int nc, int micro, hipStream_t st);
+hipError_t launch_forward(const DevLevel& L, const DevLevel& child, int n_samples, hipStream_t st);
 
 // Full-field and readout kernels (FP64)
 hipError_t launch_fill(double* p, long long n, double v, hipStream_t st);

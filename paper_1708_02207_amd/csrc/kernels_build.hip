@@ -1,4 +1,4 @@
-// HDD "Leaves to Root" kernels (Section 3.1-3.4): micro-block assembly, the
+// HDD "Leaves to Root" kernels above the block level (Sections 3.2-3.4): the
 // extend-add of two sons' Schur complements into the father's frame, and the
 // elimination of the father's interface by a partial Cholesky factorization
 // of its frame (panel factorization + triangular solve, then a symmetric
@@ -9,75 +9,6 @@
 #include "kernels.hpp"
 
 namespace hdd {
-
-// ---------------------------------------------------------------------------
-// Micro-block assembly (Section 3.1).  One thread per (micro-block, sample).
-// The micro-block is 2 x 2 cells: 9 mesh nodes, 8 triangles.  Frame order:
-// [centre ; 8 boundary nodes counter-clockwise from the lower-left ; rhs].
-// Element matrices follow eq. coefA through the barycentric gradients of the
-// triangle (integer vertex coordinates in units of h, so |det| = 1 and
-// K_ij = kappa (g_i . g_j) / 2 exactly); the load follows the vertex rule of
-// eq. coefc: every triangle adds |t| f(x_i) / 3 to each of its vertices.
-// ---------------------------------------------------------------------------
-__constant__ int c_micro2_local[3][3] = {  // [b][a] -> frame index of local node (a, b)
-    {1, 2, 3},
-    {8, 0, 4},
-    {7, 6, 5}};
-
-template <typename T>
-__global__ void k_assemble_micro2(DevLevel L, int n_samples, int nc, const double* __restrict__ kappa,
-                                  const double* __restrict__ f, int* __restrict__ bad) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)L.n_nodes * n_samples) return;
-  const int node = int(t / n_samples);
-  const int s = int(t % n_samples);
-  const DevNode nd = L.nodes[node];
-  const double h = 1.0 / nc;
-  const double area = 0.5 * h * h;
-  double A[10][10];
-#pragma unroll
-  for (int r = 0; r < 10; ++r)
-#pragma unroll
-    for (int c = 0; c < 10; ++c) A[r][c] = 0.0;
-  const double* ks = kappa + (long long)s * nc * nc * 2;
-  bool ok = true;
-#pragma unroll
-  for (int cb = 0; cb < 2; ++cb) {
-#pragma unroll
-    for (int ca = 0; ca < 2; ++ca) {
-#pragma unroll
-      for (int tri = 0; tri < 2; ++tri) {
-        // T-: (0,0),(1,0),(1,1); T+: (0,0),(1,1),(0,1) relative to the cell corner
-        const int vx[3] = {ca, ca + 1, tri == 0 ? ca + 1 : ca};
-        const int vy[3] = {cb, tri == 0 ? cb : cb + 1, cb + 1};
-        const double kap = ks[((long long)(nd.y0 + cb) * nc + (nd.x0 + ca)) * 2 + tri];
-        ok = ok && (kap > 0.0) && (kap < 1.0e300);
-        const double det = double((vx[1] - vx[0]) * (vy[2] - vy[0]) - (vx[2] - vx[0]) * (vy[1] - vy[0]));
-        const double gx[3] = {double(vy[1] - vy[2]), double(vy[2] - vy[0]), double(vy[0] - vy[1])};
-        const double gy[3] = {double(vx[2] - vx[1]), double(vx[0] - vx[2]), double(vx[1] - vx[0])};
-        const double scale = kap / (2.0 * fabs(det));
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const int ia = c_micro2_local[vy[a]][vx[a]];
-#pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            const int ib = c_micro2_local[vy[b]][vx[b]];
-            A[ia][ib] += scale * (gx[a] * gx[b] + gy[a] * gy[b]);
-          }
-          const double fv = f[(long long)(nd.y0 + vy[a]) * (nc + 1) + (nd.x0 + vx[a])];
-          A[9][ia] += area * fv / 3.0;
-        }
-      }
-    }
-  }
-  if (!ok && bad) atomicCAS(bad + s, 0, 1);
-  T* F = frame_ptr<T>(L, node, s);
-  const int ld = nd.ld;
-#pragma unroll
-  for (int r = 0; r < 10; ++r)
-#pragma unroll
-    for (int c = 0; c <= r; ++c) F[r * ld + c] = T(A[r][c]);
-}
 
 // ---------------------------------------------------------------------------
 // Extend-add (eq. Psi_sum and the block system eq. block_equation4): the
@@ -388,17 +319,6 @@ __global__ void __launch_bounds__(256) k_syrk_simple(DevLevel L, SyrkArgs a, int
 // Host launchers
 // ---------------------------------------------------------------------------
 static int ceil_div(long long a, long long b) { return int((a + b - 1) / b); }
-
-hipError_t launch_assemble_micro(const DevLevel& L, int n_samples, int nc, const double* kappa, const double* f,
-                                 int* bad, hipStream_t st) {
-  const long long n = (long long)L.n_nodes * n_samples;
-  dim3 grid(ceil_div(n, 128)), block(128);
-  if (L.is_double)
-    hipLaunchKernelGGL(k_assemble_micro2<double>, grid, block, 0, st, L, n_samples, nc, kappa, f, bad);
-  else
-    hipLaunchKernelGGL(k_assemble_micro2<float>, grid, block, 0, st, L, n_samples, nc, kappa, f, bad);
-  return hipGetLastError();
-}
 
 hipError_t launch_extend_add(const DevLevel& F, const DevLevel& S, int n_samples, hipStream_t st) {
   const long long n = (long long)F.max_U + 1;

@@ -88,16 +88,11 @@ __global__ void __launch_bounds__(BS) k_topdown(DevLevel L, const int* __restric
 
 // ---------------------------------------------------------------------------
 // Forward (bottom-up) propagation of a right-hand side for all nodes of a
-// level.  At the micro level the load is taken from the nodal residual r by
-// ownership (node (i,j) belongs to the micro-block that contains cell (i,j)),
-// which splits every global entry exactly once among the micro-blocks; above,
-// the load is the extend-add of the sons' condensed loads.
-// vec[node] = [z (gamma) ; g_omega (Gamma)].
+// level above the blocks: the load is the extend-add of the sons' condensed
+// loads.  vec[node] = [z (gamma) ; g_omega (Gamma)].
 // ---------------------------------------------------------------------------
 template <typename T, int BS>
-__global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int has_child, int n_samples,
-                                                const double* __restrict__ res, long long rstride, int nc,
-                                                int micro) {
+__global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int n_samples) {
   extern __shared__ double gt[];
   __shared__ double LD[64][65];
   const int e = blockIdx.x;
@@ -106,18 +101,9 @@ __global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int has_
   const DevNode nd = L.nodes[node];
   const int g = L.gam, G = nd.bnd, U = nd.U, ld = nd.ld;
   const T* F = frame_ptr<T>(L, node, s);
-  const int* ids = L.ids + nd.ids_off;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   constexpr int NW = BS / 64;
-  if (!has_child) {
-    const double* rs = res + (long long)s * rstride;
-    for (int t = tid; t < U; t += BS) {
-      const int id = ids[t];
-      const int i = id % (nc + 1), j = id / (nc + 1);
-      const bool own = i >= nd.x0 && i < nd.x0 + micro && j >= nd.y0 && j < nd.y0 + micro;
-      gt[t] = own ? rs[id] : 0.0;
-    }
-  } else {
+  {
     const int* mA = L.maps + nd.map_off;
     const int* mB = mA + (U + 1);
     const DevNode na = C.nodes[2 * node], nb = C.nodes[2 * node + 1];
@@ -394,22 +380,19 @@ hipError_t launch_topdown(const DevLevel& L, const int* list, int n_list, int n_
   return hipGetLastError();
 }
 
-hipError_t launch_forward(const DevLevel& L, const DevLevel* child, int n_samples, const double* r, long long rstride,
-                          int nc, int micro, hipStream_t st) {
+hipError_t launch_forward(const DevLevel& L, const DevLevel& child, int n_samples, hipStream_t st) {
   const size_t lds = sizeof(double) * size_t(L.max_U + 1);
   dim3 grid(L.n_nodes * n_samples);
-  const DevLevel C = child ? *child : L;
-  const int hc = child ? 1 : 0;
   if (L.gam <= 64) {
     if (L.is_double)
-      hipLaunchKernelGGL((k_forward<double, 64>), grid, dim3(64), lds, st, L, C, hc, n_samples, r, rstride, nc, micro);
+      hipLaunchKernelGGL((k_forward<double, 64>), grid, dim3(64), lds, st, L, child, n_samples);
     else
-      hipLaunchKernelGGL((k_forward<float, 64>), grid, dim3(64), lds, st, L, C, hc, n_samples, r, rstride, nc, micro);
+      hipLaunchKernelGGL((k_forward<float, 64>), grid, dim3(64), lds, st, L, child, n_samples);
   } else {
     if (L.is_double)
-      hipLaunchKernelGGL((k_forward<double, 256>), grid, dim3(256), lds, st, L, C, hc, n_samples, r, rstride, nc, micro);
+      hipLaunchKernelGGL((k_forward<double, 256>), grid, dim3(256), lds, st, L, child, n_samples);
     else
-      hipLaunchKernelGGL((k_forward<float, 256>), grid, dim3(256), lds, st, L, C, hc, n_samples, r, rstride, nc, micro);
+      hipLaunchKernelGGL((k_forward<float, 256>), grid, dim3(256), lds, st, L, child, n_samples);
   }
   return hipGetLastError();
 }

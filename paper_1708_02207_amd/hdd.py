@@ -129,7 +129,7 @@ def hdd_workspace_size(opts: HddOpts, max_samples: int) -> int:
 def hdd_plan_summary(opts: HddOpts) -> dict:
     out = np.zeros(6, dtype=np.int64)
     _check(_lib.hdd_plan_summary(ctypes.byref(opts), _np_ptr(out)), "hdd_plan_summary")
-    keys = ["levels", "nodes", "depth_leaf", "depth_micro", "frame_elems", "flops"]
+    keys = ["levels", "nodes", "depth_leaf", "depth_block", "frame_elems", "flops"]
     return dict(zip(keys, (int(v) for v in out)))
 
 

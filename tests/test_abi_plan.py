@@ -65,9 +65,10 @@ def test_fig_hrhs_index_sets(H):
 
 
 def test_tree_geometry(H):
-    """Root cut is the vertical midline; leaves tile the square exactly once;
+    """Root cut is the vertical midline; blocks tile the square exactly once;
     interfaces exclude the cut's endpoints (eq. gamma_def); Dirichlet nodes
-    are dropped from Gamma above the micro level."""
+    are dropped from Gamma above the block level; every interior mesh node
+    lies on exactly one interface (I(Omega) is the union of the I(gamma))."""
     o = H.hdd_default_opts(63, leaf=8)
     nc = 64
     s = H.hdd_plan_summary(o)
@@ -77,22 +78,24 @@ def test_tree_geometry(H):
     assert all(i % (nc + 1) == 32 for i in ids)
     assert sorted(i // (nc + 1) for i in ids) == list(range(1, 64))
     cover = np.zeros((nc, nc), dtype=int)
-    dm = s["depth_micro"]
-    lv = H.hdd_plan_level(o, dm)
-    for k in range(lv["nodes"]):
-        nd = H.hdd_plan_node(o, dm, k)
-        cover[nd["y0"]:nd["y0"] + nd["h"], nd["x0"]:nd["x0"] + nd["w"]] += 1
-    assert (cover == 1).all()
-    # every interior mesh node is on exactly one interface (I(Omega) = union of I(gamma))
+    db = s["depth_block"]
+    assert db == s["levels"] - 1
     seen = np.zeros((nc + 1) ** 2, dtype=int)
-    for d in range(s["levels"]):
+    for k in range(H.hdd_plan_level(o, db)["nodes"]):
+        nd = H.hdd_plan_node(o, db, k)
+        cover[nd["y0"]:nd["y0"] + nd["h"], nd["x0"]:nd["x0"] + nd["w"]] += 1
+        assert nd["bnd"] == 2 * (nd["w"] + nd["h"])  # Dirichlet nodes kept inside blocks
+        for b in range(nd["y0"] + 1, nd["y0"] + nd["h"]):
+            for a in range(nd["x0"] + 1, nd["x0"] + nd["w"]):
+                seen[b * (nc + 1) + a] += 1
+    assert (cover == 1).all()
+    for d in range(db):
         for k in range(H.hdd_plan_level(o, d)["nodes"]):
             nd = H.hdd_plan_node(o, d, k)
             seen[nd["ids"][: nd["gam"]]] += 1
-            if d < dm:
-                for i in nd["ids"][nd["gam"]:]:
-                    x, y = i % (nc + 1), i // (nc + 1)
-                    assert 0 < x < nc and 0 < y < nc
+            for i in nd["ids"][nd["gam"]:]:
+                x, y = i % (nc + 1), i // (nc + 1)
+                assert 0 < x < nc and 0 < y < nc
     inner = np.array([(i % (nc + 1)) not in (0, nc) and (i // (nc + 1)) not in (0, nc) for i in range((nc + 1) ** 2)])
     assert (seen[inner] == 1).all() and (seen[~inner] == 0).all()
 
@@ -102,7 +105,7 @@ def test_plan_flops_match_dense_count(H):
     o = H.hdd_default_opts(1023, leaf=32)
     s = H.hdd_plan_summary(o)
     assert 2.0e10 < s["flops"] < 2.2e10
-    assert s["levels"] == 19 and s["depth_leaf"] == 10
+    assert s["levels"] == 13 and s["depth_leaf"] == 10 and s["depth_block"] == 12
 
 
 def test_precision_levels(H):
