@@ -73,7 +73,7 @@ typedef struct hdd_opts {
   int32_t fp64_top_levels; /* HDD_FP32_REFINE: levels (from the root) kept in float64; default 2 */
   int32_t max_refine;      /* refinement sweeps allowed (HDD_FP32_REFINE default 6; HDD_FP64 default 0) */
   int32_t flags;           /* HDD_FLAG_* */
-  double refine_tol;       /* stop when max|du| <= refine_tol * max|u| (default 1e-12) */
+  double refine_tol;       /* stop when max|du| <= refine_tol * max|u| (default 1e-10) */
   int32_t reserved[8];     /* must be zero */
 } hdd_opts;
 

@@ -362,7 +362,7 @@ int hdd_default_opts(int32_t n, int32_t precision, hdd_opts* o) {
   o->precision = precision;
   o->fp64_top_levels = 2;
   o->max_refine = precision == HDD_FP32_REFINE ? 6 : 0;
-  o->refine_tol = 1e-12;
+  o->refine_tol = 1e-10;
   return validate_opts(o);
 }
 
@@ -490,8 +490,13 @@ int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* works
         hipMemcpy(h->ws + L.origin, org.data(), org.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
       return fail(HDD_EDEVICE);
     const bool bdbl = B.top.is_double != 0;
-    const size_t lds = hdd::block_build_lds(B, bdbl);
-    if (lds > 160 * 1024) return fail(HDD_EINVAL);
+    if (!hdd::block_shape_ok(B)) return fail(HDD_EINVAL);
+    // the build stages the block's coefficients and load in its second frame buffer
+    if (size_t(2 * B.s * B.s + (B.s + 1) * (B.s + 1)) * 8 > size_t(B.max_buf) * (bdbl ? 8 : 4))
+      return fail(HDD_EINVAL);
+    if (hdd::block_build_lds(B, bdbl) > 160 * 1024 || hdd::block_topdown_lds(B, bdbl) > 160 * 1024 ||
+        hdd::block_forward_lds(B, bdbl) > 160 * 1024)
+      return fail(HDD_EINVAL);
   }
   h->nn = (long long)(h->plan.nc + 1) * (h->plan.nc + 1);
   h->kappa = reinterpret_cast<double*>(h->ws + L.kappa);

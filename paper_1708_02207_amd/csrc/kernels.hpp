@@ -17,6 +17,9 @@ hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1
 
 // Blocks (in-LDS nested dissection of the leaf interior)
 size_t block_build_lds(const DevBlocks& B, bool dbl);
+size_t block_topdown_lds(const DevBlocks& B, bool dbl);
+size_t block_forward_lds(const DevBlocks& B, bool dbl);
+bool block_shape_ok(const DevBlocks& B);  // template sizes match the compiled shapes
 hipError_t launch_block_build(const DevBlocks& B, int n_samples, int nc, const double* kappa, const double* f,
                               int* bad, int* info, hipStream_t st);
 hipError_t launch_block_topdown(const DevBlocks& B, const int* list, int n_list, int n_samples, int nc, double* u,

@@ -2,8 +2,10 @@
 //
 // One workgroup handles one (block, sample).  All blocks share one local
 // sub-tree (outer Dirichlet nodes are kept inside a block), so every level
-// has n nodes of identical shape and the whole level is processed in
-// parallel with workgroup-wide barriers.
+// has n nodes of identical shape, known at compile time from the block size
+// S, and the whole level is processed in parallel with workgroup barriers.
+// Level k (0 = the block) has 2^k nodes of (S >> ((k+1)/2)) x (S >> (k/2))
+// cells; the last level holds the 2 x 2-cell micro-blocks.
 //
 //  k_block_build     Section 3.1 (leaf assembly, eq. coefA, eq. coefc) and
 //                    Sections 2.4 / 3.3 (Schur elimination and merge of
@@ -28,189 +30,309 @@ __constant__ int c_mb_local[3][3] = {  // micro-block local node (a, b) -> frame
     {8, 0, 4},
     {7, 6, 5}};
 
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+template <int S, int K> struct Lv {
+  static constexpr int Lm = 2 * ilog2c(S / 2);  // micro level
+  static constexpr int w = S >> ((K + 1) / 2);
+  static constexpr int h = S >> (K / 2);
+  static constexpr int n = 1 << K;
+  static constexpr int gam = (K == Lm) ? 1 : (w >= h ? h - 1 : w - 1);
+  static constexpr int bnd = 2 * (w + h);
+  static constexpr int U = gam + bnd;
+  static constexpr int ld = U + 1;              // logical frame size
+  static constexpr int ldp = ld | 1;              // odd LDS row stride (no bank conflicts on columns)
+  static constexpr int fsz = ld * ldp;            // LDS elements per frame
+  static constexpr int per = ld * gam;            // compact elements per node
+};
+
+// Largest per-level index table (maps: n * 2 * (U+1), local ids: n * U).
+template <int S, int K> constexpr int idx_max_from() {
+  using L = Lv<S, K>;
+  constexpr int a = (K < L::Lm) ? L::n * 2 * L::ld : 0;
+  constexpr int b = L::n * L::U;
+  constexpr int m = a > b ? a : b;
+  if constexpr (K < L::Lm) {
+    constexpr int rest = idx_max_from<S, K + 1>();
+    return m > rest ? m : rest;
+  } else {
+    return m;
+  }
+}
+template <int S> constexpr int kIdxMax = idx_max_from<S, 0>();
+
+__device__ __forceinline__ void stage_ints(int* dst, const int* src, int n) {
+  for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
+}
+
 template <typename T> __device__ __forceinline__ T* cst_block(const DevBlocks& B, int q, int s) {
   return reinterpret_cast<T*>(B.cst) + (long long)s * B.cst_stride + (long long)q * B.cst_size;
 }
 
+constexpr int NT = 256;   // threads of the top-down / forward kernels
+constexpr int NTB = 512;  // threads of the build kernel
+
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256) k_block_build(DevBlocks B, int n_samples, int nc,
-                                                     const double* __restrict__ kappa, const double* __restrict__ f,
-                                                     int* __restrict__ bad, int* __restrict__ info) {
+// Column J of the left-looking partial Cholesky for all n frames of a level:
+// L_jj = sqrt(A_jj - sum_l L_jl^2), then every row below (interface,
+// boundary and load rows) L_ij = (A_ij - sum_l L_il L_jl) / L_jj.  Unrolled
+// over the (compile-time) columns so every inner loop has a fixed length.
+template <typename T, typename L, int J>
+__device__ __forceinline__ void crout_columns(T* cur, int& bad_pivot) {
+  if constexpr (J < L::gam) {
+    constexpr int ld = L::ldp;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < L::n; t += NTB) {
+      T* F = cur + t * L::fsz;
+      T d = F[J * ld + J];
+#pragma unroll
+      for (int l = 0; l < J; ++l) d -= F[J * ld + l] * F[J * ld + l];
+      if (!(d > T(0)) || !(d < T(1e300))) {
+        bad_pivot = 1;
+        d = T(1);
+      }
+      F[J * ld + J] = sqrt(d);
+    }
+    __syncthreads();
+    constexpr int m = L::U - J;  // rows J+1 .. U
+    for (int e = tid; e < L::n * m; e += NTB) {
+      const int t = e / m, i = J + 1 + e % m;
+      T* F = cur + t * L::fsz;
+      T v = F[i * ld + J];
+#pragma unroll
+      for (int l = 0; l < J; ++l) v -= F[i * ld + l] * F[J * ld + l];
+      F[i * ld + J] = v / F[J * ld + J];
+    }
+    __syncthreads();
+    crout_columns<T, L, J + 1>(cur, bad_pivot);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Build: one level (extend-add from the sons in `prev`, eliminate in `cur`).
+template <typename T, int S, int K>
+__device__ __forceinline__ void build_level(const DevBlocks& B, T* cur, const T* prev, T* cst, int* idx,
+                                            int& bad_pivot) {
+  using L = Lv<S, K>;
+  const int tid = threadIdx.x;
+  constexpr int NB = NTB;
+  if constexpr (K < L::Lm) {
+    using C = Lv<S, K + 1>;
+    stage_ints(idx, B.maps + B.lv[K].map_off, L::n * 2 * L::ld);
+    __syncthreads();
+    const int* maps = idx;
+    for (int e = tid; e < L::n * L::ld * L::ld; e += NB) {
+      const int t = e / (L::ld * L::ld), rc = e % (L::ld * L::ld);
+      const int r = rc / L::ld, c = rc % L::ld;
+      if (c > r) continue;
+      const int* mA = maps + t * 2 * L::ld;
+      const int* mB = mA + L::ld;
+      const T* SA = prev + (2 * t) * C::fsz + C::gam * C::ldp + C::gam;
+      const T* SB = SA + C::fsz;
+      T v = T(0);
+      const int ar = mA[r], ac = mA[c];
+      if (ar >= 0 && ac >= 0) v += ar >= ac ? SA[ar * C::ldp + ac] : SA[ac * C::ldp + ar];
+      const int br = mB[r], bc = mB[c];
+      if (br >= 0 && bc >= 0) v += br >= bc ? SB[br * C::ldp + bc] : SB[bc * C::ldp + br];
+      cur[t * L::fsz + r * L::ldp + c] = v;
+    }
+    __syncthreads();
+  }
+  // Partial Cholesky of the first gam columns (left-looking, column by
+  // column): L_jj = sqrt(A_jj - sum_l L_jl^2), then every row below
+  // (interface, boundary and load rows) L_ij = (A_ij - sum_l L_il L_jl) / L_jj.
+  constexpr int g = L::gam, ld = L::ldp;
+  crout_columns<T, L, 0>(cur, bad_pivot);
+  // Schur update of the boundary block and the load row (rank-g, eq.
+  // SchurC1): S[i][l] -= sum_k P[i][k] P[l][k], g <= l <= i <= U.
+  {
+    constexpr int nr = L::U + 1 - g;
+    for (int e = tid; e < L::n * nr * nr; e += NB) {
+      const int t = e / (nr * nr), p = e % (nr * nr);
+      const int i = g + p / nr, l = g + p % nr;
+      if (l > i) continue;
+      T* F = cur + t * L::fsz;
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < g; ++k) acc += F[i * ld + k] * F[l * ld + k];
+      F[i * ld + l] -= acc;
+    }
+  }
+  __syncthreads();
+  // retained columns [L ; P ; z] of every node -> compact store
+  T* out = cst + B.lv[K].cst_off;
+  for (int e = tid; e < L::n * L::per; e += NB) {
+    const int t = e / L::per, rc = e % L::per;
+    const int r = rc / g, c = rc % g;
+    out[e] = (c <= r) ? cur[t * L::fsz + r * ld + c] : T(0);  // ld = physical stride here
+  }
+  __syncthreads();
+}
+
+template <typename T, int S, int K>
+__device__ __forceinline__ void build_levels(const DevBlocks& B, T* cur, T* prev, T* cst, int* idx, int& bad_pivot) {
+  build_level<T, S, K>(B, cur, prev, cst, idx, bad_pivot);
+  if constexpr (K > 0) build_levels<T, S, K - 1>(B, prev, cur, cst, idx, bad_pivot);
+}
+
+template <typename T, int S>
+__global__ void __launch_bounds__(NTB) k_block_build(DevBlocks B, int n_samples, int nc,
+                                                    const double* __restrict__ kappa, const double* __restrict__ f,
+                                                    int* __restrict__ bad, int* __restrict__ info) {
+  using M = Lv<S, Lv<S, 0>::Lm>;
+  constexpr int Lm = M::Lm;
   extern __shared__ __align__(16) unsigned char smem[];
   T* buf0 = reinterpret_cast<T*>(smem);
   T* buf1 = buf0 + B.max_buf;
   __shared__ int bad_pivot;
+  __shared__ int idx[kIdxMax<S>];
   const int q = blockIdx.x / n_samples;
   const int s = blockIdx.x % n_samples;
   const int X0 = B.origin[2 * q], Y0 = B.origin[2 * q + 1];
   const int tid = threadIdx.x;
-  const int NT = blockDim.x;
-  const int Lm = B.nlev - 1;
   if (tid == 0) bad_pivot = 0;
-  // ---- micro-blocks: assemble the 9 x 9 local systems (lower triangle + load row)
+  // The block's coefficients (S x S cells x 2 triangles) and nodal load
+  // ((S+1)^2) are staged in the still unused second frame buffer.
+  constexpr int S1 = S + 1;
+  double* kL = reinterpret_cast<double*>(buf1);
+  double* fL = kL + 2 * S * S;
   {
-    const DevSubLevel M = B.lv[Lm];
-    for (int e = tid; e < M.n * M.fsz; e += NT) buf0[e] = T(0);
-    __syncthreads();
+    const double* ks = kappa + (long long)s * nc * nc * 2;
+    for (int e = tid; e < 2 * S * S; e += NTB) {
+      const int row = e / (2 * S), col = e % (2 * S);
+      kL[e] = ks[((long long)(Y0 + row) * nc + X0) * 2 + col];
+    }
+    for (int e = tid; e < S1 * S1; e += NTB) fL[e] = f[(long long)(Y0 + e / S1) * (nc + 1) + X0 + e % S1];
+  }
+  // micro-blocks: assemble the 9 x 9 local systems (lower triangle + load row)
+  for (int e = tid; e < M::n * M::fsz; e += NTB) buf0[e] = T(0);
+  __syncthreads();
+  {
     const double h = 1.0 / nc;
     const double area = 0.5 * h * h;
-    const double* ks = kappa + (long long)s * nc * nc * 2;
-    for (int t = tid; t < M.n; t += NT) {
-      T* F = buf0 + t * M.fsz;
-      const int a0 = X0 + B.micro_xy[2 * t], b0 = Y0 + B.micro_xy[2 * t + 1];
+    for (int t = tid; t < M::n; t += NTB) {
+      T* F = buf0 + t * M::fsz;
+      const int a0 = B.micro_xy[2 * t], b0 = B.micro_xy[2 * t + 1];  // local corner
       bool ok = true;
+#pragma unroll
       for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
         for (int ca = 0; ca < 2; ++ca)
+#pragma unroll
           for (int tri = 0; tri < 2; ++tri) {
             // T-: (0,0),(1,0),(1,1); T+: (0,0),(1,1),(0,1) relative to the cell corner
             const int vx[3] = {ca, ca + 1, tri == 0 ? ca + 1 : ca};
             const int vy[3] = {cb, tri == 0 ? cb : cb + 1, cb + 1};
-            const double kap = ks[((long long)(b0 + cb) * nc + (a0 + ca)) * 2 + tri];
+            const double kap = kL[(b0 + cb) * 2 * S + (a0 + ca) * 2 + tri];
             ok = ok && (kap > 0.0) && (kap < 1.0e300);
             const double det = double((vx[1] - vx[0]) * (vy[2] - vy[0]) - (vx[2] - vx[0]) * (vy[1] - vy[0]));
             const double gx[3] = {double(vy[1] - vy[2]), double(vy[2] - vy[0]), double(vy[0] - vy[1])};
             const double gy[3] = {double(vx[2] - vx[1]), double(vx[0] - vx[2]), double(vx[1] - vx[0])};
             const double scale = kap / (2.0 * fabs(det));
+#pragma unroll
             for (int a = 0; a < 3; ++a) {
               const int ia = c_mb_local[vy[a]][vx[a]];
+#pragma unroll
               for (int b = 0; b < 3; ++b) {
                 const int ib = c_mb_local[vy[b]][vx[b]];
-                if (ib <= ia) F[ia * 10 + ib] += T(scale * (gx[a] * gx[b] + gy[a] * gy[b]));
+                if (ib <= ia) F[ia * M::ldp + ib] += T(scale * (gx[a] * gx[b] + gy[a] * gy[b]));
               }
-              const double fv = f[(long long)(b0 + vy[a]) * (nc + 1) + (a0 + vx[a])];
-              F[9 * 10 + ia] += T(area * fv / 3.0);
+              const double fv = fL[(b0 + vy[a]) * S1 + (a0 + vx[a])];
+              F[9 * M::ldp + ia] += T(area * fv / 3.0);
             }
           }
       if (!ok && bad) atomicCAS(bad + s, 0, 1);
     }
-    __syncthreads();
   }
-  T* cur = buf0;
-  T* prev = buf1;
-  for (int k = Lm; k >= 0; --k) {
-    const DevSubLevel L = B.lv[k];
-    const int ld = L.U + 1;
-    if (k < Lm) {
-      // extend-add of the sons' [Gamma ; rhs] blocks (in `prev`) into the frames (in `cur`)
-      const DevSubLevel C = B.lv[k + 1];
-      const int lds = C.U + 1;
-      for (int e = tid; e < L.n * L.fsz; e += NT) {
-        const int t = e / L.fsz, rc = e % L.fsz;
-        const int r = rc / ld, c = rc % ld;
-        if (c > r) continue;
-        const int* mA = B.maps + L.map_off + t * 2 * ld;
-        const int* mB = mA + ld;
-        T v = T(0);
-        const T* SA = prev + (2 * t) * C.fsz + C.gam * lds + C.gam;
-        const T* SB = prev + (2 * t + 1) * C.fsz + C.gam * lds + C.gam;
-        const int ar = mA[r], ac = mA[c];
-        if (ar >= 0 && ac >= 0) v += ar >= ac ? SA[ar * lds + ac] : SA[ac * lds + ar];
-        const int br = mB[r], bc = mB[c];
-        if (br >= 0 && bc >= 0) v += br >= bc ? SB[br * lds + bc] : SB[bc * lds + br];
-        cur[e] = v;
-      }
-      __syncthreads();
-    }
-    // partial Cholesky of the first gam columns of every frame of the level
-    for (int j = 0; j < L.gam; ++j) {
-      for (int t = tid; t < L.n; t += NT) {
-        T d = cur[t * L.fsz + j * ld + j];
-        if (!(d > T(0)) || !(d < T(1e300))) {
-          bad_pivot = 1;
-          d = T(1);
-        }
-        cur[t * L.fsz + j * ld + j] = sqrt(d);
-      }
-      __syncthreads();
-      const int m = L.U - j;  // rows j+1 .. U
-      for (int e = tid; e < L.n * m; e += NT) {
-        const int t = e / m, i = j + 1 + e % m;
-        cur[t * L.fsz + i * ld + j] /= cur[t * L.fsz + j * ld + j];
-      }
-      __syncthreads();
-      for (int e = tid; e < L.n * m * m; e += NT) {
-        const int t = e / (m * m), rr = e % (m * m);
-        const int i = j + 1 + rr / m, l = j + 1 + rr % m;
-        if (l <= i) {
-          T* F = cur + t * L.fsz;
-          F[i * ld + l] -= F[i * ld + j] * F[l * ld + j];
-        }
-      }
-      __syncthreads();
-    }
-    // retained columns [L ; P ; z] of every node -> compact store
-    T* out = cst_block<T>(B, q, s) + L.cst_off;
-    const int per = ld * L.gam;
-    for (int e = tid; e < L.n * per; e += NT) {
-      const int t = e / per, rc = e % per;
-      const int r = rc / L.gam, c = rc % L.gam;
-      out[e] = (c <= r) ? cur[t * L.fsz + r * ld + c] : T(0);
-    }
-    __syncthreads();
-    T* tmp = cur;
-    cur = prev;
-    prev = tmp;
-  }
-  // block root frame (now in `prev`) -> global frame store (lower triangle)
+  __syncthreads();
+  T* cst = cst_block<T>(B, q, s);
+  int bp = 0;
+  build_levels<T, S, Lm>(B, buf0, buf1, cst, idx, bp);
+  if (bp) bad_pivot = 1;
+  __syncthreads();
+  // block root frame -> global frame store (lower triangle)
   {
-    const DevSubLevel R = B.lv[0];
-    const int ld = R.U + 1;
+    using R = Lv<S, 0>;
+    const T* root = (Lm % 2 == 0) ? buf0 : buf1;
     const DevNode nd = B.top.nodes[q];
     T* G = reinterpret_cast<T*>(B.top.frames) + (long long)s * B.top.stride + nd.frame_off;
-    for (int e = tid; e < R.fsz; e += NT) {
-      const int r = e / ld, c = e % ld;
-      if (c <= r) G[(long long)r * nd.ld + c] = prev[e];
+    for (int e = tid; e < R::ld * R::ld; e += NTB) {
+      const int r = e / R::ld, c = e % R::ld;
+      if (c <= r) G[(long long)r * nd.ld + c] = root[r * R::ldp + c];
     }
   }
   if (tid == 0 && bad_pivot && info) atomicCAS(info + s, 0, B.top.node_base + q + 1);
 }
 
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256) k_block_topdown(DevBlocks B, const int* __restrict__ list, int n_samples,
-                                                       int nc, double* __restrict__ u, long long ustride,
-                                                       int from_vec) {
-  extern __shared__ double dsm[];
-  const int S1 = B.s + 1;
-  double* uL = dsm;               // (s+1)^2 local nodal values
-  double* rb = dsm + S1 * S1;     // n * gam work values of one level
+// Top-down: the block's compact factors are staged in LDS, u on the block's
+// (S+1)^2 nodes lives in LDS; levels are solved root first.
+template <typename T, int S, int K>
+__device__ __forceinline__ void topdown_level(const DevBlocks& B, const T* cst, const double* vz, double* uL,
+                                              double* rb, int* idx) {
+  using L = Lv<S, K>;
+  constexpr int g = L::gam, U = L::U;
+  const int tid = threadIdx.x;
+  const T* base = cst + B.lv[K].cst_off;
+  stage_ints(idx, B.lids + B.lv[K].lid_off, L::n * U);
+  __syncthreads();
+  const int* lids = idx;
+  for (int e = tid; e < L::n * g; e += NT) {
+    const int t = e / g, i = e % g;
+    const T* blk = base + t * L::per;
+    const int* lid = lids + t * U;
+    double acc = vz ? vz[B.lv[K].vec_off + e] : double(blk[U * g + i]);
+#pragma unroll
+    for (int j = 0; j < L::bnd; ++j) acc -= double(blk[(g + j) * g + i]) * uL[lid[g + j]];
+    rb[e] = acc;
+  }
+  __syncthreads();
+  for (int t = tid; t < L::n; t += NT) {
+    const T* blk = base + t * L::per;
+    const int* lid = lids + t * U;
+    double* x = rb + t * g;
+#pragma unroll
+    for (int i = g - 1; i >= 0; --i) {
+      double v = x[i];
+#pragma unroll
+      for (int l = i + 1; l < g; ++l) v -= double(blk[l * g + i]) * x[l];
+      v /= double(blk[i * g + i]);
+      x[i] = v;
+      uL[lid[i]] = v;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int S, int K>
+__device__ __forceinline__ void topdown_levels(const DevBlocks& B, const T* cst, const double* vz, double* uL,
+                                               double* rb, int* idx) {
+  topdown_level<T, S, K>(B, cst, vz, uL, rb, idx);
+  if constexpr (K < Lv<S, 0>::Lm) topdown_levels<T, S, K + 1>(B, cst, vz, uL, rb, idx);
+}
+
+template <typename T, int S>
+__global__ void __launch_bounds__(NT) k_block_topdown(DevBlocks B, const int* __restrict__ list, int n_samples,
+                                                      int nc, double* __restrict__ u, long long ustride,
+                                                      int from_vec) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int S1 = S + 1;
+  T* cs = reinterpret_cast<T*>(smem);                                    // cst_size
+  double* uL = reinterpret_cast<double*>(smem + ((size_t(B.cst_size) * sizeof(T) + 15) / 16) * 16);
+  double* rb = uL + S1 * S1;                                             // max n * gam
+  __shared__ int idx[kIdxMax<S>];
   const int q = list[blockIdx.x / n_samples];
   const int s = blockIdx.x % n_samples;
   const int X0 = B.origin[2 * q], Y0 = B.origin[2 * q + 1];
-  const int tid = threadIdx.x, NT = blockDim.x;
+  const int tid = threadIdx.x;
   double* us = u + (long long)s * ustride;
+  const T* cst = cst_block<T>(B, q, s);
+  for (int e = tid; e < B.cst_size; e += NT) cs[e] = cst[e];
   for (int e = tid; e < S1 * S1; e += NT) uL[e] = us[(long long)(Y0 + e / S1) * (nc + 1) + X0 + e % S1];
   __syncthreads();
-  const T* cst = cst_block<T>(B, q, s);
   const double* vz = from_vec ? B.vec + (long long)s * B.vec_stride + (long long)q * B.vec_size : nullptr;
-  for (int k = 0; k < B.nlev; ++k) {
-    const DevSubLevel L = B.lv[k];
-    const int g = L.gam, per = (L.U + 1) * g;
-    for (int e = tid; e < L.n * g; e += NT) {
-      const int t = e / g, i = e % g;
-      const T* blk = cst + L.cst_off + t * per;
-      const int* lid = B.lids + L.lid_off + t * L.U;
-      double acc = from_vec ? vz[L.vec_off + e] : double(blk[L.U * g + i]);
-      for (int j = 0; j < L.bnd; ++j) acc -= double(blk[(g + j) * g + i]) * uL[lid[g + j]];
-      rb[e] = acc;
-    }
-    __syncthreads();
-    for (int t = tid; t < L.n; t += NT) {
-      const T* blk = cst + L.cst_off + t * per;
-      const int* lid = B.lids + L.lid_off + t * L.U;
-      double* x = rb + t * g;
-      for (int i = g - 1; i >= 0; --i) {
-        double v = x[i];
-        for (int l = i + 1; l < g; ++l) v -= double(blk[l * g + i]) * x[l];
-        v /= double(blk[i * g + i]);
-        x[i] = v;
-        uL[lid[i]] = v;
-      }
-    }
-    __syncthreads();
-  }
-  const int si = B.s - 1;
+  topdown_levels<T, S, 0>(B, cs, vz, uL, rb, idx);
+  constexpr int si = S - 1;
   for (int e = tid; e < si * si; e += NT) {
     const int a = 1 + e % si, b = 1 + e / si;
     us[(long long)(Y0 + b) * (nc + 1) + X0 + a] = uL[b * S1 + a];
@@ -218,124 +340,192 @@ __global__ void __launch_bounds__(256) k_block_topdown(DevBlocks B, const int* _
 }
 
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256) k_block_forward(DevBlocks B, int n_samples, int nc,
-                                                       const double* __restrict__ res, long long rstride) {
-  extern __shared__ double dsm[];
-  double* g0 = dsm;                       // per level: n * U values
-  double* g1 = dsm + B.max_bnd_nodes;
-  const int S1 = B.s + 1;
+// Forward: new load propagated bottom-up through the block's factors.
+template <typename T, int S, int K>
+__device__ __forceinline__ void forward_level(const DevBlocks& B, const T* cst, double* vz, double* cur,
+                                              const double* prev, int* idx) {
+  using L = Lv<S, K>;
+  constexpr int g = L::gam, U = L::U;
+  const int tid = threadIdx.x;
+  if constexpr (K < L::Lm) {
+    using C = Lv<S, K + 1>;
+    stage_ints(idx, B.maps + B.lv[K].map_off, L::n * 2 * (U + 1));
+    __syncthreads();
+    const int* maps = idx;
+    for (int e = tid; e < L::n * U; e += NT) {
+      const int t = e / U, i = e % U;
+      const int* mA = maps + t * 2 * (U + 1);
+      const int* mB = mA + (U + 1);
+      double v = 0.0;
+      if (mA[i] >= 0) v += prev[(2 * t) * C::U + C::gam + mA[i]];
+      if (mB[i] >= 0) v += prev[(2 * t + 1) * C::U + C::gam + mB[i]];
+      cur[e] = v;
+    }
+    __syncthreads();
+  }
+  const T* base = cst + B.lv[K].cst_off;
+  for (int t = tid; t < L::n; t += NT) {  // z = L^-1 g_gamma
+    const T* blk = base + t * L::per;
+    double* x = cur + t * U;
+#pragma unroll
+    for (int i = 0; i < g; ++i) {
+      double v = x[i];
+#pragma unroll
+      for (int l = 0; l < i; ++l) v -= double(blk[i * g + l]) * x[l];
+      x[i] = v / double(blk[i * g + i]);
+      vz[B.lv[K].vec_off + t * g + i] = x[i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < L::n * L::bnd; e += NT) {  // g_omega = g_Gamma - P z
+    const int t = e / L::bnd, j = e % L::bnd;
+    const T* blk = base + t * L::per;
+    const double* x = cur + t * U;
+    double v = x[g + j];
+#pragma unroll
+    for (int i = 0; i < g; ++i) v -= double(blk[(g + j) * g + i]) * x[i];
+    cur[t * U + g + j] = v;  // own slot; other threads read only x[0..g)
+  }
+  __syncthreads();
+}
+
+template <typename T, int S, int K>
+__device__ __forceinline__ void forward_levels(const DevBlocks& B, const T* cst, double* vz, double* cur,
+                                               double* prev, int* idx) {
+  forward_level<T, S, K>(B, cst, vz, cur, prev, idx);
+  if constexpr (K > 0) forward_levels<T, S, K - 1>(B, cst, vz, prev, cur, idx);
+}
+
+template <typename T, int S>
+__global__ void __launch_bounds__(NT) k_block_forward(DevBlocks B, int n_samples, int nc,
+                                                      const double* __restrict__ res, long long rstride) {
+  using M = Lv<S, Lv<S, 0>::Lm>;
+  constexpr int Lm = M::Lm;
+  constexpr int S1 = S + 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* cs = reinterpret_cast<T*>(smem);
+  double* g0 = reinterpret_cast<double*>(smem + ((size_t(B.cst_size) * sizeof(T) + 15) / 16) * 16);
+  double* g1 = g0 + B.max_bnd_nodes;
+  __shared__ int idx[kIdxMax<S>];
   const int q = blockIdx.x / n_samples;
   const int s = blockIdx.x % n_samples;
   const int X0 = B.origin[2 * q], Y0 = B.origin[2 * q + 1];
-  const int tid = threadIdx.x, NT = blockDim.x;
-  const int Lm = B.nlev - 1;
+  const int tid = threadIdx.x;
   const T* cst = cst_block<T>(B, q, s);
+  for (int e = tid; e < B.cst_size; e += NT) cs[e] = cst[e];
   double* vz = B.vec + (long long)s * B.vec_stride + (long long)q * B.vec_size;
   const double* rs = res + (long long)s * rstride;
-  double* cur = g0;
-  double* prev = g1;
-  for (int k = Lm; k >= 0; --k) {
-    const DevSubLevel L = B.lv[k];
-    const int g = L.gam, U = L.U, per = (U + 1) * g;
-    if (k == Lm) {
-      // micro-blocks: the residual node (i, j) belongs to the micro-block
-      // that contains cell (i, j), so each global entry is counted once
-      for (int e = tid; e < L.n * U; e += NT) {
-        const int t = e / U, i = e % U;
-        const int lid = B.lids[L.lid_off + e];
-        const int a = lid % S1, b = lid / S1;
-        const int a0 = B.micro_xy[2 * t], b0 = B.micro_xy[2 * t + 1];
-        const bool own = a >= a0 && a < a0 + 2 && b >= b0 && b < b0 + 2;
-        cur[e] = own ? rs[(long long)(Y0 + b) * (nc + 1) + X0 + a] : 0.0;
-        (void)i;
-      }
-    } else {
-      const DevSubLevel C = B.lv[k + 1];
-      for (int e = tid; e < L.n * U; e += NT) {
-        const int t = e / U, i = e % U;
-        const int* mA = B.maps + L.map_off + t * 2 * (U + 1);
-        const int* mB = mA + (U + 1);
-        double v = 0.0;
-        if (mA[i] >= 0) v += prev[(2 * t) * C.U + C.gam + mA[i]];
-        if (mB[i] >= 0) v += prev[(2 * t + 1) * C.U + C.gam + mB[i]];
-        cur[e] = v;
-      }
-    }
+  // micro-blocks: node (i, j) of the residual belongs to the micro-block that
+  // contains cell (i, j), so each global entry is counted exactly once
+  {
+    stage_ints(idx, B.lids + B.lv[Lm].lid_off, M::n * M::U);
     __syncthreads();
-    // z = L^-1 g_gamma, one thread per node
-    for (int t = tid; t < L.n; t += NT) {
-      const T* blk = cst + L.cst_off + t * per;
-      double* x = cur + t * U;
-      for (int i = 0; i < g; ++i) {
-        double v = x[i];
-        for (int l = 0; l < i; ++l) v -= double(blk[i * g + l]) * x[l];
-        x[i] = v / double(blk[i * g + i]);
-        vz[L.vec_off + t * g + i] = x[i];
-      }
+    const int* lids = idx;
+    for (int e = tid; e < M::n * M::U; e += NT) {
+      const int t = e / M::U;
+      const int lid = lids[e];
+      const int a = lid % S1, b = lid / S1;
+      const int a0 = B.micro_xy[2 * t], b0 = B.micro_xy[2 * t + 1];
+      const bool own = a >= a0 && a < a0 + 2 && b >= b0 && b < b0 + 2;
+      g0[e] = own ? rs[(long long)(Y0 + b) * (nc + 1) + X0 + a] : 0.0;
     }
-    __syncthreads();
-    // g_omega = g_Gamma - P z
-    for (int e = tid; e < L.n * L.bnd; e += NT) {
-      const int t = e / L.bnd, j = e % L.bnd;
-      const T* blk = cst + L.cst_off + t * per;
-      const double* x = cur + t * U;
-      double v = x[g + j];
-      for (int i = 0; i < g; ++i) v -= double(blk[(g + j) * g + i]) * x[i];
-      cur[t * U + g + j] = v;  // own slot only: rows g+j are not read by other threads
-    }
-    __syncthreads();
-    double* tmp = cur;
-    cur = prev;
-    prev = tmp;
   }
+  __syncthreads();
+  forward_levels<T, S, Lm>(B, cs, vz, g0, g1, idx);
   // block root [z ; g_omega] -> the global vector store of the block level
-  const DevSubLevel R = B.lv[0];
+  using R = Lv<S, 0>;
+  const double* root = (Lm % 2 == 0) ? g0 : g1;
   const DevNode nd = B.top.nodes[q];
   double* out = B.top.vec + (long long)s * B.top.vec_stride + nd.ids_off;
-  for (int e = tid; e < R.U; e += NT) out[e] = prev[e];
+  for (int e = tid; e < R::U; e += NT) out[e] = root[e];
 }
 
 // ---------------------------------------------------------------------------
-static int ceil_div_b(long long a, long long b) { return int((a + b - 1) / b); }
-
 size_t block_build_lds(const DevBlocks& B, bool dbl) { return size_t(2) * B.max_buf * (dbl ? 8 : 4); }
+
+static size_t stage_bytes(const DevBlocks& B, bool dbl) { return (size_t(B.cst_size) * (dbl ? 8 : 4) + 15) / 16 * 16; }
+
+size_t block_topdown_lds(const DevBlocks& B, bool dbl) {
+  return stage_bytes(B, dbl) + sizeof(double) * size_t((B.s + 1) * (B.s + 1) + B.max_gam_nodes);
+}
+
+size_t block_forward_lds(const DevBlocks& B, bool dbl) {
+  return stage_bytes(B, dbl) + sizeof(double) * size_t(2 * B.max_bnd_nodes);
+}
+
+template <int S, int K> static bool shape_ok_from(const DevBlocks& B) {
+  using L = Lv<S, K>;
+  const bool ok = B.lv[K].n == L::n && B.lv[K].gam == L::gam && B.lv[K].bnd == L::bnd && B.lv[K].fsz == L::fsz;
+  if constexpr (K < Lv<S, 0>::Lm) return ok && shape_ok_from<S, K + 1>(B);
+  return ok;
+}
+
+template <int S> static bool shape_ok(const DevBlocks& B) {
+  return B.nlev == Lv<S, 0>::Lm + 1 && shape_ok_from<S, 0>(B);
+}
+
+bool block_shape_ok(const DevBlocks& B) {
+  switch (B.s) {
+    case 2: return shape_ok<2>(B);
+    case 4: return shape_ok<4>(B);
+    case 8: return shape_ok<8>(B);
+    case 16: return shape_ok<16>(B);
+    default: return false;
+  }
+}
+
+template <typename T, int S>
+static void launch_build_t(const DevBlocks& B, int n_samples, int nc, const double* kappa, const double* f, int* bad,
+                           int* info, hipStream_t st) {
+  const size_t lds = block_build_lds(B, sizeof(T) == 8);
+  hipLaunchKernelGGL((k_block_build<T, S>), dim3(B.nb * n_samples), dim3(NTB), lds, st, B, n_samples, nc, kappa, f,
+                     bad, info);
+}
+
+template <typename T, int S>
+static void launch_topdown_t(const DevBlocks& B, const int* list, int n_list, int n_samples, int nc, double* u,
+                             long long ustride, bool from_vec, hipStream_t st) {
+  const size_t lds = block_topdown_lds(B, sizeof(T) == 8);
+  hipLaunchKernelGGL((k_block_topdown<T, S>), dim3(n_list * n_samples), dim3(NT), lds, st, B, list, n_samples, nc, u,
+                     ustride, from_vec ? 1 : 0);
+}
+
+template <typename T, int S>
+static void launch_forward_t(const DevBlocks& B, int n_samples, int nc, const double* r, long long rstride,
+                             hipStream_t st) {
+  const size_t lds = block_forward_lds(B, sizeof(T) == 8);
+  hipLaunchKernelGGL((k_block_forward<T, S>), dim3(B.nb * n_samples), dim3(NT), lds, st, B, n_samples, nc, r,
+                     rstride);
+}
+
+#define HDD_BLOCK_DISPATCH(FN, ...)                                   \
+  do {                                                                \
+    const bool dbl_ = B.top.is_double != 0;                           \
+    switch (B.s) {                                                    \
+      case 2: dbl_ ? FN<double, 2>(__VA_ARGS__) : FN<float, 2>(__VA_ARGS__); break;    \
+      case 4: dbl_ ? FN<double, 4>(__VA_ARGS__) : FN<float, 4>(__VA_ARGS__); break;    \
+      case 8: dbl_ ? FN<double, 8>(__VA_ARGS__) : FN<float, 8>(__VA_ARGS__); break;    \
+      case 16: dbl_ ? FN<double, 16>(__VA_ARGS__) : FN<float, 16>(__VA_ARGS__); break; \
+      default: return hipErrorInvalidValue;                           \
+    }                                                                 \
+  } while (0)
 
 hipError_t launch_block_build(const DevBlocks& B, int n_samples, int nc, const double* kappa, const double* f,
                               int* bad, int* info, hipStream_t st) {
-  dim3 grid(B.nb * n_samples), block(256);
-  const bool dbl = B.top.is_double != 0;
-  const size_t lds = block_build_lds(B, dbl);
-  if (dbl)
-    hipLaunchKernelGGL(k_block_build<double>, grid, block, lds, st, B, n_samples, nc, kappa, f, bad, info);
-  else
-    hipLaunchKernelGGL(k_block_build<float>, grid, block, lds, st, B, n_samples, nc, kappa, f, bad, info);
+  HDD_BLOCK_DISPATCH(launch_build_t, B, n_samples, nc, kappa, f, bad, info, st);
   return hipGetLastError();
 }
 
 hipError_t launch_block_topdown(const DevBlocks& B, const int* list, int n_list, int n_samples, int nc, double* u,
                                 long long ustride, bool from_vec, hipStream_t st) {
   if (n_list <= 0) return hipSuccess;
-  dim3 grid(n_list * n_samples), block(256);
-  const size_t lds = sizeof(double) * size_t((B.s + 1) * (B.s + 1) + B.max_gam_nodes);
-  if (B.top.is_double)
-    hipLaunchKernelGGL(k_block_topdown<double>, grid, block, lds, st, B, list, n_samples, nc, u, ustride,
-                       from_vec ? 1 : 0);
-  else
-    hipLaunchKernelGGL(k_block_topdown<float>, grid, block, lds, st, B, list, n_samples, nc, u, ustride,
-                       from_vec ? 1 : 0);
+  HDD_BLOCK_DISPATCH(launch_topdown_t, B, list, n_list, n_samples, nc, u, ustride, from_vec, st);
   return hipGetLastError();
 }
 
 hipError_t launch_block_forward(const DevBlocks& B, int n_samples, int nc, const double* r, long long rstride,
                                 hipStream_t st) {
-  dim3 grid(B.nb * n_samples), block(256);
-  const size_t lds = sizeof(double) * size_t(2 * B.max_bnd_nodes);
-  if (B.top.is_double)
-    hipLaunchKernelGGL(k_block_forward<double>, grid, block, lds, st, B, n_samples, nc, r, rstride);
-  else
-    hipLaunchKernelGGL(k_block_forward<float>, grid, block, lds, st, B, n_samples, nc, r, rstride);
-  (void)ceil_div_b;
+  HDD_BLOCK_DISPATCH(launch_forward_t, B, n_samples, nc, r, rstride, st);
   return hipGetLastError();
 }
 

@@ -276,6 +276,106 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
       }
 }
 
+// Large-tile version for the upper levels: 128 x 128 output tile per
+// workgroup (4 waves, 64 x 64 each as 2 x 2 blocks of 32 x 32 x 2 MFMA),
+// K chunks of 32 staged through LDS, the next chunk prefetched into registers
+// while the current one is multiplied.  Requires ld % 4 == 0 and k0 % 4 == 0
+// (16-byte aligned rows), which holds for frames with 64 or more rows.
+__global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int n_samples) {
+  constexpr int KC = 32, TM = 128;
+  __shared__ float As[TM][KC + 1];
+  __shared__ float Bs[TM][KC + 1];
+  const int pair = blockIdx.x;
+  const int node = pair / n_samples, s = pair % n_samples;
+  const DevNode nd = L.nodes[node];
+  const int U = nd.U;
+  const int c1e = a.c1 < 0 ? U + 1 : a.c1;
+  const int ti = blockIdx.y / a.tiles_c, tj = blockIdx.y % a.tiles_c;
+  const int i0 = a.r0 + ti * TM, j0 = a.c0 + tj * TM;
+  if (i0 > U || j0 >= c1e || i0 + TM - 1 < j0) return;
+  float* F = frame_ptr<float>(L, node, s);
+  const int ld = nd.ld;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wr = w >> 1, wc = w & 1;
+  // loader mapping: thread -> (row lr, 16 consecutive k) for A and B
+  const int lr = tid >> 1, lk = (tid & 1) * 16;
+  const int ra = i0 + lr, rb = j0 + lr;
+  const bool vec4 = (ld % 4) == 0;  // 16-byte aligned rows
+  float4 pa[4], pb[4];
+  auto load = [&](int kb) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = kb + lk + 4 * q;
+      float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
+      if (vec4 && k + 3 < a.k1) {
+        if (ra <= U) va = *reinterpret_cast<const float4*>(F + (long long)ra * ld + k);
+        if (rb <= U) vb = *reinterpret_cast<const float4*>(F + (long long)rb * ld + k);
+      } else {
+        float ta[4] = {0.f, 0.f, 0.f, 0.f}, tb[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int x = 0; x < 4; ++x)
+          if (k + x < a.k1) {
+            if (ra <= U) ta[x] = F[(long long)ra * ld + k + x];
+            if (rb <= U) tb[x] = F[(long long)rb * ld + k + x];
+          }
+        va = make_float4(ta[0], ta[1], ta[2], ta[3]);
+        vb = make_float4(tb[0], tb[1], tb[2], tb[3]);
+      }
+      pa[q] = va;
+      pb[q] = vb;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      As[lr][lk + 4 * q + 0] = pa[q].x; As[lr][lk + 4 * q + 1] = pa[q].y;
+      As[lr][lk + 4 * q + 2] = pa[q].z; As[lr][lk + 4 * q + 3] = pa[q].w;
+      Bs[lr][lk + 4 * q + 0] = pb[q].x; Bs[lr][lk + 4 * q + 1] = pb[q].y;
+      Bs[lr][lk + 4 * q + 2] = pb[q].z; Bs[lr][lk + 4 * q + 3] = pb[q].w;
+    }
+  };
+  floatx16 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[x][y][v] = 0.f;
+  load(a.k0);
+  store();
+  __syncthreads();
+  for (int kb = a.k0; kb < a.k1; kb += KC) {
+    const bool more = kb + KC < a.k1;
+    if (more) load(kb + KC);
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 2) {
+      float av[2], bv[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) av[x] = As[wr * 64 + x * 32 + (lane & 31)][kk + (lane >> 5)];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y] = Bs[wc * 64 + y * 32 + (lane & 31)][kk + (lane >> 5)];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[x], bv[y], acc[x][y], 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) {
+      store();
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int i = i0 + wr * 64 + x * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        const int j = j0 + wc * 64 + y * 32 + (lane & 31);
+        syrk_store<float>(F, ld, U, i, j, a, c1e, acc[x][y][v]);
+      }
+}
+
 // Plain FMA version of the same update (no matrix cores), kept as a
 // cross-check of the MFMA lane layouts.
 template <typename T>
@@ -360,9 +460,17 @@ hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1
   const int rows = L.max_U + 1 - r0;
   const int cols = (c1 < 0 ? L.max_U + 1 : c1) - c0;
   if (rows <= 0 || cols <= 0) return hipSuccess;
-  const int tr = ceil_div(rows, 64);
-  a.tiles_c = ceil_div(cols, 64);
+  // Large frames (16-byte aligned rows) with enough work per tile use the
+  // 128 x 128 matrix-core tile.
+  const bool big = mfma && !L.is_double && rows >= 192 && cols >= 128 && (k0 % 4) == 0 && L.max_U + 1 >= 64;
+  const int TM = big ? 128 : 64;
+  const int tr = ceil_div(rows, TM);
+  a.tiles_c = ceil_div(cols, TM);
   dim3 grid(L.n_nodes * n_samples, tr * a.tiles_c), block(256);
+  if (big) {
+    hipLaunchKernelGGL(k_syrk128_f32, grid, block, 0, st, L, a, n_samples);
+    return hipGetLastError();
+  }
   if (L.is_double) {
     if (mfma)
       hipLaunchKernelGGL(k_syrk_mfma_f64, grid, block, 0, st, L, a, n_samples);

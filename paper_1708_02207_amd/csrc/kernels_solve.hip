@@ -18,91 +18,111 @@ static int ceil_div(long long a, long long b) { return int((a + b - 1) / b); }
 
 template <typename T> __device__ __forceinline__ double ldd(const T* p) { return double(*p); }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+// ---------------------------------------------------------------------------
+// Shared pieces of the per-node solves.  Dynamic LDS layout (doubles):
+//   v[U] (work vector), part[NW * gam] (GEMV partial sums), LD[nb][nb+1]
+// with nb = min(64, gam) the diagonal block of the triangular solves.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int solve_nb(int g) { return g < 64 ? g : 64; }
+
+size_t solve_lds(int max_U, int gam, int bs) {
+  const int nb = solve_nb(gam);
+  return sizeof(double) * (size_t(max_U + 1) + size_t(bs / 64) * gam + size_t(nb) * (nb + 1));
 }
 
-// ---------------------------------------------------------------------------
 // Top-down solve of the nodes in `list` (indices within the level) for all
-// samples.  grid.x = list entry * n_samples + sample.  Dynamic LDS holds
-// r[gamma] and u_Gamma[max |Gamma|]; a 64 x 65 diagonal block is static.
-// ---------------------------------------------------------------------------
+// samples: u_gamma = L^-T (z - P^T u_Gamma).  grid.x = entry * n_samples + s.
 template <typename T, int BS>
 __global__ void __launch_bounds__(BS) k_topdown(DevLevel L, const int* __restrict__ list, int n_samples,
                                                 double* __restrict__ u, long long ustride, int z_from_vec) {
   extern __shared__ double dyn[];
-  __shared__ double LD[64][65];
+  constexpr int NW = BS / 64;
   const int e = blockIdx.x;
   const int node = list[e / n_samples];
   const int s = e % n_samples;
   const DevNode nd = L.nodes[node];
   const int g = L.gam, G = nd.bnd, U = nd.U, ld = nd.ld;
+  const int nbm = solve_nb(g);
+  double* r = dyn;                 // [g]
+  double* ub = dyn + g;            // [G]
+  double* part = dyn + (L.max_U + 1);
+  double* LD = part + NW * g;      // [nbm][nbm+1]
   const T* F = frame_ptr<T>(L, node, s);
   const int* ids = L.ids + nd.ids_off;
   double* us = u + (long long)s * ustride;
-  double* r = dyn;
-  double* ub = dyn + g;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double* vz = z_from_vec ? L.vec + (long long)s * L.vec_stride + nd.ids_off : nullptr;
   for (int i = tid; i < g; i += BS) r[i] = z_from_vec ? vz[i] : ldd(F + (long long)U * ld + i);
   for (int j = tid; j < G; j += BS) ub[j] = us[ids[g + j]];
   __syncthreads();
-  // r -= P^T u_Gamma, P[j][i] = F[(g + j) * ld + i]
-  for (int i = tid; i < g; i += BS) {
-    double acc = 0.0;
-    const T* col = F + (long long)g * ld + i;
-    for (int j = 0; j < G; ++j) acc += ldd(col + (long long)j * ld) * ub[j];
-    r[i] -= acc;
+  // r -= P^T u_Gamma, P[j][i] = F[(g + j) * ld + i]; lanes over i, waves over j
+  if (G > 0) {
+    for (int i = lane; i < g; i += 64) {
+      double acc = 0.0;
+      const T* col = F + (long long)g * ld + i;
+#pragma unroll 8
+      for (int j = wv; j < G; j += NW) acc += ldd(col + (long long)j * ld) * ub[j];
+      part[wv * g + i] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < g; i += BS) {
+      double acc = 0.0;
+      for (int w = 0; w < NW; ++w) acc += part[w * g + i];
+      r[i] -= acc;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  // back substitution L^T x = r in blocks of 64 rows from the bottom
-  for (int b1 = g; b1 > 0; b1 -= 64) {
-    const int b0 = b1 > 64 ? b1 - 64 : 0;
+  // back substitution L^T x = r in blocks of nbm rows from the bottom
+  for (int b1 = g; b1 > 0; b1 -= nbm) {
+    const int b0 = b1 > nbm ? b1 - nbm : 0;
     const int nb = b1 - b0;
     for (int q = tid; q < nb * nb; q += BS) {
       const int i = q / nb, j = q % nb;
-      LD[i][j] = (j <= i) ? ldd(F + (long long)(b0 + i) * ld + (b0 + j)) : 0.0;
+      LD[i * (nbm + 1) + j] = (j <= i) ? ldd(F + (long long)(b0 + i) * ld + (b0 + j)) : 0.0;
     }
     __syncthreads();
     if (tid < 64) {
       double v = tid < nb ? r[b0 + tid] : 0.0;
       for (int jj = nb - 1; jj >= 0; --jj) {
-        const double xj = __shfl(v, jj) / LD[jj][jj];
+        const double xj = __shfl(v, jj) / LD[jj * (nbm + 1) + jj];
         if (tid == jj) v = xj;
-        else if (tid < jj) v -= LD[jj][tid] * xj;
+        else if (tid < jj) v -= LD[jj * (nbm + 1) + tid] * xj;
       }
       if (tid < nb) r[b0 + tid] = v;
     }
     __syncthreads();
-    for (int i = tid; i < b0; i += BS) {
-      double acc = 0.0;
-      for (int k = b0; k < b1; ++k) acc += ldd(F + (long long)k * ld + i) * r[k];
-      r[i] -= acc;
+    if (b0 > 0) {
+      for (int i = tid; i < b0; i += BS) {
+        double acc = 0.0;
+        const T* col = F + (long long)b0 * ld + i;
+#pragma unroll 16
+        for (int k = 0; k < nb; ++k) acc += ldd(col + (long long)k * ld) * r[b0 + k];
+        r[i] -= acc;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   for (int i = tid; i < g; i += BS) us[ids[i]] = r[i];
 }
 
-// ---------------------------------------------------------------------------
 // Forward (bottom-up) propagation of a right-hand side for all nodes of a
 // level above the blocks: the load is the extend-add of the sons' condensed
-// loads.  vec[node] = [z (gamma) ; g_omega (Gamma)].
-// ---------------------------------------------------------------------------
+// loads; z = L^-1 g~_gamma, g_omega = g~_Gamma - P z.
+// vec[node] = [z (gamma) ; g_omega (Gamma)].
 template <typename T, int BS>
 __global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int n_samples) {
-  extern __shared__ double gt[];
-  __shared__ double LD[64][65];
+  extern __shared__ double dyn[];
+  constexpr int NW = BS / 64;
   const int e = blockIdx.x;
   const int node = e / n_samples;
   const int s = e % n_samples;
   const DevNode nd = L.nodes[node];
   const int g = L.gam, G = nd.bnd, U = nd.U, ld = nd.ld;
+  const int nbm = solve_nb(g);
+  double* gt = dyn;  // [U]
+  double* LD = dyn + (L.max_U + 1) + NW * g;
   const T* F = frame_ptr<T>(L, node, s);
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  constexpr int NW = BS / 64;
+  const int tid = threadIdx.x;
   {
     const int* mA = L.maps + nd.map_off;
     const int* mB = mA + (U + 1);
@@ -118,41 +138,44 @@ __global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int n_sa
     }
   }
   __syncthreads();
-  // forward substitution L z = gt[0:g] in blocks of 64
-  for (int b0 = 0; b0 < g; b0 += 64) {
-    const int b1 = b0 + 64 < g ? b0 + 64 : g;
+  // forward substitution L z = gt[0:g] in blocks of nbm rows from the top
+  for (int b0 = 0; b0 < g; b0 += nbm) {
+    const int b1 = b0 + nbm < g ? b0 + nbm : g;
     const int nb = b1 - b0;
     for (int q = tid; q < nb * nb; q += BS) {
       const int i = q / nb, j = q % nb;
-      LD[i][j] = (j <= i) ? ldd(F + (long long)(b0 + i) * ld + (b0 + j)) : 0.0;
+      LD[i * (nbm + 1) + j] = (j <= i) ? ldd(F + (long long)(b0 + i) * ld + (b0 + j)) : 0.0;
     }
     __syncthreads();
     if (tid < 64) {
       double v = tid < nb ? gt[b0 + tid] : 0.0;
       for (int jj = 0; jj < nb; ++jj) {
-        const double zj = __shfl(v, jj) / LD[jj][jj];
+        const double zj = __shfl(v, jj) / LD[jj * (nbm + 1) + jj];
         if (tid == jj) v = zj;
-        else if (tid > jj) v -= LD[tid][jj] * zj;
+        else if (tid > jj) v -= LD[tid * (nbm + 1) + jj] * zj;
       }
       if (tid < nb) gt[b0 + tid] = v;
     }
     __syncthreads();
-    // rows below the block: one wave per row, lanes over the block columns
-    for (int i = b1 + wv; i < g; i += NW) {
-      double p = lane < nb ? ldd(F + (long long)i * ld + b0 + lane) * gt[b0 + lane] : 0.0;
-      p = wave_sum(p);
-      if (lane == 0) gt[i] -= p;
+    if (b1 < g) {
+      for (int i = b1 + tid; i < g; i += BS) {  // rows below: one thread per row
+        double acc = 0.0;
+        const T* row = F + (long long)i * ld + b0;
+#pragma unroll 16
+        for (int k = 0; k < nb; ++k) acc += ldd(row + k) * gt[b0 + k];
+        gt[i] -= acc;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  // g_omega[j] = gt[g + j] - sum_i P[j][i] z_i : one wave per row j
+  // g_omega[j] = gt[g + j] - sum_i P[j][i] z_i : one thread per row j
   double* out = L.vec + (long long)s * L.vec_stride + nd.ids_off;
-  for (int j = wv; j < G; j += NW) {
-    double p = 0.0;
+  for (int j = tid; j < G; j += BS) {
+    double acc = 0.0;
     const T* row = F + (long long)(g + j) * ld;
-    for (int i = lane; i < g; i += 64) p += ldd(row + i) * gt[i];
-    p = wave_sum(p);
-    if (lane == 0) out[g + j] = gt[g + j] - p;
+#pragma unroll 16
+    for (int i = 0; i < g; ++i) acc += ldd(row + i) * gt[i];
+    out[g + j] = gt[g + j] - acc;
   }
   for (int i = tid; i < g; i += BS) out[i] = gt[i];
 }
@@ -364,31 +387,34 @@ __global__ void k_mfma_selftest(int dtype, double* out) {
 hipError_t launch_topdown(const DevLevel& L, const int* list, int n_list, int n_samples, double* u, long long ustride,
                           bool z_from_vec, hipStream_t st) {
   if (n_list <= 0) return hipSuccess;
-  const size_t lds = sizeof(double) * size_t(L.gam + L.max_U - L.gam + 1);
   dim3 grid(n_list * n_samples);
+  const int zv = z_from_vec ? 1 : 0;
   if (L.gam <= 64) {
+    const size_t lds = solve_lds(L.max_U, L.gam, 64);
     if (L.is_double)
-      hipLaunchKernelGGL((k_topdown<double, 64>), grid, dim3(64), lds, st, L, list, n_samples, u, ustride, z_from_vec ? 1 : 0);
+      hipLaunchKernelGGL((k_topdown<double, 64>), grid, dim3(64), lds, st, L, list, n_samples, u, ustride, zv);
     else
-      hipLaunchKernelGGL((k_topdown<float, 64>), grid, dim3(64), lds, st, L, list, n_samples, u, ustride, z_from_vec ? 1 : 0);
+      hipLaunchKernelGGL((k_topdown<float, 64>), grid, dim3(64), lds, st, L, list, n_samples, u, ustride, zv);
   } else {
+    const size_t lds = solve_lds(L.max_U, L.gam, 256);
     if (L.is_double)
-      hipLaunchKernelGGL((k_topdown<double, 256>), grid, dim3(256), lds, st, L, list, n_samples, u, ustride, z_from_vec ? 1 : 0);
+      hipLaunchKernelGGL((k_topdown<double, 256>), grid, dim3(256), lds, st, L, list, n_samples, u, ustride, zv);
     else
-      hipLaunchKernelGGL((k_topdown<float, 256>), grid, dim3(256), lds, st, L, list, n_samples, u, ustride, z_from_vec ? 1 : 0);
+      hipLaunchKernelGGL((k_topdown<float, 256>), grid, dim3(256), lds, st, L, list, n_samples, u, ustride, zv);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_forward(const DevLevel& L, const DevLevel& child, int n_samples, hipStream_t st) {
-  const size_t lds = sizeof(double) * size_t(L.max_U + 1);
   dim3 grid(L.n_nodes * n_samples);
   if (L.gam <= 64) {
+    const size_t lds = solve_lds(L.max_U, L.gam, 64);
     if (L.is_double)
       hipLaunchKernelGGL((k_forward<double, 64>), grid, dim3(64), lds, st, L, child, n_samples);
     else
       hipLaunchKernelGGL((k_forward<float, 64>), grid, dim3(64), lds, st, L, child, n_samples);
   } else {
+    const size_t lds = solve_lds(L.max_U, L.gam, 256);
     if (L.is_double)
       hipLaunchKernelGGL((k_forward<double, 256>), grid, dim3(256), lds, st, L, child, n_samples);
     else
