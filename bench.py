@@ -26,8 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "hbm_gbs": 8000.0}
-KIND = {"syrk32": 0, "factor": 1, "extend": 2, "assemble": 3, "topdown": 4, "forward": 5, "residual": 6,
-        "syrk64": 7}
+KIND = {"syrk32": 0, "factor": 1, "extend": 2, "block_build": 3, "topdown": 4, "forward": 5, "residual": 6,
+        "syrk64": 7, "syrk128": 8}
 
 
 def parse():
@@ -148,12 +148,17 @@ def main():
         kern[name] = {"ms": ms / max(a.profile_steps, 1), "launches": n // max(a.profile_steps, 1),
                       "tflops": (fl / (ms * 1e-3) / 1e12) if ms > 0 and fl > 0 else None}
     t.timing_enable(0)
-    syrk_key = "syrk32" if prec == H.HDD_FP32_REFINE else "syrk64"
-    peak = PEAK["fp32_mfma"] if syrk_key == "syrk32" else PEAK["fp64_mfma"]
+    # dominant kernel: the 128 x 128-tile float32 Schur update (FP32 path) or
+    # the float64 Schur update (FP64 path); algorithmic flops = 2 K per
+    # lower-triangle output element of every launch
+    syrk_key = "syrk128" if prec == H.HDD_FP32_REFINE else "syrk64"
+    kname = "k_syrk128_f32" if syrk_key == "syrk128" else "k_syrk_mfma_f64"
+    peak = PEAK["fp32_mfma"] if syrk_key == "syrk128" else PEAK["fp64_mfma"]
     ach = kern[syrk_key]["tflops"] or 0.0
-    roofline = {"bound": "mfma", "kernel": f"Schur update (rank-k, {syrk_key})", "achieved": ach, "peak": peak,
+    roofline = {"bound": "mfma", "kernel": kname, "achieved": ach, "peak": peak,
                 "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
-                "per_launch_avg_ms": kern[syrk_key]["ms"] / max(kern[syrk_key]["launches"], 1)}
+                "launches_per_step": kern[syrk_key]["launches"],
+                "avg_launch_ms": kern[syrk_key]["ms"] / max(kern[syrk_key]["launches"], 1)}
     t.close()
     del t
 

@@ -202,8 +202,10 @@ int hdd_debug_frame(hdd_handle h, int32_t sample, int32_t depth, int32_t index, 
 /* Timing of kernel classes with HIP events around every launch of the class
  * on the handle's stream.  kind: 0 Schur update (rank-k, matrix cores) on
  * float32 levels, 1 interface factorization (diagonal + row solves),
- * 2 extend-add, 3 leaf assembly, 4 top-down, 5 forward pass, 6 residual,
- * 7 Schur update on float64 levels.
+ * 2 extend-add, 3 block build (leaf assembly and in-LDS elimination of the
+ * leaf interior), 4 top-down, 5 forward pass, 6 residual, 7 Schur update on
+ * float64 levels, 8 the 128 x 128-tile float32 Schur update kernel (launches
+ * of kind 8 are not counted in kind 0).
  * hdd_timing_enable(h, mask): bit k enables kind k (0 disables and clears).
  * hdd_timing_get: total milliseconds, number of launches and summed
  * algorithmic flops of the timed launches (Schur update: 2 K per lower-

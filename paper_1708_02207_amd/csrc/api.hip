@@ -18,9 +18,10 @@ using hdd::Plan;
 
 namespace {
 
-constexpr int kKinds = 8;
+constexpr int kKinds = 9;
 enum Kind {
-  K_SYRK = 0, K_FACTOR = 1, K_EXTEND = 2, K_ASSEMBLE = 3, K_TOPDOWN = 4, K_FORWARD = 5, K_RESIDUAL = 6, K_SYRK64 = 7
+  K_SYRK = 0, K_FACTOR = 1, K_EXTEND = 2, K_ASSEMBLE = 3, K_TOPDOWN = 4, K_FORWARD = 5, K_RESIDUAL = 6, K_SYRK64 = 7,
+  K_SYRK128 = 8
 };
 
 int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
@@ -569,14 +570,16 @@ int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double
       HDD_TRY(timed(h, K_FACTOR, 0.0, [&] { return hdd::launch_panel(L, k0, kb, n_samples, h->info, h->st); }));
       if (k0 + kb < g) {
         const double fl = h->timing_mask ? syrk_flops(h, d, k0, k0 + kb, k0 + kb, k0 + kb, g) : 0.0;
-        HDD_TRY(timed(h, syrk_kind, fl, [&] {
+        const int kind = hdd::syrk_uses_big_tile(L, k0, k0 + kb, k0 + kb, k0 + kb, g, mfma) ? K_SYRK128 : syrk_kind;
+        HDD_TRY(timed(h, kind, fl, [&] {
           return hdd::launch_syrk(L, k0, k0 + kb, k0 + kb, k0 + kb, g, n_samples, mfma, h->st);
         }));
       }
     }
     if (L.max_U > g) {  // Schur update of Gamma (and the boundary load row)
       const double fl = h->timing_mask ? syrk_flops(h, d, 0, g, g, g, -1) : 0.0;
-      HDD_TRY(timed(h, syrk_kind, fl, [&] { return hdd::launch_syrk(L, 0, g, g, g, -1, n_samples, mfma, h->st); }));
+      const int kind = hdd::syrk_uses_big_tile(L, 0, g, g, g, -1, mfma) ? K_SYRK128 : syrk_kind;
+      HDD_TRY(timed(h, kind, fl, [&] { return hdd::launch_syrk(L, 0, g, g, g, -1, n_samples, mfma, h->st); }));
     }
     return HDD_OK;
   };

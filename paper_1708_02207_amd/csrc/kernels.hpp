@@ -14,6 +14,7 @@ hipError_t launch_extend_add(const DevLevel& F, const DevLevel& S, int n_samples
 hipError_t launch_panel(const DevLevel& L, int k0, int kb, int n_samples, int* info, hipStream_t st);
 hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, int n_samples, bool mfma,
                        hipStream_t st);
+bool syrk_uses_big_tile(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, bool mfma);
 
 // Blocks (in-LDS nested dissection of the leaf interior)
 size_t block_build_lds(const DevBlocks& B, bool dbl);

@@ -453,6 +453,14 @@ hipError_t launch_panel(const DevLevel& L, int k0, int kb, int n_samples, int* i
   return hipGetLastError();
 }
 
+// Large frames (16-byte aligned rows) with enough work per tile use the
+// 128 x 128 matrix-core tile.
+bool syrk_uses_big_tile(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, bool mfma) {
+  const int rows = L.max_U + 1 - r0;
+  const int cols = (c1 < 0 ? L.max_U + 1 : c1) - c0;
+  return mfma && !L.is_double && k1 > k0 && rows >= 192 && cols >= 128 && (k0 % 4) == 0 && L.max_U + 1 >= 64;
+}
+
 hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, int n_samples, bool mfma,
                        hipStream_t st) {
   if (k1 <= k0) return hipSuccess;
@@ -460,9 +468,7 @@ hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1
   const int rows = L.max_U + 1 - r0;
   const int cols = (c1 < 0 ? L.max_U + 1 : c1) - c0;
   if (rows <= 0 || cols <= 0) return hipSuccess;
-  // Large frames (16-byte aligned rows) with enough work per tile use the
-  // 128 x 128 matrix-core tile.
-  const bool big = mfma && !L.is_double && rows >= 192 && cols >= 128 && (k0 % 4) == 0 && L.max_U + 1 >= 64;
+  const bool big = syrk_uses_big_tile(L, k0, k1, r0, c0, c1, mfma);
   const int TM = big ? 128 : 64;
   const int tr = ceil_div(rows, TM);
   a.tiles_c = ceil_div(cols, TM);
