@@ -139,7 +139,7 @@ def main():
         err = max(errs) if errs else None
 
     # per-kernel event timing over extra profiled steps
-    t.timing_enable(0xFF)
+    t.timing_enable((1 << len(KIND)) - 1)
     for _ in range(a.profile_steps):
         step()
     kern = {}

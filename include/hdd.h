@@ -73,7 +73,11 @@ typedef struct hdd_opts {
   int32_t fp64_top_levels; /* HDD_FP32_REFINE: levels (from the root) kept in float64; default 2 */
   int32_t max_refine;      /* refinement sweeps allowed (HDD_FP32_REFINE default 6; HDD_FP64 default 0) */
   int32_t flags;           /* HDD_FLAG_* */
-  double refine_tol;       /* stop when max|du| <= refine_tol * max|u| (default 1e-10) */
+  double refine_tol;       /* stop once the predicted relative error of the field,
+                              c r / (1 - r) with c = max|du| / max|u| of the last
+                              sweep and r = c / (c of the sweep before), is
+                              <= refine_tol for every sample (so at least two
+                              sweeps; r >= 1/2 never stops; default 1e-9) */
   int32_t reserved[8];     /* must be zero */
 } hdd_opts;
 
@@ -154,7 +158,8 @@ int hdd_solve_full(hdd_handle h);
  * hdd_solve_full. */
 int hdd_get_solution(hdd_handle h, int32_t sample, double* u_out, int32_t mem);
 
-/* Last refinement correction max|du| / max|u| per sample (0 if none ran):
+/* Last refinement correction max|du| / max|u| per sample (0 if none ran); it
+ * bounds the error left after the sweep before it:
  * rel_est host float64 [n_samples]; *sweeps = refinement sweeps done. */
 int hdd_error_estimate(hdd_handle h, double* rel_est, int32_t* sweeps);
 

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <string>
 #include <vector>
@@ -252,6 +253,7 @@ int ensure_full(hdd_tree* h) {
   const int nc = h->plan.nc;
   const int ns = h->n_samples;
   std::vector<unsigned long long> mb(2 * ns);
+  std::vector<double> prev(ns, 0.0);
   bool converged = false;
   for (int it = 0; it < max_it; ++it) {
     h->cur_level = -1;
@@ -269,13 +271,27 @@ int ensure_full(hdd_tree* h) {
     HIP_TRY(hipMemcpyAsync(mb.data(), h->maxbits, sizeof(unsigned long long) * 2 * ns, hipMemcpyDeviceToHost, h->st));
     HIP_TRY(hipStreamSynchronize(h->st));
     h->sweeps = it + 1;
+    // Stopping test on the predicted error of the refined field: for a
+    // linearly convergent correction sequence with contraction r the error
+    // left after a correction of size c is at most c r / (1 - r); r is the
+    // observed ratio of the last two corrections.  A sample whose ratio is
+    // not below 1/2 (or that has only one correction) does not stop.
     double worst = 0.0;
     for (int s = 0; s < ns; ++s) {
       double md, mu;
       std::memcpy(&md, &mb[2 * s], 8);
       std::memcpy(&mu, &mb[2 * s + 1], 8);
-      h->est[s] = mu > 0 ? md / mu : md;
-      worst = std::max(worst, h->est[s]);
+      const double c = mu > 0 ? md / mu : md;
+      double pred = std::numeric_limits<double>::infinity();
+      if (c == 0.0) {
+        pred = 0.0;
+      } else if (it > 0 && prev[s] > 0.0) {
+        const double r = c / prev[s];
+        if (r < 0.5) pred = c * r / (1.0 - r);
+      }
+      h->est[s] = c;
+      prev[s] = c;
+      worst = std::max(worst, pred);
     }
     if (worst <= h->opt.refine_tol) {
       converged = true;
@@ -363,7 +379,7 @@ int hdd_default_opts(int32_t n, int32_t precision, hdd_opts* o) {
   o->precision = precision;
   o->fp64_top_levels = 2;
   o->max_refine = precision == HDD_FP32_REFINE ? 6 : 0;
-  o->refine_tol = 1e-10;
+  o->refine_tol = 1e-9;
   return validate_opts(o);
 }
 

@@ -265,40 +265,86 @@ __global__ void __launch_bounds__(NTB) k_block_build(DevBlocks B, int n_samples,
 }
 
 // ---------------------------------------------------------------------------
+// Shared pieces of the block solves.
+//
+// Staging of a block's compact factors into LDS with 16-byte loads (the
+// per-block store is a multiple of 16 bytes whenever cst_size * sizeof(T) is).
+template <typename T>
+__device__ __forceinline__ void stage_factors(T* dst, const T* src, int n_elems) {
+  const int bytes = n_elems * int(sizeof(T));
+  if ((bytes & 15) == 0 && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
+    const uint4* s4 = reinterpret_cast<const uint4*>(src);
+    uint4* d4 = reinterpret_cast<uint4*>(dst);
+    for (int e = threadIdx.x; e < bytes / 16; e += NT) d4[e] = s4[e];
+  } else {
+    for (int e = threadIdx.x; e < n_elems; e += NT) dst[e] = src[e];
+  }
+}
+
+// Lanes per dot product of a level's GEMV: the largest power of two (at most
+// 16) such that n * gam * P threads fit in the workgroup.
+constexpr int gemv_split(int work) {
+  int p = 1;
+  while (p < 16 && work * p * 2 <= NT) p *= 2;
+  return p;
+}
+
+// The triangular solves of a level run one node per group of gam lanes,
+// floor(64 / gam) groups per wave, with the pivot values broadcast by shuffles.
+template <int G> struct Groups {
+  static constexpr int per_wave = 64 / G;
+};
+
+// ---------------------------------------------------------------------------
 // Top-down: the block's compact factors are staged in LDS, u on the block's
 // (S+1)^2 nodes lives in LDS; levels are solved root first.
 template <typename T, int S, int K>
 __device__ __forceinline__ void topdown_level(const DevBlocks& B, const T* cst, const double* vz, double* uL,
                                               double* rb, int* idx) {
   using L = Lv<S, K>;
-  constexpr int g = L::gam, U = L::U;
+  constexpr int g = L::gam, U = L::U, nbd = L::bnd;
+  constexpr int P = gemv_split(L::n * g);
+  static_assert(L::n * g * P <= NT, "level GEMV does not fit the workgroup");
   const int tid = threadIdx.x;
   const T* base = cst + B.lv[K].cst_off;
   stage_ints(idx, B.lids + B.lv[K].lid_off, L::n * U);
   __syncthreads();
   const int* lids = idx;
-  for (int e = tid; e < L::n * g; e += NT) {
-    const int t = e / g, i = e % g;
+  // rb = z - P^T u_Gamma: P lanes per entry, reduced by shuffles (the P lanes
+  // of an entry are consecutive and P divides 64, so they share a wave)
+  if (tid < L::n * g * P) {
+    const int w = tid / P, p = tid % P;
+    const int t = w / g, i = w % g;
     const T* blk = base + t * L::per;
     const int* lid = lids + t * U;
-    double acc = vz ? vz[B.lv[K].vec_off + e] : double(blk[U * g + i]);
+    double acc = 0.0;
 #pragma unroll
-    for (int j = 0; j < L::bnd; ++j) acc -= double(blk[(g + j) * g + i]) * uL[lid[g + j]];
-    rb[e] = acc;
+    for (int j = p; j < nbd; j += P) acc += double(blk[(g + j) * g + i]) * uL[lid[g + j]];
+#pragma unroll
+    for (int o = P / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (p == 0) rb[w] = (vz ? vz[B.lv[K].vec_off + w] : double(blk[U * g + i])) - acc;
   }
   __syncthreads();
-  for (int t = tid; t < L::n; t += NT) {
-    const T* blk = base + t * L::per;
-    const int* lid = lids + t * U;
-    double* x = rb + t * g;
+  // back substitution L^T x = rb, one node per group of g lanes
+  {
+    constexpr int GPW = Groups<g>::per_wave;
+    constexpr int NW = (L::n + GPW - 1) / GPW;
+    static_assert(NW * 64 <= NT, "level solve does not fit the workgroup");
+    const int wv = tid >> 6, lane = tid & 63;
+    const int grp = lane / g, i = lane % g;
+    const int t = wv * GPW + grp;
+    const bool act = grp < GPW && t < L::n;
+    if (wv < NW) {
+      const T* blk = base + (act ? t : 0) * L::per;
+      const int gb = grp * g;
+      double v = act ? rb[t * g + i] : 0.0;
 #pragma unroll
-    for (int i = g - 1; i >= 0; --i) {
-      double v = x[i];
-#pragma unroll
-      for (int l = i + 1; l < g; ++l) v -= double(blk[l * g + i]) * x[l];
-      v /= double(blk[i * g + i]);
-      x[i] = v;
-      uL[lid[i]] = v;
+      for (int l = g - 1; l >= 0; --l) {
+        const double xl = __shfl(v, gb + l) / double(blk[l * g + l]);
+        if (i == l) v = xl;
+        else if (i < l) v -= double(blk[l * g + i]) * xl;
+      }
+      if (act) uL[lids[t * U + i]] = v;
     }
   }
   __syncthreads();
@@ -326,8 +372,7 @@ __global__ void __launch_bounds__(NT) k_block_topdown(DevBlocks B, const int* __
   const int X0 = B.origin[2 * q], Y0 = B.origin[2 * q + 1];
   const int tid = threadIdx.x;
   double* us = u + (long long)s * ustride;
-  const T* cst = cst_block<T>(B, q, s);
-  for (int e = tid; e < B.cst_size; e += NT) cs[e] = cst[e];
+  stage_factors<T>(cs, cst_block<T>(B, q, s), B.cst_size);
   for (int e = tid; e < S1 * S1; e += NT) uL[e] = us[(long long)(Y0 + e / S1) * (nc + 1) + X0 + e % S1];
   __syncthreads();
   const double* vz = from_vec ? B.vec + (long long)s * B.vec_stride + (long long)q * B.vec_size : nullptr;
@@ -364,16 +409,29 @@ __device__ __forceinline__ void forward_level(const DevBlocks& B, const T* cst, 
     __syncthreads();
   }
   const T* base = cst + B.lv[K].cst_off;
-  for (int t = tid; t < L::n; t += NT) {  // z = L^-1 g_gamma
-    const T* blk = base + t * L::per;
-    double* x = cur + t * U;
+  // z = L^-1 g_gamma, one node per group of g lanes
+  {
+    constexpr int GPW = Groups<g>::per_wave;
+    constexpr int NW = (L::n + GPW - 1) / GPW;
+    static_assert(NW * 64 <= NT, "level solve does not fit the workgroup");
+    const int wv = tid >> 6, lane = tid & 63;
+    const int grp = lane / g, i = lane % g;
+    const int t = wv * GPW + grp;
+    const bool act = grp < GPW && t < L::n;
+    if (wv < NW) {
+      const T* blk = base + (act ? t : 0) * L::per;
+      const int gb = grp * g;
+      double v = act ? cur[t * U + i] : 0.0;
 #pragma unroll
-    for (int i = 0; i < g; ++i) {
-      double v = x[i];
-#pragma unroll
-      for (int l = 0; l < i; ++l) v -= double(blk[i * g + l]) * x[l];
-      x[i] = v / double(blk[i * g + i]);
-      vz[B.lv[K].vec_off + t * g + i] = x[i];
+      for (int l = 0; l < g; ++l) {
+        const double xl = __shfl(v, gb + l) / double(blk[l * g + l]);
+        if (i == l) v = xl;
+        else if (i > l) v -= double(blk[i * g + l]) * xl;
+      }
+      if (act) {
+        cur[t * U + i] = v;
+        vz[B.lv[K].vec_off + t * g + i] = v;
+      }
     }
   }
   __syncthreads();
@@ -411,8 +469,7 @@ __global__ void __launch_bounds__(NT) k_block_forward(DevBlocks B, int n_samples
   const int s = blockIdx.x % n_samples;
   const int X0 = B.origin[2 * q], Y0 = B.origin[2 * q + 1];
   const int tid = threadIdx.x;
-  const T* cst = cst_block<T>(B, q, s);
-  for (int e = tid; e < B.cst_size; e += NT) cs[e] = cst[e];
+  stage_factors<T>(cs, cst_block<T>(B, q, s), B.cst_size);
   double* vz = B.vec + (long long)s * B.vec_stride + (long long)q * B.vec_size;
   const double* rs = res + (long long)s * rstride;
   // micro-blocks: node (i, j) of the residual belongs to the micro-block that

@@ -160,8 +160,13 @@ template <> struct SyrkCfg<double> { static constexpr int KC = 16; };
 struct SyrkArgs {
   int k0, k1, r0, c0, c1;
   int tiles_c;  // number of tile columns
+  int tiles_r;  // number of tile rows
 };
 
+// One K chunk of the A rows (rowA0..) and B rows (rowB0..) into LDS.  Rows
+// past U are clamped to U (they only feed outputs that are never stored);
+// columns past k1 read a clamped address and are replaced by zero, so the
+// loads carry no branches.
 template <typename T>
 __device__ __forceinline__ void syrk_load_chunk(T (*As)[SyrkCfg<T>::KC + 1], T (*Bs)[SyrkCfg<T>::KC + 1],
                                                 const T* F, int ld, int U, int rowA0, int rowB0, int kbeg,
@@ -171,19 +176,39 @@ __device__ __forceinline__ void syrk_load_chunk(T (*As)[SyrkCfg<T>::KC + 1], T (
   const int tid = threadIdx.x;
   const int row = tid / (KC / PER);
   const int col0 = (tid % (KC / PER)) * PER;
-  const int ra = rowA0 + row, rb = rowB0 + row;
+  const T* pa = F + (long long)min(rowA0 + row, U) * ld;
+  const T* pb = F + (long long)min(rowB0 + row, U) * ld;
+  T va[PER], vb[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int k = kbeg + col0 + q;
-    const bool kin = k < k1;
-    As[row][col0 + q] = (kin && ra <= U) ? F[(long long)ra * ld + k] : T(0);
-    Bs[row][col0 + q] = (kin && rb <= U) ? F[(long long)rb * ld + k] : T(0);
+    const int kc = min(k, k1 - 1);
+    va[q] = pa[kc];
+    vb[q] = pb[kc];
   }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const bool kin = kbeg + col0 + q < k1;
+    As[row][col0 + q] = kin ? va[q] : T(0);
+    Bs[row][col0 + q] = kin ? vb[q] : T(0);
+  }
+}
+
+// Output element (i, j) of the update belongs to this call's region.
+__device__ __forceinline__ bool syrk_in(int U, int i, int j, const SyrkArgs& a, int c1e) {
+  return i <= U && i >= a.r0 && j >= a.c0 && j < c1e && j <= i;
 }
 
 template <typename T>
 __device__ __forceinline__ void syrk_store(T* F, int ld, int U, int i, int j, const SyrkArgs& a, int c1e, T v) {
-  if (i <= U && i >= a.r0 && j >= a.c0 && j < c1e && j <= i) F[(long long)i * ld + j] -= v;
+  if (syrk_in(U, i, j, a, c1e)) F[(long long)i * ld + j] -= v;
+}
+
+// Current value at (i, j) read through an address clamped into the frame,
+// so that all reads of a tile can be issued before any store.
+template <typename T>
+__device__ __forceinline__ T syrk_old(const T* F, int ld, int U, int i, int j) {
+  return F[(long long)min(i, U) * ld + min(j, U)];
 }
 
 __global__ void __launch_bounds__(256) k_syrk_mfma_f32(DevLevel L, SyrkArgs a, int n_samples) {
@@ -216,11 +241,18 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f32(DevLevel L, SyrkArgs a, i
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
     }
   }
+  float old[16];
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int i = i0 + wr * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
     const int j = j0 + wc * 32 + (lane & 31);
-    syrk_store<float>(F, ld, U, i, j, a, c1e, acc[v]);
+    old[v] = syrk_old(F, ld, U, i, j);
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int i = i0 + wr * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+    const int j = j0 + wc * 32 + (lane & 31);
+    if (syrk_in(U, i, j, a, c1e)) F[(long long)i * ld + j] = old[v] - acc[v];
   }
 }
 
@@ -264,6 +296,7 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
         for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
     }
   }
+  double old[2][2][4];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -272,7 +305,17 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
       for (int v = 0; v < 4; ++v) {
         const int i = i0 + wr * 32 + x * 16 + 4 * v + (lane >> 4);  // f64 16x16x4: row 4v + lane/16
         const int j = j0 + wc * 32 + y * 16 + (lane & 15);
-        syrk_store<double>(F, ld, U, i, j, a, c1e, acc[x][y][v]);
+        old[x][y][v] = syrk_old(F, ld, U, i, j);
+      }
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wr * 32 + x * 16 + 4 * v + (lane >> 4);
+        const int j = j0 + wc * 32 + y * 16 + (lane & 15);
+        if (syrk_in(U, i, j, a, c1e)) F[(long long)i * ld + j] = old[x][y][v] - acc[x][y][v];
       }
 }
 
@@ -285,43 +328,56 @@ __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int
   constexpr int KC = 32, TM = 128;
   __shared__ float As[TM][KC + 1];
   __shared__ float Bs[TM][KC + 1];
-  const int pair = blockIdx.x;
+  // XCD-aware order: workgroup b runs on XCD b % 8; all tiles of one (node,
+  // sample) frame go to the same XCD in consecutive order, so its panel
+  // columns stay in that XCD's L2 while its tiles are computed.
+  const int n_pairs = L.n_nodes * n_samples;
+  const int n_tiles = a.tiles_r * a.tiles_c;
+  const int b = blockIdx.x;
+  const int loc = b >> 3;
+  const int pair = (loc / n_tiles) * 8 + (b & 7);
+  if (pair >= n_pairs) return;
+  const int tile = loc % n_tiles;
   const int node = pair / n_samples, s = pair % n_samples;
   const DevNode nd = L.nodes[node];
   const int U = nd.U;
   const int c1e = a.c1 < 0 ? U + 1 : a.c1;
-  const int ti = blockIdx.y / a.tiles_c, tj = blockIdx.y % a.tiles_c;
+  const int ti = tile / a.tiles_c, tj = tile % a.tiles_c;
   const int i0 = a.r0 + ti * TM, j0 = a.c0 + tj * TM;
   if (i0 > U || j0 >= c1e || i0 + TM - 1 < j0) return;
   float* F = frame_ptr<float>(L, node, s);
   const int ld = nd.ld;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;
-  // loader mapping: thread -> (row lr, 16 consecutive k) for A and B
+  // loader mapping: thread -> (row lr, 16 consecutive k) for A and B.  Rows
+  // past U are clamped to U: they only feed outputs that are never stored.
   const int lr = tid >> 1, lk = (tid & 1) * 16;
-  const int ra = i0 + lr, rb = j0 + lr;
-  const bool vec4 = (ld % 4) == 0;  // 16-byte aligned rows
+  const float* rowA = F + (long long)min(i0 + lr, U) * ld;
+  const float* rowB = F + (long long)min(j0 + lr, U) * ld;
+  const bool vec4 = (ld % 4) == 0;  // 16-byte aligned rows (k0 % 4 == 0)
   float4 pa[4], pb[4];
   auto load = [&](int kb) {
+    if (vec4 && kb + KC <= a.k1) {  // uniform: a whole chunk inside [k0, k1)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = kb + lk + 4 * q;
-      float4 va = make_float4(0.f, 0.f, 0.f, 0.f), vb = va;
-      if (vec4 && k + 3 < a.k1) {
-        if (ra <= U) va = *reinterpret_cast<const float4*>(F + (long long)ra * ld + k);
-        if (rb <= U) vb = *reinterpret_cast<const float4*>(F + (long long)rb * ld + k);
-      } else {
-        float ta[4] = {0.f, 0.f, 0.f, 0.f}, tb[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int x = 0; x < 4; ++x)
-          if (k + x < a.k1) {
-            if (ra <= U) ta[x] = F[(long long)ra * ld + k + x];
-            if (rb <= U) tb[x] = F[(long long)rb * ld + k + x];
-          }
-        va = make_float4(ta[0], ta[1], ta[2], ta[3]);
-        vb = make_float4(tb[0], tb[1], tb[2], tb[3]);
+      for (int q = 0; q < 4; ++q) {
+        pa[q] = *reinterpret_cast<const float4*>(rowA + kb + lk + 4 * q);
+        pb[q] = *reinterpret_cast<const float4*>(rowB + kb + lk + 4 * q);
       }
-      pa[q] = va;
-      pb[q] = vb;
+    } else {  // ragged tail: clamped addresses, out-of-range k selected to 0
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float ta[4], tb[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+          const int k = kb + lk + 4 * q + x;
+          const int kc = min(k, a.k1 - 1);
+          const float va = rowA[kc], vb = rowB[kc];
+          ta[x] = k < a.k1 ? va : 0.f;
+          tb[x] = k < a.k1 ? vb : 0.f;
+        }
+        pa[q] = make_float4(ta[0], ta[1], ta[2], ta[3]);
+        pb[q] = make_float4(tb[0], tb[1], tb[2], tb[3]);
+      }
     }
   };
   auto store = [&]() {
@@ -364,16 +420,22 @@ __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int
       __syncthreads();
     }
   }
+  // one 32 x 32 accumulator at a time: its 16 reads are issued together
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
+    for (int y = 0; y < 2; ++y) {
+      const int ib = i0 + wr * 64 + x * 32 + (lane >> 5) * 4;
+      const int j = j0 + wc * 64 + y * 32 + (lane & 31);
+      float old[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) old[v] = syrk_old(F, ld, U, ib + (v >> 2) * 8 + (v & 3), j);
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int i = i0 + wr * 64 + x * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-        const int j = j0 + wc * 64 + y * 32 + (lane & 31);
-        syrk_store<float>(F, ld, U, i, j, a, c1e, acc[x][y][v]);
+        const int i = ib + (v >> 2) * 8 + (v & 3);
+        if (syrk_in(U, i, j, a, c1e)) F[(long long)i * ld + j] = old[v] - acc[x][y][v];
       }
+    }
 }
 
 // Plain FMA version of the same update (no matrix cores), kept as a
@@ -464,7 +526,7 @@ bool syrk_uses_big_tile(const DevLevel& L, int k0, int k1, int r0, int c0, int c
 hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, int n_samples, bool mfma,
                        hipStream_t st) {
   if (k1 <= k0) return hipSuccess;
-  SyrkArgs a{k0, k1, r0, c0, c1, 0};
+  SyrkArgs a{k0, k1, r0, c0, c1, 0, 0};
   const int rows = L.max_U + 1 - r0;
   const int cols = (c1 < 0 ? L.max_U + 1 : c1) - c0;
   if (rows <= 0 || cols <= 0) return hipSuccess;
@@ -472,9 +534,13 @@ hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1
   const int TM = big ? 128 : 64;
   const int tr = ceil_div(rows, TM);
   a.tiles_c = ceil_div(cols, TM);
+  a.tiles_r = tr;
   dim3 grid(L.n_nodes * n_samples, tr * a.tiles_c), block(256);
   if (big) {
-    hipLaunchKernelGGL(k_syrk128_f32, grid, block, 0, st, L, a, n_samples);
+    const long long pairs8 = (long long)ceil_div(L.n_nodes * n_samples, 8) * 8;
+    const long long nwg = pairs8 * tr * a.tiles_c;
+    if (nwg > 0x7fffffffll) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_syrk128_f32, dim3(unsigned(nwg)), block, 0, st, L, a, n_samples);
     return hipGetLastError();
   }
   if (L.is_double) {

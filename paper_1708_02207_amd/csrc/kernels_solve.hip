@@ -20,14 +20,125 @@ template <typename T> __device__ __forceinline__ double ldd(const T* p) { return
 
 // ---------------------------------------------------------------------------
 // Shared pieces of the per-node solves.  Dynamic LDS layout (doubles):
-//   v[U] (work vector), part[NW * gam] (GEMV partial sums), LD[nb][nb+1]
-// with nb = min(64, gam) the diagonal block of the triangular solves.
+//   v[U+1] (work vector), part[...] (GEMV partial sums).  The triangular
+// solves go in diagonal blocks of nb = min(64, gam) rows.
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int solve_nb(int g) { return g < 64 ? g : 64; }
 
+// Lanes that share one row of a wave-level dot product: the columns of a row
+// are spread over `lanes_for(n)` consecutive lanes (a power of two, at most
+// 64), so a wave covers 64 / lanes_for(n) rows per step.
+__host__ __device__ inline int lanes_for(int n) {
+  int p = 1;
+  while (p < n && p < 64) p <<= 1;
+  return p;
+}
+
+// Partial sums of the transposed GEMV: one row of g per lane group.
+__host__ __device__ inline int solve_part(int g, int bs) { return g < 64 ? bs : (bs / 64) * g; }
+
 size_t solve_lds(int max_U, int gam, int bs) {
-  const int nb = solve_nb(gam);
-  return sizeof(double) * (size_t(max_U + 1) + size_t(bs / 64) * gam + size_t(nb) * (nb + 1));
+  return sizeof(double) * (size_t(max_U + 1) + size_t(solve_part(gam, bs)));
+}
+
+// Value of lane l (wave-uniform l) in every lane, through the scalar unit.
+__device__ __forceinline__ double bcast(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Diagonal-block solves by one wave, nb <= 64 rows, in chunks of 16 rows
+// held in registers (one column, resp. row, of the chunk per lane) so that
+// the only serial dependency is the broadcast of each solved entry.
+//   back:    L^T x = v  (lane i holds column i: c[q] = L[j0 + q][i], j >= i)
+//   forward: L z = v    (lane i holds row i:    c[q] = L[i][j0 + q], j <= i)
+template <typename T>
+__device__ __forceinline__ double diag_back(const T* D, int ld, int nb, double v) {
+  const int lane = threadIdx.x & 63;
+  for (int j0 = ((nb - 1) >> 4) << 4; j0 >= 0; j0 -= 16) {
+    T c[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int j = j0 + q;
+      c[q] = (j < nb && lane <= j) ? D[(long long)j * ld + lane] : T(0);
+    }
+#pragma unroll
+    for (int q = 15; q >= 0; --q) {
+      const int j = j0 + q;
+      if (j < nb) {
+        const double xj = bcast(v / double(c[q]), j);
+        if (lane == j) v = xj;
+        else if (lane < j) v -= double(c[q]) * xj;
+      }
+    }
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ double diag_forward(const T* D, int ld, int nb, double v) {
+  const int lane = threadIdx.x & 63;
+  for (int j0 = 0; j0 < nb; j0 += 16) {
+    T c[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int j = j0 + q;
+      c[q] = (lane < nb && j <= lane) ? D[(long long)lane * ld + j] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int j = j0 + q;
+      if (j < nb) {
+        const double zj = bcast(v / double(c[q]), j);
+        if (lane == j) v = zj;
+        else if (lane > j) v -= double(c[q]) * zj;
+      }
+    }
+  }
+  return v;
+}
+
+// y_r = sum_c F[r][c0 + c] x[c] for rows r0 <= r < r1 and 0 <= c < nc (F row
+// major with stride ld), by all waves of the workgroup: the columns of a row
+// are read by consecutive lanes (coalesced), reduced with shuffles, and
+// fn(r, y_r) is called by the first lane of the row.  RB row steps are
+// loaded before any reduction so that many loads are in flight.
+template <typename T, int BS, typename Fn>
+__device__ __forceinline__ void rows_dot(const T* F, int ld, int r0, int r1, int c0, int nc, const double* x, Fn&& fn) {
+  constexpr int NW = BS / 64;
+  constexpr int RB = 16;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int gp = lanes_for(nc);
+  const int rpi = 64 / gp;
+  const int sub = lane / gp, c = lane % gp;
+  const int step = NW * rpi;
+  for (int rb = r0 + wv * rpi; rb < r1; rb += step * RB) {  // uniform within a wave
+    double acc[RB];
+#pragma unroll
+    for (int q = 0; q < RB; ++q) acc[q] = 0.0;
+    for (int cb = 0; cb < nc; cb += gp) {
+      const int cc = cb + c;
+      const bool cok = cc < nc;
+      T v[RB];
+#pragma unroll
+      for (int q = 0; q < RB; ++q) {
+        const int r = rb + q * step + sub;
+        v[q] = (cok && r < r1) ? F[(long long)r * ld + c0 + cc] : T(0);
+      }
+      const double xv = cok ? x[cc] : 0.0;
+#pragma unroll
+      for (int q = 0; q < RB; ++q) acc[q] += double(v[q]) * xv;
+    }
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+      double v = acc[q];
+      for (int o = gp >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      const int r = rb + q * step + sub;
+      if (c == 0 && r < r1) fn(r, v);
+    }
+  }
 }
 
 // Top-down solve of the nodes in `list` (indices within the level) for all
@@ -46,7 +157,6 @@ __global__ void __launch_bounds__(BS) k_topdown(DevLevel L, const int* __restric
   double* r = dyn;                 // [g]
   double* ub = dyn + g;            // [G]
   double* part = dyn + (L.max_U + 1);
-  double* LD = part + NW * g;      // [nbm][nbm+1]
   const T* F = frame_ptr<T>(L, node, s);
   const int* ids = L.ids + nd.ids_off;
   double* us = u + (long long)s * ustride;
@@ -55,19 +165,26 @@ __global__ void __launch_bounds__(BS) k_topdown(DevLevel L, const int* __restric
   for (int i = tid; i < g; i += BS) r[i] = z_from_vec ? vz[i] : ldd(F + (long long)U * ld + i);
   for (int j = tid; j < G; j += BS) ub[j] = us[ids[g + j]];
   __syncthreads();
-  // r -= P^T u_Gamma, P[j][i] = F[(g + j) * ld + i]; lanes over i, waves over j
+  // r -= P^T u_Gamma, P[j][i] = F[(g + j) * ld + i]: a group of gp lanes
+  // covers consecutive i, the 64 / gp groups of a wave and the waves split j
   if (G > 0) {
-    for (int i = lane; i < g; i += 64) {
-      double acc = 0.0;
-      const T* col = F + (long long)g * ld + i;
-#pragma unroll 8
-      for (int j = wv; j < G; j += NW) acc += ldd(col + (long long)j * ld) * ub[j];
-      part[wv * g + i] = acc;
+    const int gp = lanes_for(g);
+    const int rpw = 64 / gp;
+    const int jg = wv * rpw + lane / gp, JG = NW * rpw;
+    for (int i0 = 0; i0 < g; i0 += gp) {
+      const int i = i0 + lane % gp;
+      if (i < g) {
+        double acc = 0.0;
+        const T* col = F + (long long)g * ld + i;
+#pragma unroll 16
+        for (int j = jg; j < G; j += JG) acc += ldd(col + (long long)j * ld) * ub[j];
+        part[jg * g + i] = acc;
+      }
     }
     __syncthreads();
     for (int i = tid; i < g; i += BS) {
       double acc = 0.0;
-      for (int w = 0; w < NW; ++w) acc += part[w * g + i];
+      for (int w = 0; w < JG; ++w) acc += part[w * g + i];
       r[i] -= acc;
     }
     __syncthreads();
@@ -76,18 +193,8 @@ __global__ void __launch_bounds__(BS) k_topdown(DevLevel L, const int* __restric
   for (int b1 = g; b1 > 0; b1 -= nbm) {
     const int b0 = b1 > nbm ? b1 - nbm : 0;
     const int nb = b1 - b0;
-    for (int q = tid; q < nb * nb; q += BS) {
-      const int i = q / nb, j = q % nb;
-      LD[i * (nbm + 1) + j] = (j <= i) ? ldd(F + (long long)(b0 + i) * ld + (b0 + j)) : 0.0;
-    }
-    __syncthreads();
     if (tid < 64) {
-      double v = tid < nb ? r[b0 + tid] : 0.0;
-      for (int jj = nb - 1; jj >= 0; --jj) {
-        const double xj = __shfl(v, jj) / LD[jj * (nbm + 1) + jj];
-        if (tid == jj) v = xj;
-        else if (tid < jj) v -= LD[jj * (nbm + 1) + tid] * xj;
-      }
+      const double v = diag_back<T>(F + (long long)b0 * ld + b0, ld, nb, tid < nb ? r[b0 + tid] : 0.0);
       if (tid < nb) r[b0 + tid] = v;
     }
     __syncthreads();
@@ -112,7 +219,6 @@ __global__ void __launch_bounds__(BS) k_topdown(DevLevel L, const int* __restric
 template <typename T, int BS>
 __global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int n_samples) {
   extern __shared__ double dyn[];
-  constexpr int NW = BS / 64;
   const int e = blockIdx.x;
   const int node = e / n_samples;
   const int s = e % n_samples;
@@ -120,7 +226,6 @@ __global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int n_sa
   const int g = L.gam, G = nd.bnd, U = nd.U, ld = nd.ld;
   const int nbm = solve_nb(g);
   double* gt = dyn;  // [U]
-  double* LD = dyn + (L.max_U + 1) + NW * g;
   const T* F = frame_ptr<T>(L, node, s);
   const int tid = threadIdx.x;
   {
@@ -142,41 +247,19 @@ __global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int n_sa
   for (int b0 = 0; b0 < g; b0 += nbm) {
     const int b1 = b0 + nbm < g ? b0 + nbm : g;
     const int nb = b1 - b0;
-    for (int q = tid; q < nb * nb; q += BS) {
-      const int i = q / nb, j = q % nb;
-      LD[i * (nbm + 1) + j] = (j <= i) ? ldd(F + (long long)(b0 + i) * ld + (b0 + j)) : 0.0;
-    }
-    __syncthreads();
     if (tid < 64) {
-      double v = tid < nb ? gt[b0 + tid] : 0.0;
-      for (int jj = 0; jj < nb; ++jj) {
-        const double zj = __shfl(v, jj) / LD[jj * (nbm + 1) + jj];
-        if (tid == jj) v = zj;
-        else if (tid > jj) v -= LD[tid * (nbm + 1) + jj] * zj;
-      }
+      const double v = diag_forward<T>(F + (long long)b0 * ld + b0, ld, nb, tid < nb ? gt[b0 + tid] : 0.0);
       if (tid < nb) gt[b0 + tid] = v;
     }
     __syncthreads();
-    if (b1 < g) {
-      for (int i = b1 + tid; i < g; i += BS) {  // rows below: one thread per row
-        double acc = 0.0;
-        const T* row = F + (long long)i * ld + b0;
-#pragma unroll 16
-        for (int k = 0; k < nb; ++k) acc += ldd(row + k) * gt[b0 + k];
-        gt[i] -= acc;
-      }
+    if (b1 < g) {  // rows below the block: gt[i] -= L[i][b0:b1] z[b0:b1]
+      rows_dot<T, BS>(F, ld, b1, g, b0, nb, gt + b0, [&](int i, double y) { gt[i] -= y; });
       __syncthreads();
     }
   }
-  // g_omega[j] = gt[g + j] - sum_i P[j][i] z_i : one thread per row j
+  // g_omega[j] = gt[g + j] - sum_i P[j][i] z_i
   double* out = L.vec + (long long)s * L.vec_stride + nd.ids_off;
-  for (int j = tid; j < G; j += BS) {
-    double acc = 0.0;
-    const T* row = F + (long long)(g + j) * ld;
-#pragma unroll 16
-    for (int i = 0; i < g; ++i) acc += ldd(row + i) * gt[i];
-    out[g + j] = gt[g + j] - acc;
-  }
+  rows_dot<T, BS>(F, ld, g, g + G, 0, g, gt, [&](int r, double y) { out[r] = gt[r] - y; });
   for (int i = tid; i < g; i += BS) out[i] = gt[i];
 }
 
@@ -242,15 +325,20 @@ __device__ __forceinline__ void atomic_max_abs(unsigned long long* p, double v) 
 
 // u += d and per-sample max |d|, max |u| (as ordered bit patterns of
 // non-negative doubles, so the maximum is exact and order independent).
-__global__ void k_axpy_maxabs(int nc, int n_samples, double* __restrict__ u, const double* __restrict__ d,
-                              unsigned long long* __restrict__ maxbits) {
+// One atomic per workgroup and quantity: the waves reduce through LDS first.
+__global__ void __launch_bounds__(256) k_axpy_maxabs(int nc, int n_samples, double* __restrict__ u,
+                                                     const double* __restrict__ d,
+                                                     unsigned long long* __restrict__ maxbits) {
+  __shared__ double red[2][4];
   const long long nn = (long long)(nc + 1) * (nc + 1);
   const int s = blockIdx.y;
+  double* us = u + (long long)s * nn;
+  const double* ds = d + (long long)s * nn;
   double md = 0.0, mu = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += (long long)gridDim.x * blockDim.x) {
-    const double dv = d[(long long)s * nn + i];
-    const double nv = u[(long long)s * nn + i] + dv;
-    u[(long long)s * nn + i] = nv;
+    const double dv = ds[i];
+    const double nv = us[i] + dv;
+    us[i] = nv;
     md = fmax(md, fabs(dv));
     mu = fmax(mu, fabs(nv));
   }
@@ -259,9 +347,15 @@ __global__ void k_axpy_maxabs(int nc, int n_samples, double* __restrict__ u, con
     md = fmax(md, __shfl_xor(md, o));
     mu = fmax(mu, __shfl_xor(mu, o));
   }
+  const int wv = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    atomic_max_abs(maxbits + 2 * s, md);
-    atomic_max_abs(maxbits + 2 * s + 1, mu);
+    red[0][wv] = md;
+    red[1][wv] = mu;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const double m = fmax(fmax(red[threadIdx.x][0], red[threadIdx.x][1]), fmax(red[threadIdx.x][2], red[threadIdx.x][3]));
+    atomic_max_abs(maxbits + 2 * s + threadIdx.x, m);
   }
 }
 
@@ -440,7 +534,9 @@ hipError_t launch_residual(int nc, int n_samples, const double* kappa, const dou
 hipError_t launch_axpy_maxabs(int nc, int n_samples, double* u, const double* d, unsigned long long* maxbits,
                               hipStream_t st) {
   const long long nn = (long long)(nc + 1) * (nc + 1);
-  dim3 grid(std::max(1, std::min(ceil_div(nn, 256), 1024)), n_samples);
+  // about 16 elements per thread: 4096 / n_samples workgroups per sample at most
+  const int per = std::max(1, std::min(ceil_div(nn, 256 * 16), std::max(16, 4096 / std::max(n_samples, 1))));
+  dim3 grid(per, n_samples);
   hipLaunchKernelGGL(k_axpy_maxabs, grid, dim3(256), 0, st, nc, n_samples, u, d, maxbits);
   return hipGetLastError();
 }
