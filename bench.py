@@ -26,6 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "hbm_gbs": 8000.0}
+# HBM traffic per launch of the roofline kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes (scaled by a plain copy), keyed (kernel, config, batch); empty until
+# counters are taken for the current kernel build.
+TRAFFIC = {}
 KIND = {"syrk32": 0, "factor": 1, "extend": 2, "block_build": 3, "topdown": 4, "forward": 5, "residual": 6,
         "syrk64": 7, "syrk128": 8}
 
@@ -42,7 +46,23 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-steps", type=int, default=1, help="extra steps with per-kernel event timing")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run 3 device-to-device copies of BYTES (calibrates HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_probe(nbytes: int):
+    """Three plain device-to-device copies of nbytes: the reference dispatch
+    for scaling the FETCH_SIZE / WRITE_SIZE counters (reads nbytes, writes
+    nbytes per copy)."""
+    import torch
+
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "copies": 3}), flush=True)
 
 
 def cpu_baseline(w, seconds: float):
@@ -67,6 +87,9 @@ def cpu_baseline(w, seconds: float):
 
 def main():
     a = parse()
+    if a.copy_probe > 0:
+        copy_probe(a.copy_probe)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -144,8 +167,9 @@ def main():
         step()
     kern = {}
     for name, k in KIND.items():
-        ms, n, fl = t.timing_get(k)
-        kern[name] = {"ms": ms / max(a.profile_steps, 1), "launches": n // max(a.profile_steps, 1),
+        ms, n, fl, by = t.timing_get(k, with_bytes=True)
+        ps = max(a.profile_steps, 1)
+        kern[name] = {"ms": ms / ps, "launches": n // ps, "flops": fl / ps, "bytes": by / ps,
                       "tflops": (fl / (ms * 1e-3) / 1e12) if ms > 0 and fl > 0 else None}
     t.timing_enable(0)
     # dominant kernel: the 128 x 128-tile float32 Schur update (FP32 path) or
@@ -155,10 +179,13 @@ def main():
     kname = "k_syrk128_f32" if syrk_key == "syrk128" else "k_syrk_mfma_f64"
     peak = PEAK["fp32_mfma"] if syrk_key == "syrk128" else PEAK["fp64_mfma"]
     ach = kern[syrk_key]["tflops"] or 0.0
+    nl = max(kern[syrk_key]["launches"], 1)
     roofline = {"bound": "mfma", "kernel": kname, "achieved": ach, "peak": peak,
-                "unit": "TFLOP/s", "frac": ach / peak, "traffic": None,
+                "unit": "TFLOP/s", "frac": ach / peak, "traffic": TRAFFIC.get((kname, a.config, a.batch)),
                 "launches_per_step": kern[syrk_key]["launches"],
-                "avg_launch_ms": kern[syrk_key]["ms"] / max(kern[syrk_key]["launches"], 1)}
+                "avg_launch_ms": kern[syrk_key]["ms"] / nl,
+                "algorithmic_flops_per_launch": kern[syrk_key]["flops"] / nl,
+                "algorithmic_bytes_per_launch": kern[syrk_key]["bytes"] / nl}
     t.close()
     del t
 

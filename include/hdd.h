@@ -217,8 +217,12 @@ int hdd_debug_frame(hdd_handle h, int32_t sample, int32_t depth, int32_t index, 
  * triangle output element; 0 for other kinds).  Synchronizes. */
 int hdd_timing_enable(hdd_handle h, int32_t mask);
 int hdd_timing_get(hdd_handle h, int32_t kind, double* ms, int64_t* launches, double* flops);
-/* Same, restricted to launches on tree level `level` (depth; -1: all). */
-int hdd_timing_get_level(hdd_handle h, int32_t kind, int32_t level, double* ms, int64_t* launches, double* flops);
+/* Same, restricted to launches on tree level `level` (depth; -1: all), and
+ * with the summed algorithmic HBM bytes of the launches in *bytes (Schur
+ * update: the panel rows read once plus the output region read and written
+ * once; 0 for other kinds).  Any output pointer may be NULL. */
+int hdd_timing_get_level(hdd_handle h, int32_t kind, int32_t level, double* ms, int64_t* launches, double* flops,
+                         double* bytes);
 
 /* Matrix-core lane-layout self check: dtype 0 (f32 32x32x2) writes 32*32,
  * dtype 1 (f64 16x16x4) writes 16*16 products C = A B^T of fixed integer

@@ -145,7 +145,7 @@ struct hdd_tree {
   int timing_mask = 0;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
-  struct Rec { int kind, level; hipEvent_t a, b; double flops; };
+  struct Rec { int kind, level; hipEvent_t a, b; double flops, bytes; };
   int cur_level = -1;  // level of the launches being recorded
   std::vector<Rec> recs;
 };
@@ -172,14 +172,14 @@ hipEvent_t next_event(hdd_tree* h) {
 
 // Runs `launch` and, when the kind is being timed, brackets it with events.
 template <typename F>
-int timed(hdd_tree* h, int kind, double flops, F&& launch) {
+int timed(hdd_tree* h, int kind, double flops, F&& launch, double bytes = 0.0) {
   if (!(h->timing_mask & (1 << kind))) return hip_status(launch());
   hipEvent_t a = next_event(h), b = next_event(h);
   if (!a || !b) return HDD_EDEVICE;
   HIP_TRY(hipEventRecord(a, h->st));
   HIP_TRY(launch());
   HIP_TRY(hipEventRecord(b, h->st));
-  h->recs.push_back({kind, h->cur_level, a, b, flops});
+  h->recs.push_back({kind, h->cur_level, a, b, flops, bytes});
   return HDD_OK;
 }
 
@@ -200,6 +200,20 @@ double syrk_flops(const hdd_tree* h, int d, int k0, int k1, int r0, int c0, int 
     tot += lower_count(r0, U, c0, c1 < 0 ? U + 1 : c1);
   }
   return tot * 2.0 * (k1 - k0) * h->n_samples;
+}
+
+// Algorithmic HBM bytes of the same update: the panel rows it reads once
+// (rows min(r0, c0) .. U, columns k0 .. k1) and the output region read and
+// written once.
+double syrk_bytes(const hdd_tree* h, int d, int k0, int k1, int r0, int c0, int c1) {
+  const double esz = h->lev[d].is_double ? 8.0 : 4.0;
+  double tot = 0;
+  for (const auto& nd : h->plan.levels[d].nodes) {
+    const int U = nd.U();
+    const int rlo = std::min(r0, c0);
+    tot += double(U + 1 - rlo) * (k1 - k0) + 2.0 * lower_count(r0, U, c0, c1 < 0 ? U + 1 : c1);
+  }
+  return tot * esz * h->n_samples;
 }
 
 int check_deferred(hdd_tree* h) {
@@ -586,16 +600,19 @@ int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double
       HDD_TRY(timed(h, K_FACTOR, 0.0, [&] { return hdd::launch_panel(L, k0, kb, n_samples, h->info, h->st); }));
       if (k0 + kb < g) {
         const double fl = h->timing_mask ? syrk_flops(h, d, k0, k0 + kb, k0 + kb, k0 + kb, g) : 0.0;
+        const double by = h->timing_mask ? syrk_bytes(h, d, k0, k0 + kb, k0 + kb, k0 + kb, g) : 0.0;
         const int kind = hdd::syrk_uses_big_tile(L, k0, k0 + kb, k0 + kb, k0 + kb, g, mfma) ? K_SYRK128 : syrk_kind;
-        HDD_TRY(timed(h, kind, fl, [&] {
-          return hdd::launch_syrk(L, k0, k0 + kb, k0 + kb, k0 + kb, g, n_samples, mfma, h->st);
-        }));
+        HDD_TRY(timed(
+            h, kind, fl,
+            [&] { return hdd::launch_syrk(L, k0, k0 + kb, k0 + kb, k0 + kb, g, n_samples, mfma, h->st); }, by));
       }
     }
     if (L.max_U > g) {  // Schur update of Gamma (and the boundary load row)
       const double fl = h->timing_mask ? syrk_flops(h, d, 0, g, g, g, -1) : 0.0;
+      const double by = h->timing_mask ? syrk_bytes(h, d, 0, g, g, g, -1) : 0.0;
       const int kind = hdd::syrk_uses_big_tile(L, 0, g, g, g, -1, mfma) ? K_SYRK128 : syrk_kind;
-      HDD_TRY(timed(h, kind, fl, [&] { return hdd::launch_syrk(L, 0, g, g, g, -1, n_samples, mfma, h->st); }));
+      HDD_TRY(timed(
+          h, kind, fl, [&] { return hdd::launch_syrk(L, 0, g, g, g, -1, n_samples, mfma, h->st); }, by));
     }
     return HDD_OK;
   };
@@ -853,13 +870,14 @@ int hdd_timing_enable(hdd_handle h, int32_t mask) {
 }
 
 int hdd_timing_get(hdd_handle h, int32_t kind, double* ms, int64_t* launches, double* flops) {
-  return hdd_timing_get_level(h, kind, -1, ms, launches, flops);
+  return hdd_timing_get_level(h, kind, -1, ms, launches, flops, nullptr);
 }
 
-int hdd_timing_get_level(hdd_handle h, int32_t kind, int32_t level, double* ms, int64_t* launches, double* flops) {
+int hdd_timing_get_level(hdd_handle h, int32_t kind, int32_t level, double* ms, int64_t* launches, double* flops,
+                         double* bytes) {
   if (!h || kind < 0 || kind >= kKinds) return HDD_EINVAL;
   HIP_TRY(hipStreamSynchronize(h->st));
-  double tot = 0, fl = 0;
+  double tot = 0, fl = 0, by = 0;
   int64_t n = 0;
   for (const auto& r : h->recs) {
     if (r.kind != kind || (level >= 0 && r.level != level)) continue;
@@ -867,11 +885,13 @@ int hdd_timing_get_level(hdd_handle h, int32_t kind, int32_t level, double* ms, 
     HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
     tot += t;
     fl += r.flops;
+    by += r.bytes;
     ++n;
   }
   if (ms) *ms = tot;
   if (launches) *launches = n;
   if (flops) *flops = fl;
+  if (bytes) *bytes = by;
   return HDD_OK;
 }
 

@@ -18,31 +18,63 @@ namespace hdd {
 // grid.x = (node, sample) pair, grid.y strides over the lower triangle.
 // ---------------------------------------------------------------------------
 template <typename Ts, typename Tf>
-__global__ void k_extend_add(DevLevel F, DevLevel S, int n_samples) {
+__global__ void __launch_bounds__(256) k_extend_add(DevLevel F, DevLevel S, int n_samples) {
+  // One 64 x 64 tile of the father's lower triangle per workgroup: lanes run
+  // over the 64 columns (coalesced stores), the 4 waves over 16 rows each.
+  // The tile's row and column maps are staged in LDS; every son read goes
+  // through an address that is valid even when the entry is absent (then the
+  // value is dropped), so all 32 reads of a thread are issued together.
+  __shared__ int mrow[2][64], mcol[2][64];
   const int pair = blockIdx.x;
   const int node = pair / n_samples;
   const int s = pair % n_samples;
   const DevNode nd = F.nodes[node];
   const int n = nd.U + 1;
-  const long long total = (long long)n * (n + 1) / 2;
+  const int t = blockIdx.y;
+  const int ti = tri_row(t), tj = t - ti * (ti + 1) / 2;
+  const int r0 = ti * 64, c0 = tj * 64;
+  if (r0 >= n) return;  // uniform
   const int* mA = F.maps + nd.map_off;
   const int* mB = mA + n;
+  const int tid = threadIdx.x;
+  if (tid < 128) {
+    const int q = tid & 63, which = tid >> 6;
+    const int r = r0 + q, c = c0 + q;
+    const int* m = which ? mB : mA;
+    mrow[which][q] = r < n ? m[r] : -1;
+    mcol[which][q] = c < n ? m[c] : -1;
+  }
+  __syncthreads();
   const int sonA = 2 * node, sonB = 2 * node + 1;
   const DevNode na = S.nodes[sonA], nb = S.nodes[sonB];
   const int ga = na.U - na.bnd, gb = nb.U - nb.bnd;
   const Ts* SA = frame_ptr<Ts>(S, sonA, s) + (long long)ga * na.ld + ga;
   const Ts* SB = frame_ptr<Ts>(S, sonB, s) + (long long)gb * nb.ld + gb;
   Tf* out = frame_ptr<Tf>(F, node, s);
-  for (long long e = (long long)blockIdx.y * blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.y * blockDim.x) {
-    const int r = tri_row(e);
-    const int c = int(e - (long long)r * (r + 1) / 2);
-    Tf v = Tf(0);
-    const int ar = mA[r], ac = mA[c];
-    if (ar >= 0 && ac >= 0) v += Tf(ar >= ac ? SA[(long long)ar * na.ld + ac] : SA[(long long)ac * na.ld + ar]);
-    const int br = mB[r], bc = mB[c];
-    if (br >= 0 && bc >= 0) v += Tf(br >= bc ? SB[(long long)br * nb.ld + bc] : SB[(long long)bc * nb.ld + br]);
-    out[(long long)r * nd.ld + c] = v;
+  const int lane = tid & 63, w = tid >> 6;
+  const int c = c0 + lane;
+  const int ac = mcol[0][lane], bc = mcol[1][lane];
+  Ts va[16], vb[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int rr = w + 4 * q;
+    const int ar = mrow[0][rr], br = mrow[1][rr];
+    const long long ia = (ar >= 0 && ac >= 0) ? (long long)max(ar, ac) * na.ld + min(ar, ac) : 0;
+    const long long ib = (br >= 0 && bc >= 0) ? (long long)max(br, bc) * nb.ld + min(br, bc) : 0;
+    va[q] = SA[ia];
+    vb[q] = SB[ib];
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int rr = w + 4 * q;
+    const int r = r0 + rr;
+    if (r < n && c <= r) {
+      const int ar = mrow[0][rr], br = mrow[1][rr];
+      Tf v = Tf(0);
+      if (ar >= 0 && ac >= 0) v += Tf(va[q]);
+      if (br >= 0 && bc >= 0) v += Tf(vb[q]);
+      out[(long long)r * nd.ld + c] = v;
+    }
   }
 }
 
@@ -483,9 +515,8 @@ __global__ void __launch_bounds__(256) k_syrk_simple(DevLevel L, SyrkArgs a, int
 static int ceil_div(long long a, long long b) { return int((a + b - 1) / b); }
 
 hipError_t launch_extend_add(const DevLevel& F, const DevLevel& S, int n_samples, hipStream_t st) {
-  const long long n = (long long)F.max_U + 1;
-  const long long tri = n * (n + 1) / 2;
-  dim3 grid(F.n_nodes * n_samples, std::max(1, std::min(ceil_div(tri, 256 * 8), 4096))), block(256);
+  const long long nt = ((long long)F.max_U + 1 + 63) / 64;  // 64 x 64 tiles per side
+  dim3 grid(F.n_nodes * n_samples, unsigned(nt * (nt + 1) / 2)), block(256);
   if (F.is_double && S.is_double)
     hipLaunchKernelGGL((k_extend_add<double, double>), grid, block, 0, st, F, S, n_samples);
   else if (F.is_double)

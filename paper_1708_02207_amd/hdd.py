@@ -87,7 +87,8 @@ def _load() -> ctypes.CDLL:
         "hdd_timing_get": [P, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl)],
         "hdd_mfma_selftest": [i32, P],
         "hdd_debug_frame": [P, i32, i32, i32, P, ctypes.POINTER(i32)],
-        "hdd_timing_get_level": [P, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl)],
+        "hdd_timing_get_level": [P, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl),
+                                 ctypes.POINTER(dbl)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -305,10 +306,14 @@ class HDD:
     def timing_enable(self, mask: int):
         _check(_lib.hdd_timing_enable(self.h, int(mask)), "hdd_timing_enable")
 
-    def timing_get(self, kind: int, level: int = -1):
+    def timing_get(self, kind: int, level: int = -1, with_bytes: bool = False):
+        """(ms, launches, flops[, bytes]) of the timed launches of `kind`."""
         ms = ctypes.c_double(0)
         n = ctypes.c_int64(0)
         fl = ctypes.c_double(0)
+        by = ctypes.c_double(0)
         _check(_lib.hdd_timing_get_level(self.h, int(kind), int(level), ctypes.byref(ms), ctypes.byref(n),
-                                         ctypes.byref(fl)), "hdd_timing_get_level")
+                                         ctypes.byref(fl), ctypes.byref(by)), "hdd_timing_get_level")
+        if with_bytes:
+            return ms.value, n.value, fl.value, by.value
         return ms.value, n.value, fl.value
