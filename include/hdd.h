@@ -77,7 +77,7 @@ typedef struct hdd_opts {
                               c r / (1 - r) with c = max|du| / max|u| of the last
                               sweep and r = c / (c of the sweep before), is
                               <= refine_tol for every sample (so at least two
-                              sweeps; r >= 1/2 never stops; default 1e-9) */
+                              sweeps; r >= 1/2 never stops; default 2e-9) */
   int32_t reserved[8];     /* must be zero */
 } hdd_opts;
 

@@ -82,95 +82,127 @@ __global__ void __launch_bounds__(256) k_extend_add(DevLevel F, DevLevel S, int 
 // Panel step of the partial Cholesky (the elimination of eq. SchurMinus1 on
 // the interface block; the paper's M = -(sum of the sons' interface blocks)
 // of eq. gamma is factored as -M = L L^T, which is positive definite).
-//  k_potrf_diag: one workgroup per (node, sample) factors the kb x kb
-//    diagonal block at (k0, k0) in LDS and writes L_kk back.  A non-positive
-//    or non-finite pivot is recorded in info[sample] and replaced by 1 so that
-//    no NaN spreads.
-//  k_trsm_rows: solves X L_kk^T = A[r, k0:k0+kb] for every row r below the
-//    block (interface rows, boundary rows and the rhs row), one row per
-//    thread, with rows and L_kk staged in LDS.
+//
+// k_panel_diag: one wave per (node, sample) factors the kb x kb diagonal
+//   block at (k0, k0), kb <= 64, in registers (lane i holds row i); the
+//   scaled pivot column is exchanged through LDS, so no workgroup barrier is
+//   needed.  A non-positive or non-finite pivot is recorded in info[sample]
+//   and replaced by 1 so that no NaN spreads.
+// k_panel_rows: solves X L^T = A[r, k0:k0+kb] for the rows r below the block
+//   (interface rows, boundary rows and the rhs row), one row per thread in
+//   registers against L in LDS; rows are staged through LDS with coalesced
+//   loads and stores.  grid = (node x sample, row chunks of RW).
 // ---------------------------------------------------------------------------
-template <typename T, int NB>
-__global__ void __launch_bounds__(256) k_potrf_diag(DevLevel L, int k0, int kb, int n_samples, int* info) {
-  __shared__ T D[NB][NB + 1];
-  __shared__ int bad_pivot;
-  const int pair = blockIdx.x;
-  const int node = pair / n_samples;
-  const int s = pair % n_samples;
-  const DevNode nd = L.nodes[node];
-  T* F = frame_ptr<T>(L, node, s);
-  const int ld = nd.ld;
-  const int tid = threadIdx.x;
-  if (tid == 0) bad_pivot = 0;
-  for (int e = tid; e < kb * kb; e += blockDim.x) {
-    const int i = e / kb, j = e % kb;
-    if (j <= i) D[i][j] = F[(long long)(k0 + i) * ld + (k0 + j)];
-  }
-  __syncthreads();
-  for (int j = 0; j < kb; ++j) {
-    if (tid == 0) {
-      T d = D[j][j];
-      if (!(d > T(0)) || !(d < T(1e300))) {
-        if (!bad_pivot) bad_pivot = k0 + j + 1;
-        d = T(1);
-      }
-      D[j][j] = sqrt(d);
-    }
-    __syncthreads();
-    const T djj = D[j][j];
-    for (int i = j + 1 + tid; i < kb; i += blockDim.x) D[i][j] /= djj;
-    __syncthreads();
-    const int m = kb - j - 1;
-    for (int e = tid; e < m * m; e += blockDim.x) {
-      const int i = j + 1 + e / m, k = j + 1 + e % m;
-      if (k <= i) D[i][k] -= D[i][j] * D[k][j];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < kb * kb; e += blockDim.x) {
-    const int i = e / kb, j = e % kb;
-    if (j <= i) F[(long long)(k0 + i) * ld + (k0 + j)] = D[i][j];
-  }
-  if (tid == 0 && bad_pivot && info) atomicCAS(info + s, 0, L.node_base + node + 1);
+template <typename T> struct PanelCfg {
+  static constexpr int RW = sizeof(T) == 8 ? 64 : 128;  // rows (= threads) per workgroup
+};
+
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
 template <typename T, int NB>
-__global__ void __launch_bounds__(64) k_trsm_rows(DevLevel L, int k0, int kb, int n_samples) {
-  // 64 rows per workgroup (one wave); rows and the factored diagonal block
-  // are staged in LDS, every access stays inside [k0, k0 + kb).
-  __shared__ T D[NB][NB + 1];
-  __shared__ T X[64][NB + 1];
+__global__ void __launch_bounds__(64) k_panel_diag(DevLevel L, int k0, int kb, int n_samples, int* info) {
+  __shared__ T col[64];
   const int pair = blockIdx.x;
   const int node = pair / n_samples;
   const int s = pair % n_samples;
   const DevNode nd = L.nodes[node];
-  const int r0 = k0 + kb + blockIdx.y * 64;
-  if (r0 > nd.U) return;  // whole block idle (uniform)
-  const int nrows = min(64, nd.U + 1 - r0);
-  T* F = frame_ptr<T>(L, node, s);
   const int ld = nd.ld;
-  const int t = threadIdx.x;
-  for (int e = t; e < kb * kb; e += 64) {
-    const int i = e / kb, j = e % kb;
-    D[i][j] = (j <= i) ? F[(long long)(k0 + i) * ld + (k0 + j)] : T(0);
+  T* Dg = frame_ptr<T>(L, node, s) + (long long)k0 * ld + k0;
+  const int lane = threadIdx.x;
+  T a[NB];
+  const int lc = min(lane, kb - 1);
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const T v = Dg[(long long)lc * ld + min(k, lc)];
+    a[k] = (lane < kb && k <= lane) ? v : T(0);
   }
-  for (int e = t; e < nrows * kb; e += 64) {
-    const int i = e / kb, j = e % kb;
-    X[i][j] = F[(long long)(r0 + i) * ld + (k0 + j)];
+  int bp = 0;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    if (j < kb) {
+      T d = lane_value(a[j], j);
+      if (!(d > T(0)) || !(d < T(1e300))) {
+        if (!bp) bp = k0 + j + 1;
+        d = T(1);
+      }
+      d = sqrt(d);
+      a[j] = lane == j ? d : (lane > j ? a[j] / d : a[j]);
+      col[lane] = a[j];  // zero on lanes >= kb, so columns past kb stay zero
+#pragma unroll
+      for (int k = j + 1; k < NB; ++k) {
+        const T ck = col[k];
+        if (k <= lane) a[k] -= a[j] * ck;
+      }
+    }
   }
-  __syncthreads();
-  if (t < nrows) {
-    for (int j = 0; j < kb; ++j) {
-      T v = X[t][j];
-      for (int l = 0; l < j; ++l) v -= X[t][l] * D[j][l];
-      X[t][j] = v / D[j][j];
+#pragma unroll
+  for (int k = 0; k < NB; ++k)
+    if (lane < kb && k <= lane) Dg[(long long)lane * ld + k] = a[k];
+  if (lane == 0 && bp && info) atomicCAS(info + s, 0, L.node_base + node + 1);
+}
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(PanelCfg<T>::RW) k_panel_rows(DevLevel L, int k0, int kb, int n_samples) {
+  constexpr int RW = PanelCfg<T>::RW;
+  __shared__ T D[NB][NB + 1];
+  __shared__ T X[RW][NB + 1];
+  const int pair = blockIdx.x;
+  const int node = pair / n_samples;
+  const int s = pair % n_samples;
+  const DevNode nd = L.nodes[node];
+  const int U = nd.U, ld = nd.ld;
+  const int r0 = k0 + kb + blockIdx.y * RW;
+  if (r0 > U) return;  // uniform
+  T* F = frame_ptr<T>(L, node, s);
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kb * kb; e += RW) {
+    const int i = e / kb, j = e % kb;
+    if (j <= i) D[i][j] = F[(long long)(k0 + i) * ld + k0 + j];
+  }
+  const int nrows = min(RW, U + 1 - r0);
+  const int total = nrows * kb;
+  constexpr int UNR = 8;
+  for (int base = 0; base < total; base += RW * UNR) {  // consecutive threads read consecutive columns
+    T v[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int e = min(base + u * RW + tid, total - 1);
+      v[u] = F[(long long)(r0 + e / kb) * ld + k0 + e % kb];
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int e = base + u * RW + tid;
+      if (e < total) X[e / kb][e % kb] = v[u];
     }
   }
   __syncthreads();
-  for (int e = t; e < nrows * kb; e += 64) {
-    const int i = e / kb, j = e % kb;
-    F[(long long)(r0 + i) * ld + (k0 + j)] = X[i][j];
+  if (tid < nrows) {
+    T x[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) x[k] = k < kb ? X[tid][k] : T(0);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (j < kb) {
+        T v = x[j];
+#pragma unroll
+        for (int l = 0; l < j; ++l) v -= x[l] * D[j][l];
+        x[j] = v / D[j][j];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+      if (k < kb) X[tid][k] = x[k];
   }
+  __syncthreads();
+  for (int e = tid; e < total; e += RW) F[(long long)(r0 + e / kb) * ld + k0 + e % kb] = X[e / kb][e % kb];
 }
 
 // ---------------------------------------------------------------------------
@@ -528,21 +560,30 @@ hipError_t launch_extend_add(const DevLevel& F, const DevLevel& S, int n_samples
   return hipGetLastError();
 }
 
-hipError_t launch_panel(const DevLevel& L, int k0, int kb, int n_samples, int* info, hipStream_t st) {
-  dim3 g1(L.n_nodes * n_samples), block(256);
-  if (L.is_double)
-    hipLaunchKernelGGL((k_potrf_diag<double, kPanelNB>), g1, block, 0, st, L, k0, kb, n_samples, info);
-  else
-    hipLaunchKernelGGL((k_potrf_diag<float, kPanelNB>), g1, block, 0, st, L, k0, kb, n_samples, info);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+template <typename T, int NB>
+static void launch_panel_t(const DevLevel& L, int k0, int kb, int n_samples, int* info, hipStream_t st) {
+  const int pairs = L.n_nodes * n_samples;
   const int rows = L.max_U + 1 - (k0 + kb);
-  if (rows <= 0) return hipSuccess;
-  dim3 g2(L.n_nodes * n_samples, ceil_div(rows, 64));
-  if (L.is_double)
-    hipLaunchKernelGGL((k_trsm_rows<double, kPanelNB>), g2, dim3(64), 0, st, L, k0, kb, n_samples);
-  else
-    hipLaunchKernelGGL((k_trsm_rows<float, kPanelNB>), g2, dim3(64), 0, st, L, k0, kb, n_samples);
+  hipLaunchKernelGGL((k_panel_diag<T, NB>), dim3(pairs), dim3(64), 0, st, L, k0, kb, n_samples, info);
+  if (rows > 0) {
+    constexpr int RW = PanelCfg<T>::RW;
+    hipLaunchKernelGGL((k_panel_rows<T, NB>), dim3(pairs, ceil_div(rows, RW)), dim3(RW), 0, st, L, k0, kb,
+                       n_samples);
+  }
+}
+
+hipError_t launch_panel(const DevLevel& L, int k0, int kb, int n_samples, int* info, hipStream_t st) {
+  if (kb < 1 || kb > kPanelNB) return hipErrorInvalidValue;
+  // the smallest compiled panel width that holds kb columns
+  if (L.is_double) {
+    if (kb <= 16) launch_panel_t<double, 16>(L, k0, kb, n_samples, info, st);
+    else if (kb <= 32) launch_panel_t<double, 32>(L, k0, kb, n_samples, info, st);
+    else launch_panel_t<double, 64>(L, k0, kb, n_samples, info, st);
+  } else {
+    if (kb <= 16) launch_panel_t<float, 16>(L, k0, kb, n_samples, info, st);
+    else if (kb <= 32) launch_panel_t<float, 32>(L, k0, kb, n_samples, info, st);
+    else launch_panel_t<float, 64>(L, k0, kb, n_samples, info, st);
+  }
   return hipGetLastError();
 }
 
