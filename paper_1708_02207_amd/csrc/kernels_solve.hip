@@ -145,7 +145,8 @@ __device__ __forceinline__ void rows_dot(const T* F, int ld, int r0, int r1, int
 // samples: u_gamma = L^-T (z - P^T u_Gamma).  grid.x = entry * n_samples + s.
 template <typename T, int BS>
 __global__ void __launch_bounds__(BS) k_topdown(DevLevel L, const int* __restrict__ list, int n_samples,
-                                                double* __restrict__ u, long long ustride, int z_from_vec) {
+                                                double* __restrict__ u, long long ustride, int z_from_vec,
+                                                int r_ready) {
   extern __shared__ double dyn[];
   constexpr int NW = BS / 64;
   const int e = blockIdx.x;
@@ -162,12 +163,16 @@ __global__ void __launch_bounds__(BS) k_topdown(DevLevel L, const int* __restric
   double* us = u + (long long)s * ustride;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double* vz = z_from_vec ? L.vec + (long long)s * L.vec_stride + nd.ids_off : nullptr;
-  for (int i = tid; i < g; i += BS) r[i] = z_from_vec ? vz[i] : ldd(F + (long long)U * ld + i);
-  for (int j = tid; j < G; j += BS) ub[j] = us[ids[g + j]];
+  if (r_ready) {  // r = z - P^T u_Gamma was left in the gamma slots of u by k_topdown_gemv
+    for (int i = tid; i < g; i += BS) r[i] = us[ids[i]];
+  } else {
+    for (int i = tid; i < g; i += BS) r[i] = z_from_vec ? vz[i] : ldd(F + (long long)U * ld + i);
+    for (int j = tid; j < G; j += BS) ub[j] = us[ids[g + j]];
+  }
   __syncthreads();
   // r -= P^T u_Gamma, P[j][i] = F[(g + j) * ld + i]: a group of gp lanes
   // covers consecutive i, the 64 / gp groups of a wave and the waves split j
-  if (G > 0) {
+  if (G > 0 && !r_ready) {
     const int gp = lanes_for(g);
     const int rpw = 64 / gp;
     const int jg = wv * rpw + lane / gp, JG = NW * rpw;
@@ -212,12 +217,50 @@ __global__ void __launch_bounds__(BS) k_topdown(DevLevel L, const int* __restric
   for (int i = tid; i < g; i += BS) us[ids[i]] = r[i];
 }
 
+// The GEMV of the top-down for wide interfaces, spread over 64-column
+// chunks of gamma: r_i = z_i - sum_j P[j][i] u_Gamma[j] for the chunk's i,
+// left in the gamma slots of u for k_topdown (r_ready) to solve.
+// grid = (entry x sample, gamma / 64); dynamic LDS: G_max + 256 doubles.
+template <typename T>
+__global__ void __launch_bounds__(256) k_topdown_gemv(DevLevel L, const int* __restrict__ list, int n_samples,
+                                                      double* __restrict__ u, long long ustride, int z_from_vec) {
+  extern __shared__ double dyn[];
+  const int e = blockIdx.x;
+  const int node = list[e / n_samples];
+  const int s = e % n_samples;
+  const DevNode nd = L.nodes[node];
+  const int g = L.gam, G = nd.bnd, U = nd.U, ld = nd.ld;
+  const int i0 = blockIdx.y * 64;
+  if (i0 >= g) return;  // uniform
+  double* ub = dyn;                  // [G]
+  double* part = dyn + (L.max_U - L.gam);    // [4][64]
+  const T* F = frame_ptr<T>(L, node, s);
+  const int* ids = L.ids + nd.ids_off;
+  double* us = u + (long long)s * ustride;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int j = tid; j < G; j += 256) ub[j] = us[ids[g + j]];
+  __syncthreads();
+  const int i = i0 + lane;
+  double acc = 0.0;
+  if (i < g) {
+    const T* col = F + (long long)g * ld + i;
+#pragma unroll 16
+    for (int j = wv; j < G; j += 4) acc += ldd(col + (long long)j * ld) * ub[j];
+  }
+  part[wv * 64 + lane] = acc;
+  __syncthreads();
+  if (wv == 0 && i < g) {
+    const double z = z_from_vec ? L.vec[(long long)s * L.vec_stride + nd.ids_off + i] : ldd(F + (long long)U * ld + i);
+    us[ids[i]] = z - (part[lane] + part[64 + lane] + part[128 + lane] + part[192 + lane]);
+  }
+}
+
 // Forward (bottom-up) propagation of a right-hand side for all nodes of a
 // level above the blocks: the load is the extend-add of the sons' condensed
 // loads; z = L^-1 g~_gamma, g_omega = g~_Gamma - P z.
 // vec[node] = [z (gamma) ; g_omega (Gamma)].
 template <typename T, int BS>
-__global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int n_samples) {
+__global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int n_samples, int defer_gemv) {
   extern __shared__ double dyn[];
   const int e = blockIdx.x;
   const int node = e / n_samples;
@@ -257,10 +300,35 @@ __global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int n_sa
       __syncthreads();
     }
   }
-  // g_omega[j] = gt[g + j] - sum_i P[j][i] z_i
+  // g_omega[j] = gt[g + j] - sum_i P[j][i] z_i (or only gt, with the product
+  // left to k_forward_gemv)
   double* out = L.vec + (long long)s * L.vec_stride + nd.ids_off;
-  rows_dot<T, BS>(F, ld, g, g + G, 0, g, gt, [&](int r, double y) { out[r] = gt[r] - y; });
+  if (defer_gemv) {
+    for (int j = tid; j < G; j += BS) out[g + j] = gt[g + j];
+  } else {
+    rows_dot<T, BS>(F, ld, g, g + G, 0, g, gt, [&](int r, double y) { out[r] = gt[r] - y; });
+  }
   for (int i = tid; i < g; i += BS) out[i] = gt[i];
+}
+
+// g_omega -= P z for wide interfaces, spread over 128-row chunks of Gamma.
+// grid = (node x sample, Gamma / 128); dynamic LDS: gamma doubles.
+template <typename T>
+__global__ void __launch_bounds__(256) k_forward_gemv(DevLevel L, int n_samples) {
+  extern __shared__ double dyn[];
+  const int e = blockIdx.x;
+  const int node = e / n_samples;
+  const int s = e % n_samples;
+  const DevNode nd = L.nodes[node];
+  const int g = L.gam, G = nd.bnd, ld = nd.ld;
+  const int j0 = blockIdx.y * 128;
+  if (j0 >= G) return;  // uniform
+  const T* F = frame_ptr<T>(L, node, s);
+  double* out = L.vec + (long long)s * L.vec_stride + nd.ids_off;
+  double* z = dyn;
+  for (int i = threadIdx.x; i < g; i += 256) z[i] = out[i];
+  __syncthreads();
+  rows_dot<T, 256>(F, ld, g + j0, g + min(G, j0 + 128), 0, g, z, [&](int r, double y) { out[r] -= y; });
 }
 
 // ---------------------------------------------------------------------------
@@ -478,42 +546,68 @@ __global__ void k_mfma_selftest(int dtype, double* out) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+// Interfaces at least this wide run the solves' matrix-vector products as
+// separate launches spread over many workgroups.
+constexpr int kSplitGamma = 127;
+
 hipError_t launch_topdown(const DevLevel& L, const int* list, int n_list, int n_samples, double* u, long long ustride,
                           bool z_from_vec, hipStream_t st) {
   if (n_list <= 0) return hipSuccess;
   dim3 grid(n_list * n_samples);
   const int zv = z_from_vec ? 1 : 0;
+  const int split = (L.gam >= kSplitGamma && (L.max_U - L.gam) > 0) ? 1 : 0;
+  if (split) {
+    dim3 g2(n_list * n_samples, ceil_div(L.gam, 64));
+    const size_t lds = sizeof(double) * (size_t((L.max_U - L.gam)) + 256);
+    if (L.is_double)
+      hipLaunchKernelGGL(k_topdown_gemv<double>, g2, dim3(256), lds, st, L, list, n_samples, u, ustride, zv);
+    else
+      hipLaunchKernelGGL(k_topdown_gemv<float>, g2, dim3(256), lds, st, L, list, n_samples, u, ustride, zv);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (L.gam <= 64) {
     const size_t lds = solve_lds(L.max_U, L.gam, 64);
     if (L.is_double)
-      hipLaunchKernelGGL((k_topdown<double, 64>), grid, dim3(64), lds, st, L, list, n_samples, u, ustride, zv);
+      hipLaunchKernelGGL((k_topdown<double, 64>), grid, dim3(64), lds, st, L, list, n_samples, u, ustride, zv, split);
     else
-      hipLaunchKernelGGL((k_topdown<float, 64>), grid, dim3(64), lds, st, L, list, n_samples, u, ustride, zv);
+      hipLaunchKernelGGL((k_topdown<float, 64>), grid, dim3(64), lds, st, L, list, n_samples, u, ustride, zv, split);
   } else {
     const size_t lds = solve_lds(L.max_U, L.gam, 256);
     if (L.is_double)
-      hipLaunchKernelGGL((k_topdown<double, 256>), grid, dim3(256), lds, st, L, list, n_samples, u, ustride, zv);
+      hipLaunchKernelGGL((k_topdown<double, 256>), grid, dim3(256), lds, st, L, list, n_samples, u, ustride, zv,
+                         split);
     else
-      hipLaunchKernelGGL((k_topdown<float, 256>), grid, dim3(256), lds, st, L, list, n_samples, u, ustride, zv);
+      hipLaunchKernelGGL((k_topdown<float, 256>), grid, dim3(256), lds, st, L, list, n_samples, u, ustride, zv,
+                         split);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_forward(const DevLevel& L, const DevLevel& child, int n_samples, hipStream_t st) {
   dim3 grid(L.n_nodes * n_samples);
+  const int split = (L.gam >= kSplitGamma && (L.max_U - L.gam) > 0) ? 1 : 0;
   if (L.gam <= 64) {
     const size_t lds = solve_lds(L.max_U, L.gam, 64);
     if (L.is_double)
-      hipLaunchKernelGGL((k_forward<double, 64>), grid, dim3(64), lds, st, L, child, n_samples);
+      hipLaunchKernelGGL((k_forward<double, 64>), grid, dim3(64), lds, st, L, child, n_samples, split);
     else
-      hipLaunchKernelGGL((k_forward<float, 64>), grid, dim3(64), lds, st, L, child, n_samples);
+      hipLaunchKernelGGL((k_forward<float, 64>), grid, dim3(64), lds, st, L, child, n_samples, split);
   } else {
     const size_t lds = solve_lds(L.max_U, L.gam, 256);
     if (L.is_double)
-      hipLaunchKernelGGL((k_forward<double, 256>), grid, dim3(256), lds, st, L, child, n_samples);
+      hipLaunchKernelGGL((k_forward<double, 256>), grid, dim3(256), lds, st, L, child, n_samples, split);
     else
-      hipLaunchKernelGGL((k_forward<float, 256>), grid, dim3(256), lds, st, L, child, n_samples);
+      hipLaunchKernelGGL((k_forward<float, 256>), grid, dim3(256), lds, st, L, child, n_samples, split);
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !split) return e;
+  dim3 g2(L.n_nodes * n_samples, ceil_div((L.max_U - L.gam), 128));
+  const size_t lds = sizeof(double) * size_t(L.gam);
+  if (L.is_double)
+    hipLaunchKernelGGL(k_forward_gemv<double>, g2, dim3(256), lds, st, L, n_samples);
+  else
+    hipLaunchKernelGGL(k_forward_gemv<float>, g2, dim3(256), lds, st, L, n_samples);
   return hipGetLastError();
 }
 
