@@ -210,7 +210,8 @@ int hdd_debug_frame(hdd_handle h, int32_t sample, int32_t depth, int32_t index, 
  * 2 extend-add, 3 block build (leaf assembly and in-LDS elimination of the
  * leaf interior), 4 top-down, 5 forward pass, 6 residual, 7 Schur update on
  * float64 levels, 8 the 128 x 128-tile float32 Schur update kernel (launches
- * of kind 8 are not counted in kind 0).
+ * of kind 8 are not counted in kind 0), 9 fused merge of narrow float32
+ * levels (extend-add, factorization and Schur update in one launch).
  * hdd_timing_enable(h, mask): bit k enables kind k (0 disables and clears).
  * hdd_timing_get: total milliseconds, number of launches and summed
  * algorithmic flops of the timed launches (Schur update: 2 K per lower-

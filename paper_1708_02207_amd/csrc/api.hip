@@ -19,13 +19,16 @@ using hdd::Plan;
 
 namespace {
 
-constexpr int kKinds = 9;
+constexpr int kKinds = 10;
 enum Kind {
   K_SYRK = 0, K_FACTOR = 1, K_EXTEND = 2, K_ASSEMBLE = 3, K_TOPDOWN = 4, K_FORWARD = 5, K_RESIDUAL = 6, K_SYRK64 = 7,
-  K_SYRK128 = 8
+  K_SYRK128 = 8, K_MERGE = 9
 };
 
 int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
+
+// Column block of the two-level blocked interface factorization.
+constexpr int kBlockNB = 128;
 
 bool refinement_possible(const hdd_opts& o) { return o.precision == HDD_FP32_REFINE || o.max_refine > 0; }
 
@@ -595,17 +598,26 @@ int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double
     const DevLevel& L = h->lev[d];
     const int g = L.gam;
     const int syrk_kind = L.is_double ? K_SYRK64 : K_SYRK;
-    for (int k0 = 0; k0 < g; k0 += hdd::kPanelNB) {
-      const int kb = std::min(hdd::kPanelNB, g - k0);
-      HDD_TRY(timed(h, K_FACTOR, 0.0, [&] { return hdd::launch_panel(L, k0, kb, n_samples, h->info, h->st); }));
-      if (k0 + kb < g) {
-        const double fl = h->timing_mask ? syrk_flops(h, d, k0, k0 + kb, k0 + kb, k0 + kb, g) : 0.0;
-        const double by = h->timing_mask ? syrk_bytes(h, d, k0, k0 + kb, k0 + kb, k0 + kb, g) : 0.0;
-        const int kind = hdd::syrk_uses_big_tile(L, k0, k0 + kb, k0 + kb, k0 + kb, g, mfma) ? K_SYRK128 : syrk_kind;
-        HDD_TRY(timed(
-            h, kind, fl,
-            [&] { return hdd::launch_syrk(L, k0, k0 + kb, k0 + kb, k0 + kb, g, n_samples, mfma, h->st); }, by));
+    // Rank-K update C[r0.., c0..c1) -= F[.., k0..k1) F[.., k0..k1)^T, timed.
+    auto syrk = [&](int k0, int k1, int r0, int c1) -> int {
+      const double fl = h->timing_mask ? syrk_flops(h, d, k0, k1, r0, r0, c1) : 0.0;
+      const double by = h->timing_mask ? syrk_bytes(h, d, k0, k1, r0, r0, c1) : 0.0;
+      const int kind = hdd::syrk_uses_big_tile(L, k0, k1, r0, r0, c1, mfma) ? K_SYRK128 : syrk_kind;
+      return timed(
+          h, kind, fl, [&] { return hdd::launch_syrk(L, k0, k1, r0, r0, c1, n_samples, mfma, h->st); }, by);
+    };
+    // Two-level blocked right-looking partial Cholesky of the first g
+    // columns: panels of kPanelNB columns inside blocks of kBlockNB columns;
+    // a panel's trailing update stays inside its block, and the columns
+    // right of a block are updated once per block (K = kBlockNB).
+    for (int b0 = 0; b0 < g; b0 += kBlockNB) {
+      const int b1 = std::min(g, b0 + kBlockNB);
+      for (int k0 = b0; k0 < b1; k0 += hdd::kPanelNB) {
+        const int kb = std::min(hdd::kPanelNB, b1 - k0);
+        HDD_TRY(timed(h, K_FACTOR, 0.0, [&] { return hdd::launch_panel(L, k0, kb, n_samples, h->info, h->st); }));
+        if (k0 + kb < b1) HDD_TRY(syrk(k0, k0 + kb, k0 + kb, b1));
       }
+      if (b1 < g) HDD_TRY(syrk(b0, b1, b1, g));
     }
     if (L.max_U > g) {  // Schur update of Gamma (and the boundary load row)
       const double fl = h->timing_mask ? syrk_flops(h, d, 0, g, g, g, -1) : 0.0;
@@ -622,6 +634,12 @@ int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double
   }));
   for (int d = D - 1; d >= 0; --d) {
     h->cur_level = d;
+    if (hdd::merge_small_ok(h->lev[d], mfma) && !h->lev[d + 1].is_double) {
+      HDD_TRY(timed(h, K_MERGE, 0.0, [&] {
+        return hdd::launch_merge_small(h->lev[d], h->lev[d + 1], n_samples, h->info, h->st);
+      }));
+      continue;
+    }
     HDD_TRY(timed(h, K_EXTEND, 0.0, [&] { return hdd::launch_extend_add(h->lev[d], h->lev[d + 1], n_samples, h->st); }));
     HDD_TRY(eliminate(d));
   }

@@ -15,6 +15,10 @@ hipError_t launch_panel(const DevLevel& L, int k0, int kb, int n_samples, int* i
 hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, int n_samples, bool mfma,
                        hipStream_t st);
 bool syrk_uses_big_tile(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, bool mfma);
+// Fused extend-add + factorization + Schur update of a float32 level with
+// gamma <= 31 (matrix cores), one workgroup per node and sample.
+bool merge_small_ok(const DevLevel& F, bool mfma);
+hipError_t launch_merge_small(const DevLevel& F, const DevLevel& S, int n_samples, int* info, hipStream_t st);
 
 // Blocks (in-LDS nested dissection of the leaf interior)
 size_t block_build_lds(const DevBlocks& B, bool dbl);

@@ -390,8 +390,10 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
 // (16-byte aligned rows), which holds for frames with 64 or more rows.
 __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int n_samples) {
   constexpr int KC = 32, TM = 128;
-  __shared__ float As[TM][KC + 1];
-  __shared__ float Bs[TM][KC + 1];
+  // two LDS buffers: the MFMAs read one while the prefetched chunk is
+  // stored into the other, one barrier per K chunk
+  __shared__ float As[2][TM][KC + 1];
+  __shared__ float Bs[2][TM][KC + 1];
   // XCD-aware order: workgroup b runs on XCD b % 8; all tiles of one (node,
   // sample) frame go to the same XCD in consecutive order, so its panel
   // columns stay in that XCD's L2 while its tiles are computed.
@@ -444,13 +446,13 @@ __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int
       }
     }
   };
-  auto store = [&]() {
+  auto store = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      As[lr][lk + 4 * q + 0] = pa[q].x; As[lr][lk + 4 * q + 1] = pa[q].y;
-      As[lr][lk + 4 * q + 2] = pa[q].z; As[lr][lk + 4 * q + 3] = pa[q].w;
-      Bs[lr][lk + 4 * q + 0] = pb[q].x; Bs[lr][lk + 4 * q + 1] = pb[q].y;
-      Bs[lr][lk + 4 * q + 2] = pb[q].z; Bs[lr][lk + 4 * q + 3] = pb[q].w;
+      As[buf][lr][lk + 4 * q + 0] = pa[q].x; As[buf][lr][lk + 4 * q + 1] = pa[q].y;
+      As[buf][lr][lk + 4 * q + 2] = pa[q].z; As[buf][lr][lk + 4 * q + 3] = pa[q].w;
+      Bs[buf][lr][lk + 4 * q + 0] = pb[q].x; Bs[buf][lr][lk + 4 * q + 1] = pb[q].y;
+      Bs[buf][lr][lk + 4 * q + 2] = pb[q].z; Bs[buf][lr][lk + 4 * q + 3] = pb[q].w;
     }
   };
   floatx16 acc[2][2];
@@ -461,28 +463,27 @@ __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[x][y][v] = 0.f;
   load(a.k0);
-  store();
+  store(0);
   __syncthreads();
+  int buf = 0;
   for (int kb = a.k0; kb < a.k1; kb += KC) {
-    const bool more = kb + KC < a.k1;
+    const bool more = kb + KC < a.k1;  // uniform
     if (more) load(kb + KC);
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 2) {
       float av[2], bv[2];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) av[x] = As[wr * 64 + x * 32 + (lane & 31)][kk + (lane >> 5)];
+      for (int x = 0; x < 2; ++x) av[x] = As[buf][wr * 64 + x * 32 + (lane & 31)][kk + (lane >> 5)];
 #pragma unroll
-      for (int y = 0; y < 2; ++y) bv[y] = Bs[wc * 64 + y * 32 + (lane & 31)][kk + (lane >> 5)];
+      for (int y = 0; y < 2; ++y) bv[y] = Bs[buf][wc * 64 + y * 32 + (lane & 31)][kk + (lane >> 5)];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[x], bv[y], acc[x][y], 0, 0, 0);
     }
+    if (more) store(buf ^ 1);
     __syncthreads();
-    if (more) {
-      store();
-      __syncthreads();
-    }
+    buf ^= 1;
   }
   // one 32 x 32 accumulator at a time: its 16 reads are issued together
 #pragma unroll
@@ -500,6 +501,191 @@ __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int
         if (syrk_in(U, i, j, a, c1e)) F[(long long)i * ld + j] = old[v] - acc[x][y][v];
       }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Fused merge of one node for narrow interfaces (gamma <= GP - 1, float32,
+// matrix cores): extend-add, partial Cholesky and Schur update in one pass,
+// one workgroup per (node, sample), so every frame entry is written once and
+// the sons' Schur complements are read once.
+//  1. the first gamma columns of every frame row (the panel) are gathered
+//     from the sons (eq. Psi_sum) into LDS;
+//  2. wave 0 factors the gamma x gamma block in registers (eq. gamma,
+//     eq. SchurMinus1), then each thread solves one panel row: P = S L^-T
+//     and z = L^-1 g (the rhs row);
+//  3. the panel [L ; P ; z] goes to the frame;
+//  4. S_omega = S~ - P P^T and g_omega = g~ - P z (eq. SchurC1) for the lower
+//     triangle of rows / columns gamma..U in 32 x 32 matrix-core tiles, with
+//     S~ gathered from the sons in the tile epilogue.
+// Dynamic LDS: 2 nr ints (maps) + nr (GP + 1) floats (panel), with
+// nr = gamma + 32 ceil((U + 1 - gamma) / 32) rows (tile overhang is zero).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int merge_rows(int g, int n) { return g + ((n - g + 31) / 32) * 32; }
+
+size_t merge_small_lds(int max_U, int g, int GP) {
+  const int nr = merge_rows(g, max_U + 1);
+  return size_t(2) * nr * 4 + size_t(nr) * (GP + 1) * 4;
+}
+
+template <int GP>
+__global__ void __launch_bounds__(256) k_merge_small(DevLevel F, DevLevel S, int n_samples, int* info) {
+  constexpr int KP = GP + 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ float col[64];
+  __shared__ int bad_pivot;
+  const int pair = blockIdx.x;
+  const int node = pair / n_samples;
+  const int s = pair % n_samples;
+  const DevNode nd = F.nodes[node];
+  const int U = nd.U, n = U + 1, g = F.gam, ld = nd.ld;
+  const int nr = merge_rows(g, n);
+  int* mA = reinterpret_cast<int*>(smem);
+  int* mB = mA + nr;
+  float* P = reinterpret_cast<float*>(mB + nr);  // [nr][KP]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  {
+    const int* gA = F.maps + nd.map_off;
+    const int* gB = gA + n;
+    for (int r = tid; r < nr; r += 256) {
+      mA[r] = r < n ? gA[r] : -1;
+      mB[r] = r < n ? gB[r] : -1;
+    }
+  }
+  if (tid == 0) bad_pivot = 0;
+  const DevNode na = S.nodes[2 * node], nb = S.nodes[2 * node + 1];
+  const int ga = na.U - na.bnd, gb = nb.U - nb.bnd;
+  const float* SA = frame_ptr<float>(S, 2 * node, s) + (long long)ga * na.ld + ga;
+  const float* SB = frame_ptr<float>(S, 2 * node + 1, s) + (long long)gb * nb.ld + gb;
+  float* Fo = frame_ptr<float>(F, node, s);
+  __syncthreads();
+  // S~(r, c) from the sons; addresses are valid for absent entries too
+  auto gather = [&](int r, int c, float& va, float& vb) {
+    const int ar = mA[r], ac = mA[c], br = mB[r], bc = mB[c];
+    const long long ia = (ar >= 0 && ac >= 0) ? (long long)max(ar, ac) * na.ld + min(ar, ac) : 0;
+    const long long ib = (br >= 0 && bc >= 0) ? (long long)max(br, bc) * nb.ld + min(br, bc) : 0;
+    const float xa = SA[ia], xb = SB[ib];
+    va = (ar >= 0 && ac >= 0) ? xa : 0.f;
+    vb = (br >= 0 && bc >= 0) ? xb : 0.f;
+  };
+  // 1. panel gather (rows past U and columns past gamma are zero)
+  {
+    constexpr int UNR = 4;
+    const int total = nr * GP;
+    for (int base = 0; base < total; base += 256 * UNR) {
+      float va[UNR], vb[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int e = min(base + u * 256 + tid, total - 1);
+        gather(e / GP, e % GP, va[u], vb[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int e = base + u * 256 + tid;
+        const int r = e / GP, c = e % GP;
+        if (e < total) P[r * KP + c] = (r < n && c < g && c <= r) ? va[u] + vb[u] : 0.f;
+      }
+    }
+  }
+  __syncthreads();
+  // 2a. Cholesky of the gamma x gamma block by wave 0 (lane i holds row i)
+  if (tid < 64) {
+    float a[GP];
+    const int lc = min(lane, g - 1);
+#pragma unroll
+    for (int k = 0; k < GP; ++k) a[k] = (lane < g && k <= lane) ? P[lc * KP + k] : 0.f;
+    int bp = 0;
+#pragma unroll
+    for (int j = 0; j < GP; ++j) {
+      if (j < g) {
+        float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[j]), j));
+        if (!(d > 0.f) || !(d < 3.0e38f)) {
+          if (!bp) bp = j + 1;
+          d = 1.f;
+        }
+        d = sqrtf(d);
+        a[j] = lane == j ? d : (lane > j ? a[j] / d : a[j]);
+        col[lane] = a[j];
+#pragma unroll
+        for (int k = j + 1; k < GP; ++k) {
+          const float ck = col[k];
+          if (k <= lane) a[k] -= a[j] * ck;
+        }
+      }
+    }
+    if (lane < g) {
+#pragma unroll
+      for (int k = 0; k < GP; ++k)
+        if (k <= lane) P[lane * KP + k] = a[k];
+    }
+    if (lane == 0) bad_pivot = bp;
+  }
+  __syncthreads();
+  if (tid == 0 && bad_pivot && info) atomicCAS(info + s, 0, F.node_base + node + 1);
+  // 2b. panel rows below the block: x L^T = a
+  for (int r = g + tid; r < n; r += 256) {
+    float x[GP];
+#pragma unroll
+    for (int k = 0; k < GP; ++k) x[k] = P[r * KP + k];
+#pragma unroll
+    for (int j = 0; j < GP; ++j) {
+      if (j < g) {
+        float v = x[j];
+#pragma unroll
+        for (int l = 0; l < j; ++l) v -= x[l] * P[j * KP + l];
+        x[j] = v / P[j * KP + j];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < GP; ++k) P[r * KP + k] = x[k];
+  }
+  __syncthreads();
+  // 3. panel -> frame (lower part of the interface rows, all columns below)
+  for (int e = tid; e < n * GP; e += 256) {
+    const int r = e / GP, c = e % GP;
+    if (c < g && c <= r) Fo[(long long)r * ld + c] = P[r * KP + c];
+  }
+  // 4. Schur update tiles over rows / columns g..U (lower tiles only)
+  const int nt = (n - g + 31) / 32;
+  for (int t = wv; t < nt * (nt + 1) / 2; t += 4) {
+    const int ti = tri_row(t), tj = t - ti * (ti + 1) / 2;
+    const int i0 = g + ti * 32, j0 = g + tj * 32;
+    floatx16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+#pragma unroll
+    for (int kk = 0; kk < GP; kk += 2) {
+      const float av = P[(i0 + (lane & 31)) * KP + kk + (lane >> 5)];
+      const float bv = P[(j0 + (lane & 31)) * KP + kk + (lane >> 5)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    }
+    const int j = j0 + (lane & 31);
+    float va[16], vb[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = i0 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+      gather(i, j, va[v], vb[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = i0 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+      if (i < n && j <= i) Fo[(long long)i * ld + j] = va[v] + vb[v] - acc[v];
+    }
+  }
+}
+
+bool merge_small_ok(const DevLevel& F, bool mfma) { return mfma && !F.is_double && F.gam <= 31 && F.gam >= 1; }
+
+hipError_t launch_merge_small(const DevLevel& F, const DevLevel& S, int n_samples, int* info, hipStream_t st) {
+  if (F.is_double || S.is_double || F.gam > 31 || F.gam < 1) return hipErrorInvalidValue;
+  dim3 grid(F.n_nodes * n_samples), block(256);
+  if (F.gam <= 15) {
+    const size_t lds = merge_small_lds(F.max_U, F.gam, 16);
+    hipLaunchKernelGGL(k_merge_small<16>, grid, block, lds, st, F, S, n_samples, info);
+  } else {
+    const size_t lds = merge_small_lds(F.max_U, F.gam, 32);
+    hipLaunchKernelGGL(k_merge_small<32>, grid, block, lds, st, F, S, n_samples, info);
+  }
+  return hipGetLastError();
 }
 
 // Plain FMA version of the same update (no matrix cores), kept as a

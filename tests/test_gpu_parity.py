@@ -126,6 +126,43 @@ def test_node_schur_bruteforce(H, oracle_mod, n, leaf, flags):
     t.close()
 
 
+@pytest.mark.parametrize("n,leaf", [(63, 8), (127, 16)])
+def test_node_schur_fp32(H, oracle_mod, n, leaf):
+    """The float32 matrix-core levels (fused narrow-interface merges and the
+    panel + Schur-update path) produce S_omega and g_omega equal to the dense
+    Schur complement of the subdomain's own matrix to float32 accuracy."""
+    O = oracle_mod
+    kappa = np.random.default_rng(5).uniform(0.2, 5.0, size=(1, n + 1, n + 1, 2))
+    f = np.random.default_rng(6).uniform(0.0, 1.0, size=(n + 2, n + 2))
+    o = H.hdd_default_opts(n, H.HDD_FP32_REFINE, leaf=leaf)
+    t = H.HDD(o, 1)
+    t.build(kappa, f)
+    nc = n + 1
+    levels = H.hdd_plan_summary(o)["levels"]
+    say("fp32 node schur n", n, "levels", levels, "sync", t.sync())
+    worst = 0.0
+    for d in range(levels - 2, 0, -1):
+        nodes = H.hdd_plan_level(o, d)["nodes"]
+        for k in sorted({0, nodes // 2, nodes - 1}):
+            info = H.hdd_plan_node(o, d, k)
+            if (info["w"] - 1) * (info["h"] - 1) > 4000:  # dense brute force stays small
+                continue
+            S, g, ids = t.node_schur(0, d, k)
+            rect = (info["x0"], info["x0"] + info["w"], info["y0"], info["y0"] + info["h"])
+            So, go, bnodes = O.subdomain_schur(n, kappa[0], f, rect, drop_dirichlet=True)
+            pos = {(i, j): q for q, (i, j) in enumerate(bnodes)}
+            perm = [pos[(int(x) % (nc + 1), int(x) // (nc + 1))] for x in ids]
+            So = So[np.ix_(perm, perm)]
+            go = go[perm]
+            eS = np.abs(S - So).max() / np.abs(So).max()
+            eg = np.abs(g - go).max() / max(np.abs(go).max(), 1e-30)
+            say(f"  depth {d} node {k} gamma {info['gam']} |Gamma| {len(ids)} errS {eS:.2e} errg {eg:.2e}")
+            worst = max(worst, eS, eg)
+    # float32 frames: a few hundred units of float32 rounding
+    assert worst < 5e-5, worst
+    t.close()
+
+
 def test_c0_fp32_refine(H, oracle_mod):
     w = make_workload("c0_63")
     say("c0_63 fp32+refine")
