@@ -65,6 +65,7 @@ extern "C" {
 /* option flags */
 #define HDD_FLAG_NO_MFMA 1        /* use the plain FMA Schur update (cross-check) */
 #define HDD_FLAG_KEEP_DIRICHLET 2 /* plan only: keep outer-boundary nodes in every Gamma */
+#define HDD_FLAG_BLOCK8 4         /* eliminate leaf interiors in 8 x 8-cell blocks (default 16 x 16) */
 
 typedef struct hdd_opts {
   int32_t n;               /* N, interior nodes per side */

@@ -49,7 +49,7 @@ bool make_plan(const hdd_opts& o, Plan& p) {
   hdd::PlanOptions po;
   po.n = o.n;
   po.leaf = o.leaf;
-  po.block = 16;
+  po.block = (o.flags & HDD_FLAG_BLOCK8) ? 8 : 16;
   po.keep_dirichlet = (o.flags & HDD_FLAG_KEEP_DIRICHLET) != 0;
   return hdd::build_plan(po, p);
 }

@@ -16,7 +16,8 @@ hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1
                        hipStream_t st);
 bool syrk_uses_big_tile(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, bool mfma);
 // Fused extend-add + factorization + Schur update of a float32 level with
-// gamma <= 31 (matrix cores), one workgroup per node and sample.
+// gamma <= 31 (matrix cores), one workgroup per node and sample, when the
+// node's panel fits in LDS.
 bool merge_small_ok(const DevLevel& F, bool mfma);
 hipError_t launch_merge_small(const DevLevel& F, const DevLevel& S, int n_samples, int* info, hipStream_t st);
 

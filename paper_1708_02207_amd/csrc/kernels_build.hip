@@ -527,9 +527,10 @@ size_t merge_small_lds(int max_U, int g, int GP) {
   return size_t(2) * nr * 4 + size_t(nr) * (GP + 1) * 4;
 }
 
-template <int GP>
-__global__ void __launch_bounds__(256) k_merge_small(DevLevel F, DevLevel S, int n_samples, int* info) {
+template <int GP, int NT>
+__global__ void __launch_bounds__(NT) k_merge_small(DevLevel F, DevLevel S, int n_samples, int* info) {
   constexpr int KP = GP + 1;
+  constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ float col[64];
   __shared__ int bad_pivot;
@@ -546,7 +547,7 @@ __global__ void __launch_bounds__(256) k_merge_small(DevLevel F, DevLevel S, int
   {
     const int* gA = F.maps + nd.map_off;
     const int* gB = gA + n;
-    for (int r = tid; r < nr; r += 256) {
+    for (int r = tid; r < nr; r += NT) {
       mA[r] = r < n ? gA[r] : -1;
       mB[r] = r < n ? gB[r] : -1;
     }
@@ -569,18 +570,18 @@ __global__ void __launch_bounds__(256) k_merge_small(DevLevel F, DevLevel S, int
   };
   // 1. panel gather (rows past U and columns past gamma are zero)
   {
-    constexpr int UNR = 4;
+    constexpr int UNR = 8;
     const int total = nr * GP;
-    for (int base = 0; base < total; base += 256 * UNR) {
+    for (int base = 0; base < total; base += NT * UNR) {
       float va[UNR], vb[UNR];
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const int e = min(base + u * 256 + tid, total - 1);
+        const int e = min(base + u * NT + tid, total - 1);
         gather(e / GP, e % GP, va[u], vb[u]);
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const int e = base + u * 256 + tid;
+        const int e = base + u * NT + tid;
         const int r = e / GP, c = e % GP;
         if (e < total) P[r * KP + c] = (r < n && c < g && c <= r) ? va[u] + vb[u] : 0.f;
       }
@@ -622,7 +623,7 @@ __global__ void __launch_bounds__(256) k_merge_small(DevLevel F, DevLevel S, int
   __syncthreads();
   if (tid == 0 && bad_pivot && info) atomicCAS(info + s, 0, F.node_base + node + 1);
   // 2b. panel rows below the block: x L^T = a
-  for (int r = g + tid; r < n; r += 256) {
+  for (int r = g + tid; r < n; r += NT) {
     float x[GP];
 #pragma unroll
     for (int k = 0; k < GP; ++k) x[k] = P[r * KP + k];
@@ -640,13 +641,13 @@ __global__ void __launch_bounds__(256) k_merge_small(DevLevel F, DevLevel S, int
   }
   __syncthreads();
   // 3. panel -> frame (lower part of the interface rows, all columns below)
-  for (int e = tid; e < n * GP; e += 256) {
+  for (int e = tid; e < n * GP; e += NT) {
     const int r = e / GP, c = e % GP;
     if (c < g && c <= r) Fo[(long long)r * ld + c] = P[r * KP + c];
   }
   // 4. Schur update tiles over rows / columns g..U (lower tiles only)
   const int nt = (n - g + 31) / 32;
-  for (int t = wv; t < nt * (nt + 1) / 2; t += 4) {
+  for (int t = wv; t < nt * (nt + 1) / 2; t += NW) {
     const int ti = tri_row(t), tj = t - ti * (ti + 1) / 2;
     const int i0 = g + ti * 32, j0 = g + tj * 32;
     floatx16 acc;
@@ -673,17 +674,26 @@ __global__ void __launch_bounds__(256) k_merge_small(DevLevel F, DevLevel S, int
   }
 }
 
-bool merge_small_ok(const DevLevel& F, bool mfma) { return mfma && !F.is_double && F.gam <= 31 && F.gam >= 1; }
+static constexpr size_t kMaxDynLds = 160 * 1024 - 1024;  // LDS per workgroup minus the static part
+
+// gamma <= 31 only: with 64-column panels the in-register factorization
+// loses accuracy (the second refinement correction doubles at 1023^2) and
+// the level runs at one workgroup per CU for no net gain.
+bool merge_small_ok(const DevLevel& F, bool mfma) {
+  if (!mfma || F.is_double || F.gam < 1 || F.gam > 31) return false;
+  const int GP = F.gam <= 15 ? 16 : 32;
+  return merge_small_lds(F.max_U, F.gam, GP) <= kMaxDynLds;
+}
 
 hipError_t launch_merge_small(const DevLevel& F, const DevLevel& S, int n_samples, int* info, hipStream_t st) {
-  if (F.is_double || S.is_double || F.gam > 31 || F.gam < 1) return hipErrorInvalidValue;
-  dim3 grid(F.n_nodes * n_samples), block(256);
+  if (!merge_small_ok(F, true) || S.is_double) return hipErrorInvalidValue;
+  dim3 grid(F.n_nodes * n_samples);
   if (F.gam <= 15) {
     const size_t lds = merge_small_lds(F.max_U, F.gam, 16);
-    hipLaunchKernelGGL(k_merge_small<16>, grid, block, lds, st, F, S, n_samples, info);
+    hipLaunchKernelGGL((k_merge_small<16, 256>), grid, dim3(256), lds, st, F, S, n_samples, info);
   } else {
     const size_t lds = merge_small_lds(F.max_U, F.gam, 32);
-    hipLaunchKernelGGL(k_merge_small<32>, grid, block, lds, st, F, S, n_samples, info);
+    hipLaunchKernelGGL((k_merge_small<32, 256>), grid, dim3(256), lds, st, F, S, n_samples, info);
   }
   return hipGetLastError();
 }

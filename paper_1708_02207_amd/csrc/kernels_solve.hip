@@ -37,8 +37,8 @@ __host__ __device__ inline int lanes_for(int n) {
 // Partial sums of the transposed GEMV: one row of g per lane group.
 __host__ __device__ inline int solve_part(int g, int bs) { return g < 64 ? bs : (bs / 64) * g; }
 
-size_t solve_lds(int max_U, int gam, int bs) {
-  return sizeof(double) * (size_t(max_U + 1) + size_t(solve_part(gam, bs)));
+size_t solve_lds(int max_U, int gam, int bs, bool need_part = true) {
+  return sizeof(double) * (size_t(max_U + 1) + (need_part ? size_t(solve_part(gam, bs)) : 0));
 }
 
 // Value of lane l (wave-uniform l) in every lane, through the scalar unit.
@@ -566,7 +566,16 @@ hipError_t launch_topdown(const DevLevel& L, const int* list, int n_list, int n_
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (L.gam <= 64) {
+  const bool no_part = split || L.max_U == L.gam;  // no transposed GEMV in this kernel
+  if (L.gam > 64 && no_part && n_list * n_samples < 256) {  // few workgroups: 16 waves each
+    const size_t lds = solve_lds(L.max_U, L.gam, 1024, false);
+    if (L.is_double)
+      hipLaunchKernelGGL((k_topdown<double, 1024>), grid, dim3(1024), lds, st, L, list, n_samples, u, ustride, zv,
+                         split);
+    else
+      hipLaunchKernelGGL((k_topdown<float, 1024>), grid, dim3(1024), lds, st, L, list, n_samples, u, ustride, zv,
+                         split);
+  } else if (L.gam <= 64) {
     const size_t lds = solve_lds(L.max_U, L.gam, 64);
     if (L.is_double)
       hipLaunchKernelGGL((k_topdown<double, 64>), grid, dim3(64), lds, st, L, list, n_samples, u, ustride, zv, split);
@@ -587,7 +596,13 @@ hipError_t launch_topdown(const DevLevel& L, const int* list, int n_list, int n_
 hipError_t launch_forward(const DevLevel& L, const DevLevel& child, int n_samples, hipStream_t st) {
   dim3 grid(L.n_nodes * n_samples);
   const int split = (L.gam >= kSplitGamma && (L.max_U - L.gam) > 0) ? 1 : 0;
-  if (L.gam <= 64) {
+  if (L.gam > 64 && L.n_nodes * n_samples < 256) {  // few workgroups: 16 waves each
+    const size_t lds = solve_lds(L.max_U, L.gam, 1024, false);
+    if (L.is_double)
+      hipLaunchKernelGGL((k_forward<double, 1024>), grid, dim3(1024), lds, st, L, child, n_samples, split);
+    else
+      hipLaunchKernelGGL((k_forward<float, 1024>), grid, dim3(1024), lds, st, L, child, n_samples, split);
+  } else if (L.gam <= 64) {
     const size_t lds = solve_lds(L.max_U, L.gam, 64);
     if (L.is_double)
       hipLaunchKernelGGL((k_forward<double, 64>), grid, dim3(64), lds, st, L, child, n_samples, split);

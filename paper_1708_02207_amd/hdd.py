@@ -29,6 +29,7 @@ HDD_MEM_HOST = 0
 HDD_MEM_DEVICE = 1
 HDD_FLAG_NO_MFMA = 1
 HDD_FLAG_KEEP_DIRICHLET = 2
+HDD_FLAG_BLOCK8 = 4
 
 EXPORTED = [
     "hdd_default_opts", "hdd_workspace_size", "hdd_create", "hdd_build", "hdd_query_points",
