@@ -151,6 +151,23 @@ int hdd_query_mean(hdd_handle h, const double rect[4], double* out, int32_t mem)
 int hdd_loglik(hdd_handle h, int32_t n_y, const double* xy, const double* y, double sigma, int32_t normalized,
                double* out, int32_t mem);
 
+/*
+ * Sample-specific observation sites (each sample of the batch has its own
+ * points, e.g. independent requests batched together).  Sample s owns points
+ * offsets[s] .. offsets[s+1]-1 of xy; offsets: host int32 [n_samples+1] with
+ * offsets[0] = 0, non-decreasing, total at most 4096.
+ * hdd_query_points_ragged: u_out (mem) float64 [offsets[n_samples]], the P1
+ *   interpolated values in the order of xy.
+ * hdd_loglik_ragged: out (mem) float64 [n_samples], sample s's Gaussian
+ *   log-likelihood of its own y (host float64, indexed like xy) with its own
+ *   noise level sigma[s] (host float64 [n_samples], > 0), as hdd_loglik.
+ * Host arrays are read during the call only.  EINVAL for bad offsets, points
+ * outside the unit square or non-positive sigma.
+ */
+int hdd_query_points_ragged(hdd_handle h, const int32_t* offsets, const double* xy, double* u_out, int32_t mem);
+int hdd_loglik_ragged(hdd_handle h, const int32_t* offsets, const double* xy, const double* y, const double* sigma,
+                      int32_t normalized, double* out, int32_t mem);
+
 /* Root to Leaves on every node (Section 3.4), plus refinement in
  * HDD_FP32_REFINE mode.  Errors: HDD_ENOTCONVERGED (values still usable). */
 int hdd_solve_full(hdd_handle h);
@@ -231,6 +248,61 @@ int hdd_timing_get_level(hdd_handle h, int32_t kind, int32_t level, double* ms, 
  * patterns into out (host).  Needs a GPU. */
 int hdd_mfma_selftest(int32_t dtype, double* out);
 
+
+/* ------------------------------------------------------------------------
+ * Likelihood server with continuous batching (the serving loop around the
+ * calls above; implementation in serve.hip).
+ *
+ * One handle, one stream and one worker thread per mesh size.  A request is
+ * one parameter sample (kappa of its mesh), its observation sites and
+ * optional observations; the answer is the P1 values at the sites and the
+ * unnormalized Gaussian log-likelihood (0 without observations).  Requests
+ * queue per mesh; a free mesh takes all waiting requests up to its slot
+ * count as one batch (Leaves to Root, then hdd_query_points_ragged and
+ * hdd_loglik_ragged), so requests arriving while others run are admitted as
+ * soon as a slot frees up, and batches of different meshes overlap on the
+ * GPU.  Device workspaces for full batches are allocated at creation: slots
+ * (default 32) are halved until all meshes' workspaces fit hbm_budget bytes
+ * (0: no limit); ENOMEM if one slot per mesh does not fit.
+ * ------------------------------------------------------------------------ */
+#define HDD_SERVER_MAX_MESHES 8
+#define HDD_SERVER_MAX_POINTS 256
+
+typedef struct hdd_server* hdd_server_t;
+
+typedef struct {
+  int32_t n_meshes;                      /* 1 .. HDD_SERVER_MAX_MESHES */
+  int32_t n[HDD_SERVER_MAX_MESHES];      /* interior nodes per side of each mesh */
+  int32_t leaf[HDD_SERVER_MAX_MESHES];   /* leaf size in cells (0: default) */
+  int32_t precision;                     /* HDD_FP64 or HDD_FP32_REFINE */
+  int32_t slots;                         /* samples per batch per mesh (0: 32) */
+  double hbm_budget;                     /* bytes for all device workspaces (0: no limit) */
+  int32_t reserved[8];                   /* must be zero */
+} hdd_server_opts;
+
+/* f: per mesh host float64 [(n+2)^2] nodal right-hand side copied at
+ * creation, or NULL (f = 1 on every mesh); an entry may also be NULL. */
+int hdd_server_create(const hdd_server_opts* opts, const double* const* f, hdd_server_t* out);
+/* Samples per batch each mesh was given (after the budget). */
+int hdd_server_slots(hdd_server_t s, int32_t* slots);
+/* Queue a request on mesh `mesh` (index into opts.n): kappa host float64
+ * [n+1][n+1][2] (positive, finite), xy host float64 [n_pts][2] in the unit
+ * square (1 <= n_pts <= HDD_SERVER_MAX_POINTS), y host float64 [n_pts] or
+ * NULL, sigma > 0.  Inputs are copied; *id identifies the request. */
+int hdd_server_submit(hdd_server_t s, int32_t mesh, const double* kappa, int32_t n_pts, const double* xy,
+                      const double* y, double sigma, int64_t* id);
+/* *done = 1 once the request's batch has finished (non-blocking). */
+int hdd_server_poll(hdd_server_t s, int64_t id, int32_t* done);
+/* Wait for a request, copy its values (host float64 [n_pts]) and
+ * log-likelihood, and release it.  times (host float64 [4], may be NULL):
+ * queue wait, batch time, submit-to-done seconds, and the batch size.
+ * Returns the batch's status code. */
+int hdd_server_result(hdd_server_t s, int64_t id, double* values, double* loglik, double* times);
+/* out int64 [4]: submitted, completed, batches run, queued now. */
+int hdd_server_stats(hdd_server_t s, int64_t* out);
+/* Stops the workers after their running batches; queued requests fail with
+ * HDD_ESTATE. */
+int hdd_server_destroy(hdd_server_t s);
 #ifdef __cplusplus
 }
 #endif

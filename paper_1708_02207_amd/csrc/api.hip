@@ -57,7 +57,7 @@ bool make_plan(const hdd_opts& o, Plan& p) {
 // Byte offsets of everything the handle keeps in its device workspace.
 struct Layout {
   std::vector<int64_t> frames, nodes, maps, ids, vec;
-  int64_t kappa, f, u, d, r, info, bad, maxbits, qout, qxy, qy, lists, iota;
+  int64_t kappa, f, u, d, r, info, bad, maxbits, qout, qxy, qy, qsmp, qoff, qsig, lists, iota;
   int64_t cst, bvec, tmaps, tlids, tmicro, origin;
   int64_t max_q;
   int64_t total;
@@ -97,9 +97,12 @@ Layout make_layout(const Plan& p, const hdd_opts& o, int ms) {
   L.info = take(int64_t(ms) * 4);
   L.bad = take(int64_t(ms) * 4);
   L.maxbits = take(int64_t(ms) * 16);
-  L.qout = take(int64_t(ms) * L.max_q * 8);
+  L.qout = take((int64_t(ms) + 1) * L.max_q * 8);
   L.qxy = take(L.max_q * 16);
   L.qy = take(L.max_q * 8);
+  L.qsmp = take(L.max_q * 4);
+  L.qoff = take((int64_t(ms) + 1) * 4);
+  L.qsig = take(int64_t(ms) * 8);
   L.lists = take(total_nodes * 4);
   L.iota = take(max_nodes * 4);
   const auto& T = p.sub;
@@ -134,7 +137,8 @@ struct hdd_tree {
   double *kappa = nullptr, *f = nullptr, *u = nullptr, *d = nullptr, *r = nullptr;
   int *info = nullptr, *bad = nullptr;
   unsigned long long* maxbits = nullptr;
-  double *qout = nullptr, *qxy = nullptr, *qy = nullptr;
+  double *qout = nullptr, *qxy = nullptr, *qy = nullptr, *qsig = nullptr;
+  int *qsmp = nullptr, *qoff = nullptr;
   int *lists = nullptr, *iota = nullptr;
   int* pinned_lists = nullptr;
   hipEvent_t lists_done = nullptr;
@@ -544,6 +548,9 @@ int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* works
   h->qout = reinterpret_cast<double*>(h->ws + L.qout);
   h->qxy = reinterpret_cast<double*>(h->ws + L.qxy);
   h->qy = reinterpret_cast<double*>(h->ws + L.qy);
+  h->qsmp = reinterpret_cast<int*>(h->ws + L.qsmp);
+  h->qoff = reinterpret_cast<int*>(h->ws + L.qoff);
+  h->qsig = reinterpret_cast<double*>(h->ws + L.qsig);
   h->lists = reinterpret_cast<int*>(h->ws + L.lists);
   h->iota = reinterpret_cast<int*>(h->ws + L.iota);
   if (hipHostMalloc(&h->pinned_lists, sizeof(int) * size_t(std::max<int64_t>(list_off, 1))) != hipSuccess) {
@@ -665,6 +672,62 @@ int hdd_query_points(hdd_handle h, int32_t n_pts, const double* xy, double* u_ou
   HIP_TRY(hdd::launch_points(nc, h->n_samples, n_pts, h->qxy, h->u, dst, h->st));
   if (mem == HDD_MEM_DEVICE) return HDD_OK;
   return copy_out(h, u_out, h->qout, size_t(n_pts) * h->n_samples, HDD_MEM_HOST);
+}
+
+// Marks the paths to every point of a ragged set, uploads the points and
+// their sample index, and interpolates into dst (device).
+static int ragged_points(hdd_tree* h, const int32_t* off, const double* xy, double* dst) {
+  const int ns = h->n_samples;
+  if (!off || !xy || off[0] != 0) return HDD_EINVAL;
+  for (int s = 0; s < ns; ++s)
+    if (off[s + 1] < off[s]) return HDD_EINVAL;
+  const int n_total = off[ns];
+  if (n_total < 1 || n_total > h->lay.max_q) return HDD_EINVAL;
+  const int nc = h->plan.nc;
+  auto need = empty_need(h);
+  std::vector<int> smp(n_total);
+  for (int s = 0; s < ns; ++s)
+    for (int p = off[s]; p < off[s + 1]; ++p) {
+      const double x = xy[2 * p], y = xy[2 * p + 1];
+      if (!(x >= 0.0 && x <= 1.0 && y >= 0.0 && y <= 1.0)) return HDD_EINVAL;
+      const int ci = std::min(int(std::floor(x * nc)), nc - 1), cj = std::min(int(std::floor(y * nc)), nc - 1);
+      mark_cell_path(h, ci, cj, need);
+      smp[p] = s;
+    }
+  HDD_TRY(prepare_values(h, need));
+  HIP_TRY(hipMemcpyAsync(h->qxy, xy, size_t(n_total) * 16, hipMemcpyHostToDevice, h->st));
+  HIP_TRY(hipMemcpyAsync(h->qsmp, smp.data(), size_t(n_total) * 4, hipMemcpyHostToDevice, h->st));
+  HIP_TRY(hdd::launch_points_ragged(nc, n_total, h->qxy, h->qsmp, h->u, dst, h->st));
+  // the pageable sources above must stay valid until the copies complete
+  HIP_TRY(hipStreamSynchronize(h->st));
+  return HDD_OK;
+}
+
+int hdd_query_points_ragged(hdd_handle h, const int32_t* offsets, const double* xy, double* u_out, int32_t mem) {
+  if (!h || !u_out) return HDD_EINVAL;
+  if (!h->built) return HDD_ESTATE;
+  double* dst = mem == HDD_MEM_DEVICE ? u_out : h->qout;
+  HDD_TRY(ragged_points(h, offsets, xy, dst));
+  if (mem == HDD_MEM_DEVICE) return HDD_OK;
+  return copy_out(h, u_out, h->qout, size_t(offsets[h->n_samples]), HDD_MEM_HOST);
+}
+
+int hdd_loglik_ragged(hdd_handle h, const int32_t* offsets, const double* xy, const double* y, const double* sigma,
+                      int32_t normalized, double* out, int32_t mem) {
+  if (!h || !y || !sigma || !out || !offsets) return HDD_EINVAL;
+  if (!h->built) return HDD_ESTATE;
+  const int ns = h->n_samples;
+  for (int s = 0; s < ns; ++s)
+    if (!(sigma[s] > 0.0)) return HDD_EINVAL;
+  HDD_TRY(ragged_points(h, offsets, xy, h->qout));
+  const int n_total = offsets[ns];
+  HIP_TRY(hipMemcpyAsync(h->qy, y, size_t(n_total) * 8, hipMemcpyHostToDevice, h->st));
+  HIP_TRY(hipMemcpyAsync(h->qoff, offsets, size_t(ns + 1) * 4, hipMemcpyHostToDevice, h->st));
+  HIP_TRY(hipMemcpyAsync(h->qsig, sigma, size_t(ns) * 8, hipMemcpyHostToDevice, h->st));
+  double* dst = mem == HDD_MEM_DEVICE ? out : h->qout + n_total;
+  HIP_TRY(hdd::launch_loglik_ragged(ns, h->qoff, h->qout, h->qy, h->qsig, normalized, dst, h->st));
+  if (mem == HDD_MEM_DEVICE) return hip_status(hipStreamSynchronize(h->st));  // host sources stay valid until here
+  return copy_out(h, out, dst, size_t(ns), HDD_MEM_HOST);
 }
 
 int hdd_query_interface(hdd_handle h, double* u_out, int32_t* len, int32_t mem) {

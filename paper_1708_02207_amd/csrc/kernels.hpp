@@ -49,6 +49,10 @@ hipError_t launch_points(int nc, int n_samples, int n_pts, const double* xy, con
 hipError_t launch_interface(int nc, int n_samples, const double* u, double* out, hipStream_t st);
 hipError_t launch_mean(int nc, int n_samples, int i0, int i1, int j0, int j1, const double* u, double* out,
                        hipStream_t st);
+hipError_t launch_points_ragged(int nc, int n_total, const double* xy, const int* smp, const double* u, double* out,
+                                hipStream_t st);
+hipError_t launch_loglik_ragged(int n_samples, const int* off, const double* hu, const double* y, const double* sigma,
+                                int normalized, double* out, hipStream_t st);
 hipError_t launch_loglik(int n_samples, int n_y, const double* hu, const double* y, double sigma, int normalized,
                          double* out, hipStream_t st);
 hipError_t launch_mfma_selftest(int dtype, double* out, hipStream_t st);

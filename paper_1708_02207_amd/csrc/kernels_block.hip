@@ -73,45 +73,52 @@ constexpr int NT = 256;   // threads of the top-down / forward kernels
 constexpr int NTB = 512;  // threads of the build kernel
 
 // ---------------------------------------------------------------------------
-// Column J of the left-looking partial Cholesky for all n frames of a level:
-// L_jj = sqrt(A_jj - sum_l L_jl^2), then every row below (interface,
-// boundary and load rows) L_ij = (A_ij - sum_l L_il L_jl) / L_jj.  Unrolled
-// over the (compile-time) columns so every inner loop has a fixed length.
+// Column J of the left-looking partial Cholesky for all n frames of a level,
+// one barrier per column: every thread of a node recomputes the pivot
+// L_JJ = sqrt(A_JJ - sum_l L_Jl^2) from row J (whose diagonal entry is left
+// untouched until the end), the thread of row J records it in dg, and the
+// rows below (interface, boundary and load rows) take
+// L_iJ = (A_iJ - sum_l L_il L_Jl) / L_JJ.  The recorded pivots are written to
+// the diagonal after the last column.  Unrolled over the (compile-time)
+// columns so every inner loop has a fixed length.
 template <typename T, typename L, int J>
-__device__ __forceinline__ void crout_columns(T* cur, int& bad_pivot) {
+__device__ __forceinline__ void crout_columns(T* cur, T* dg, int& bad_pivot) {
   if constexpr (J < L::gam) {
     constexpr int ld = L::ldp;
-    const int tid = threadIdx.x;
-    for (int t = tid; t < L::n; t += NTB) {
+    constexpr int m = L::U + 1 - J;  // rows J .. U
+    for (int e = threadIdx.x; e < L::n * m; e += NTB) {
+      const int t = e / m, i = J + e % m;
       T* F = cur + t * L::fsz;
       T d = F[J * ld + J];
 #pragma unroll
       for (int l = 0; l < J; ++l) d -= F[J * ld + l] * F[J * ld + l];
-      if (!(d > T(0)) || !(d < T(1e300))) {
-        bad_pivot = 1;
-        d = T(1);
-      }
-      F[J * ld + J] = sqrt(d);
-    }
-    __syncthreads();
-    constexpr int m = L::U - J;  // rows J+1 .. U
-    for (int e = tid; e < L::n * m; e += NTB) {
-      const int t = e / m, i = J + 1 + e % m;
-      T* F = cur + t * L::fsz;
-      T v = F[i * ld + J];
+      const bool ok = (d > T(0)) && (d < T(1e300));
+      d = ok ? sqrt(d) : T(1);
+      if (i == J) {
+        if (!ok) bad_pivot = 1;
+        dg[t * L::gam + J] = d;
+      } else {
+        T v = F[i * ld + J];
 #pragma unroll
-      for (int l = 0; l < J; ++l) v -= F[i * ld + l] * F[J * ld + l];
-      F[i * ld + J] = v / F[J * ld + J];
+        for (int l = 0; l < J; ++l) v -= F[i * ld + l] * F[J * ld + l];
+        F[i * ld + J] = v / d;
+      }
     }
     __syncthreads();
-    crout_columns<T, L, J + 1>(cur, bad_pivot);
+    crout_columns<T, L, J + 1>(cur, dg, bad_pivot);
+  } else {
+    for (int e = threadIdx.x; e < L::n * L::gam; e += NTB) {
+      const int t = e / L::gam, j = e % L::gam;
+      cur[t * L::fsz + j * L::ldp + j] = dg[e];
+    }
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
 // Build: one level (extend-add from the sons in `prev`, eliminate in `cur`).
 template <typename T, int S, int K>
-__device__ __forceinline__ void build_level(const DevBlocks& B, T* cur, const T* prev, T* cst, int* idx,
+__device__ __forceinline__ void build_level(const DevBlocks& B, T* cur, const T* prev, T* cst, int* idx, T* dg,
                                             int& bad_pivot) {
   using L = Lv<S, K>;
   const int tid = threadIdx.x;
@@ -142,7 +149,7 @@ __device__ __forceinline__ void build_level(const DevBlocks& B, T* cur, const T*
   // column): L_jj = sqrt(A_jj - sum_l L_jl^2), then every row below
   // (interface, boundary and load rows) L_ij = (A_ij - sum_l L_il L_jl) / L_jj.
   constexpr int g = L::gam, ld = L::ldp;
-  crout_columns<T, L, 0>(cur, bad_pivot);
+  crout_columns<T, L, 0>(cur, dg, bad_pivot);
   // Schur update of the boundary block and the load row (rank-g, eq.
   // SchurC1): S[i][l] -= sum_k P[i][k] P[l][k], g <= l <= i <= U.
   {
@@ -170,9 +177,22 @@ __device__ __forceinline__ void build_level(const DevBlocks& B, T* cur, const T*
 }
 
 template <typename T, int S, int K>
-__device__ __forceinline__ void build_levels(const DevBlocks& B, T* cur, T* prev, T* cst, int* idx, int& bad_pivot) {
-  build_level<T, S, K>(B, cur, prev, cst, idx, bad_pivot);
-  if constexpr (K > 0) build_levels<T, S, K - 1>(B, prev, cur, cst, idx, bad_pivot);
+__device__ __forceinline__ void build_levels(const DevBlocks& B, T* cur, T* prev, T* cst, int* idx, T* dg,
+                                             int& bad_pivot) {
+  build_level<T, S, K>(B, cur, prev, cst, idx, dg, bad_pivot);
+  if constexpr (K > 0) build_levels<T, S, K - 1>(B, prev, cur, cst, idx, dg, bad_pivot);
+}
+
+// Largest n * gam over the levels of a block (pivots recorded per column).
+template <int S, int K> constexpr int gam_nodes_from() {
+  using L = Lv<S, K>;
+  constexpr int m = L::n * L::gam;
+  if constexpr (K < L::Lm) {
+    constexpr int rest = gam_nodes_from<S, K + 1>();
+    return m > rest ? m : rest;
+  } else {
+    return m;
+  }
 }
 
 template <typename T, int S>
@@ -186,6 +206,7 @@ __global__ void __launch_bounds__(NTB) k_block_build(DevBlocks B, int n_samples,
   T* buf1 = buf0 + B.max_buf;
   __shared__ int bad_pivot;
   __shared__ int idx[kIdxMax<S>];
+  __shared__ T dg[gam_nodes_from<S, 0>()];
   const int q = blockIdx.x / n_samples;
   const int s = blockIdx.x % n_samples;
   const int X0 = B.origin[2 * q], Y0 = B.origin[2 * q + 1];
@@ -247,7 +268,7 @@ __global__ void __launch_bounds__(NTB) k_block_build(DevBlocks B, int n_samples,
   __syncthreads();
   T* cst = cst_block<T>(B, q, s);
   int bp = 0;
-  build_levels<T, S, Lm>(B, buf0, buf1, cst, idx, bp);
+  build_levels<T, S, Lm>(B, buf0, buf1, cst, idx, dg, bp);
   if (bp) bad_pivot = 1;
   __syncthreads();
   // block root frame -> global frame store (lower triangle)

@@ -448,6 +448,27 @@ __global__ void k_points(int nc, int n_samples, int n_pts, const double* __restr
   out[t] = v;
 }
 
+// The same interpolation for sample-specific point sets: point t belongs to
+// sample smp[t].
+__global__ void k_points_ragged(int nc, int n_total, const double* __restrict__ xy, const int* __restrict__ smp,
+                                const double* __restrict__ u, double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_total) return;
+  const long long nn = (long long)(nc + 1) * (nc + 1);
+  const double* us = u + (long long)smp[t] * nn;
+  const double x = xy[2 * t] * nc, y = xy[2 * t + 1] * nc;
+  int ci = int(floor(x)), cj = int(floor(y));
+  ci = ci < 0 ? 0 : (ci > nc - 1 ? nc - 1 : ci);
+  cj = cj < 0 ? 0 : (cj > nc - 1 ? nc - 1 : cj);
+  const double fx = x - ci, fy = y - cj;
+  const double u00 = us[(long long)cj * (nc + 1) + ci];
+  const double u11 = us[(long long)(cj + 1) * (nc + 1) + ci + 1];
+  double v;
+  if (fx >= fy) v = (1.0 - fx) * u00 + (fx - fy) * us[(long long)cj * (nc + 1) + ci + 1] + fy * u11;
+  else v = (1.0 - fy) * u00 + fx * u11 + (fy - fx) * us[(long long)(cj + 1) * (nc + 1) + ci];
+  out[t] = v;
+}
+
 __global__ void k_interface(int nc, int n_samples, const double* __restrict__ u, double* __restrict__ out) {
   const int n = nc - 1;
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -485,6 +506,33 @@ __global__ void __launch_bounds__(256) k_mean(int nc, int i0, int i1, int j0, in
 
 // Gaussian log-likelihood (product of noise densities, Section 1.2):
 // -sum (y - Hu)^2 / (2 sigma^2), optionally - n_y log(sigma sqrt(2 pi)).
+// Log-likelihood per sample over its own observations y[off[s] .. off[s+1])
+// with its own noise level sigma[s]; one block per sample, fixed order.
+__global__ void __launch_bounds__(256) k_loglik_ragged(const int* __restrict__ off, const double* __restrict__ hu,
+                                                       const double* __restrict__ y, const double* __restrict__ sigma,
+                                                       int normalized, double* __restrict__ out) {
+  __shared__ double part[256];
+  const int s = blockIdx.x;
+  const int i0 = off[s], i1 = off[s + 1];
+  double acc = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += 256) {
+    const double r = y[i] - hu[i];
+    acc += r * r;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double sg = sigma[s];
+    double v = -part[0] / (2.0 * sg * sg);
+    if (normalized) v -= (i1 - i0) * log(sg * sqrt(2.0 * M_PI));
+    out[s] = v;
+  }
+}
+
 __global__ void __launch_bounds__(256) k_loglik(int n_y, const double* __restrict__ hu, const double* __restrict__ y,
                                                 double sigma, int normalized, double* __restrict__ out) {
   __shared__ double part[256];
@@ -667,6 +715,19 @@ hipError_t launch_interface(int nc, int n_samples, const double* u, double* out,
 hipError_t launch_mean(int nc, int n_samples, int i0, int i1, int j0, int j1, const double* u, double* out,
                        hipStream_t st) {
   hipLaunchKernelGGL(k_mean, dim3(n_samples), dim3(256), 0, st, nc, i0, i1, j0, j1, u, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_points_ragged(int nc, int n_total, const double* xy, const int* smp, const double* u, double* out,
+                                hipStream_t st) {
+  if (n_total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_points_ragged, dim3(ceil_div(n_total, 128)), dim3(128), 0, st, nc, n_total, xy, smp, u, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_loglik_ragged(int n_samples, const int* off, const double* hu, const double* y, const double* sigma,
+                                int normalized, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_loglik_ragged, dim3(n_samples), dim3(256), 0, st, off, hu, y, sigma, normalized, out);
   return hipGetLastError();
 }
 

@@ -37,8 +37,13 @@ EXPORTED = [
     "hdd_error_estimate", "hdd_sync", "hdd_last_node", "hdd_destroy", "hdd_strerror",
     "hdd_plan_summary", "hdd_plan_node", "hdd_plan_level", "hdd_debug_node_schur",
     "hdd_timing_enable", "hdd_timing_get", "hdd_mfma_selftest", "hdd_debug_frame",
-    "hdd_timing_get_level",
+    "hdd_timing_get_level", "hdd_query_points_ragged", "hdd_loglik_ragged",
+    "hdd_server_create", "hdd_server_slots", "hdd_server_submit", "hdd_server_poll", "hdd_server_result",
+    "hdd_server_stats", "hdd_server_destroy",
 ]
+
+SERVER_MAX_MESHES = 8
+SERVER_MAX_POINTS = 256
 
 
 class HddOpts(ctypes.Structure):
@@ -46,6 +51,14 @@ class HddOpts(ctypes.Structure):
         ("n", ctypes.c_int32), ("leaf", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("fp64_top_levels", ctypes.c_int32), ("max_refine", ctypes.c_int32), ("flags", ctypes.c_int32),
         ("refine_tol", ctypes.c_double), ("reserved", ctypes.c_int32 * 8),
+    ]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [
+        ("n_meshes", ctypes.c_int32), ("n", ctypes.c_int32 * SERVER_MAX_MESHES),
+        ("leaf", ctypes.c_int32 * SERVER_MAX_MESHES), ("precision", ctypes.c_int32), ("slots", ctypes.c_int32),
+        ("hbm_budget", ctypes.c_double), ("reserved", ctypes.c_int32 * 8),
     ]
 
 
@@ -90,6 +103,15 @@ def _load() -> ctypes.CDLL:
         "hdd_debug_frame": [P, i32, i32, i32, P, ctypes.POINTER(i32)],
         "hdd_timing_get_level": [P, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                  ctypes.POINTER(dbl)],
+        "hdd_query_points_ragged": [P, P, P, P, i32],
+        "hdd_loglik_ragged": [P, P, P, P, P, i32, P, i32],
+        "hdd_server_create": [ctypes.POINTER(ServerOpts), P, ctypes.POINTER(P)],
+        "hdd_server_slots": [P, ctypes.POINTER(i32)],
+        "hdd_server_submit": [P, i32, P, i32, P, P, dbl, ctypes.POINTER(i64)],
+        "hdd_server_poll": [P, i64, ctypes.POINTER(i32)],
+        "hdd_server_result": [P, i64, P, ctypes.POINTER(dbl), P],
+        "hdd_server_stats": [P, P],
+        "hdd_server_destroy": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -168,6 +190,14 @@ def _ptr(x):
         assert x.is_contiguous()
         return ctypes.c_void_p(x.data_ptr()), HDD_MEM_DEVICE
     return _np_ptr(x), HDD_MEM_HOST
+
+
+def _ragged(xy_per_sample, n_samples: int):
+    assert len(xy_per_sample) == n_samples
+    parts = [np.asarray(a, dtype=np.float64).reshape(-1, 2) for a in xy_per_sample]
+    off = np.zeros(n_samples + 1, dtype=np.int32)
+    off[1:] = np.cumsum([len(p) for p in parts])
+    return off, np.ascontiguousarray(np.concatenate(parts))
 
 
 class HDD:
@@ -262,6 +292,25 @@ class HDD:
                "hdd_loglik")
         return out
 
+    def query_points_ragged(self, xy_per_sample):
+        """Values at sample-specific sites: xy_per_sample[s] is an [n_s, 2]
+        array for sample s; returns a list of arrays."""
+        off, xy = _ragged(xy_per_sample, self.n_samples)
+        res = np.zeros(int(off[-1]))
+        _check(_lib.hdd_query_points_ragged(self.h, _np_ptr(off), _np_ptr(xy), _np_ptr(res), HDD_MEM_HOST),
+               "hdd_query_points_ragged")
+        return [res[off[s]:off[s + 1]] for s in range(self.n_samples)]
+
+    def loglik_ragged(self, xy_per_sample, y_per_sample, sigma, normalized: bool = False):
+        off, xy = _ragged(xy_per_sample, self.n_samples)
+        y = np.ascontiguousarray(np.concatenate([np.asarray(v, dtype=np.float64).ravel() for v in y_per_sample]))
+        assert len(y) == off[-1]
+        sg = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (self.n_samples,)))
+        res = np.zeros(self.n_samples)
+        _check(_lib.hdd_loglik_ragged(self.h, _np_ptr(off), _np_ptr(xy), _np_ptr(y), _np_ptr(sg), int(normalized),
+                                      _np_ptr(res), HDD_MEM_HOST), "hdd_loglik_ragged")
+        return res
+
     def solve_full(self, check: bool = True) -> int:
         code = _lib.hdd_solve_full(self.h)
         if check:
@@ -318,3 +367,74 @@ class HDD:
         if with_bytes:
             return ms.value, n.value, fl.value, by.value
         return ms.value, n.value, fl.value
+
+
+class Server:
+    """Continuous-batching likelihood server (hdd_server_* in include/hdd.h):
+    one HDD handle, stream and worker thread per mesh size."""
+
+    def __init__(self, meshes, precision: int = HDD_FP32_REFINE, slots: int = 0, hbm_budget: float = 0.0,
+                 leaves=None, f=None):
+        o = ServerOpts()
+        o.n_meshes = len(meshes)
+        for i, n in enumerate(meshes):
+            o.n[i] = int(n)
+            o.leaf[i] = int(leaves[i]) if leaves else 0
+        o.precision = int(precision)
+        o.slots = int(slots)
+        o.hbm_budget = float(hbm_budget)
+        self.meshes = list(meshes)
+        self._f = None
+        fp = None
+        if f is not None:
+            self._f = [np.ascontiguousarray(a, dtype=np.float64) for a in f]
+            arr = (ctypes.c_void_p * len(self._f))(*[a.ctypes.data for a in self._f])
+            fp = ctypes.cast(arr, ctypes.c_void_p)
+        h = ctypes.c_void_p()
+        _check(_lib.hdd_server_create(ctypes.byref(o), fp, ctypes.byref(h)), "hdd_server_create")
+        self.h = h
+        sl = ctypes.c_int32(0)
+        _check(_lib.hdd_server_slots(self.h, ctypes.byref(sl)), "hdd_server_slots")
+        self.slots = sl.value
+
+    def submit(self, mesh: int, kappa, xy, y=None, sigma: float = 1.0) -> int:
+        kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        yp = None
+        if y is not None:
+            y = np.ascontiguousarray(y, dtype=np.float64)
+            yp = _np_ptr(y)
+        rid = ctypes.c_int64(0)
+        _check(_lib.hdd_server_submit(self.h, int(mesh), _np_ptr(kappa), len(xy), _np_ptr(xy), yp, float(sigma),
+                                      ctypes.byref(rid)), "hdd_server_submit")
+        return rid.value
+
+    def poll(self, rid: int) -> bool:
+        d = ctypes.c_int32(0)
+        _check(_lib.hdd_server_poll(self.h, int(rid), ctypes.byref(d)), "hdd_server_poll")
+        return bool(d.value)
+
+    def result(self, rid: int, n_pts: int):
+        """(values [n_pts], loglik, times [queue, batch, total seconds, batch size])."""
+        vals = np.zeros(n_pts)
+        ll = ctypes.c_double(0)
+        times = np.zeros(4)
+        _check(_lib.hdd_server_result(self.h, int(rid), _np_ptr(vals), ctypes.byref(ll), _np_ptr(times)),
+               "hdd_server_result")
+        return vals, ll.value, times
+
+    def stats(self):
+        out = np.zeros(4, dtype=np.int64)
+        _check(_lib.hdd_server_stats(self.h, _np_ptr(out)), "hdd_server_stats")
+        return dict(submitted=int(out[0]), completed=int(out[1]), batches=int(out[2]), queued=int(out[3]))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.hdd_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
