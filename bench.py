@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-steps", type=int, default=1, help="extra steps with per-kernel event timing")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-mix measurement")
+    ap.add_argument("--serve-requests", type=int, default=96, help="requests per arrival rate in the serving mix")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run 3 device-to-device copies of BYTES (calibrates HBM byte counters) and exit")
     return ap.parse_args()
@@ -84,6 +86,61 @@ def cpu_baseline(w, seconds: float):
                       f"(sample 0), {t:.1f} s, scaled by column count to {t_full:.0f} s per solve; "
                       f"triangular solves and refinement (O(N^3)) not included",
             "host": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
+
+
+def serving_mix(H, n_req: int, seed: int = 7):
+    """Serving mix: each request draws its mesh uniformly from 127^2, 255^2 and
+    511^2 interior nodes (16x16 leaves, 20-mode log-normal kappa, corr 0.1,
+    var 1) and 1-32 uniform observation sites; arrivals are Poisson at 0.5,
+    0.8 and 1.0 times the saturated throughput measured first with a burst.
+    Latency is submit-to-result as measured by the server.  Parameter
+    samples come from a pre-drawn pool per mesh so the client stays off the
+    critical path."""
+    import threading
+
+    from workload import make_workload
+
+    names = ["s_127", "s_255", "s_511"]
+    pool = {m: make_workload(m, n_samples=16) for m in names}
+    srv = H.Server([pool[m].n for m in names], H.HDD_FP32_REFINE, slots=32,
+                   leaves=[pool[m].leaf for m in names], f=[pool[m].f for m in names])
+    rng = np.random.default_rng(seed)
+
+    def draw():
+        m = int(rng.integers(0, 3))
+        w = pool[names[m]]
+        xy = rng.uniform(size=(int(rng.integers(1, 33)), 2))
+        return m, w.kappa[int(rng.integers(0, 16))], xy
+
+    def run(rate):
+        reqs = [draw() for _ in range(n_req)]
+        # Poisson arrivals on an absolute schedule (no drift from the client)
+        at = np.cumsum(rng.exponential(1.0 / rate, size=n_req)) if rate else np.zeros(n_req)
+        ids = []
+        t0 = time.perf_counter()
+        for k, (m, kap, xy) in enumerate(reqs):
+            wait = t0 + at[k] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            ids.append((srv.submit(m, kap, xy), len(xy)))
+        t_sub = time.perf_counter() - t0
+        lat = []
+        for i, n in ids:
+            _, _, tm = srv.result(i, n)
+            lat.append(tm[2])
+        dt = time.perf_counter() - t0
+        lat = np.array(lat) * 1e3
+        return {"target_rps": rate, "offered_rps": n_req / t_sub if t_sub > 0 else None,
+                "throughput_rps": n_req / dt, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "requests": n_req}
+
+    run(0)  # warm up every mesh
+    burst = run(0)
+    sat = burst["throughput_rps"]
+    out = {"mix": "127^2/255^2/511^2 uniform, 1-32 sites, FP32+refinement", "slots_per_mesh": srv.slots,
+           "saturated_rps": sat, "rates": [run(f * sat) for f in (0.5, 0.8, 1.0)], "stats": srv.stats()}
+    srv.close()
+    return out
 
 
 def main():
@@ -214,6 +271,7 @@ def main():
                       "value": cs / cdt, "unit": "likelihood evals/s", "ms_per_eval": 1e3 * cdt / cs}
         c.close()
 
+    serving = None if a.no_serve else serving_mix(H, a.serve_requests)
     cpu = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
 
     lat_ms = sorted(1e3 * x for x in lat)
@@ -242,6 +300,7 @@ def main():
         "kernels_ms_per_step": {k: v["ms"] for k, v in kern.items()},
         "kernels_tflops": {k: v["tflops"] for k, v in kern.items() if v["tflops"]},
         "comparator": comparator,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
