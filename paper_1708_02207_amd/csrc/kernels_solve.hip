@@ -57,6 +57,7 @@ __device__ __forceinline__ double bcast(double v, int l) {
 template <typename T>
 __device__ __forceinline__ double diag_back(const T* D, int ld, int nb, double v) {
   const int lane = threadIdx.x & 63;
+  const double rinv = 1.0 / double(D[(long long)min(lane, nb - 1) * (ld + 1)]);  // lane j: 1 / L_jj
   for (int j0 = ((nb - 1) >> 4) << 4; j0 >= 0; j0 -= 16) {
     T c[16];
 #pragma unroll
@@ -68,7 +69,7 @@ __device__ __forceinline__ double diag_back(const T* D, int ld, int nb, double v
     for (int q = 15; q >= 0; --q) {
       const int j = j0 + q;
       if (j < nb) {
-        const double xj = bcast(v / double(c[q]), j);
+        const double xj = bcast(v * rinv, j);
         if (lane == j) v = xj;
         else if (lane < j) v -= double(c[q]) * xj;
       }
@@ -80,6 +81,7 @@ __device__ __forceinline__ double diag_back(const T* D, int ld, int nb, double v
 template <typename T>
 __device__ __forceinline__ double diag_forward(const T* D, int ld, int nb, double v) {
   const int lane = threadIdx.x & 63;
+  const double rinv = 1.0 / double(D[(long long)min(lane, nb - 1) * (ld + 1)]);  // lane j: 1 / L_jj
   for (int j0 = 0; j0 < nb; j0 += 16) {
     T c[16];
 #pragma unroll
@@ -91,7 +93,7 @@ __device__ __forceinline__ double diag_forward(const T* D, int ld, int nb, doubl
     for (int q = 0; q < 16; ++q) {
       const int j = j0 + q;
       if (j < nb) {
-        const double zj = bcast(v / double(c[q]), j);
+        const double zj = bcast(v * rinv, j);
         if (lane == j) v = zj;
         else if (lane > j) v -= double(c[q]) * zj;
       }
@@ -138,6 +140,72 @@ __device__ __forceinline__ void rows_dot(const T* F, int ld, int r0, int r1, int
       const int r = rb + q * step + sub;
       if (c == 0 && r < r1) fn(r, v);
     }
+  }
+}
+
+// Same product for nc <= 64 columns by a single wave through an LDS tile
+// (64 rows x 65): 64 rows are read with lanes over the columns (coalesced)
+// into tile[row][col], then each lane sums its own row against x, so no
+// cross-lane reduction is needed.  The tile is private to the wave (LDS
+// operations of one wave complete in order).
+template <typename T, typename Fn>
+__device__ __forceinline__ void rows_dot_wave64(const T* F, int ld, int r0, int r1, int c0, int nc, const double* x,
+                                                T* tile, Fn&& fn) {
+  const int lane = threadIdx.x & 63;
+  const int cl = min(lane, nc - 1);
+  const bool cok = lane < nc;
+  for (int rb = r0; rb < r1; rb += 64) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      T v[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int r = min(rb + b * 16 + q, r1 - 1);
+        v[q] = F[(long long)r * ld + c0 + cl];
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) tile[(b * 16 + q) * 65 + lane] = cok ? v[q] : T(0);
+    }
+    double acc = 0.0;
+    const T* row = tile + lane * 65;
+#pragma unroll 16
+    for (int c = 0; c < nc; ++c) acc += double(row[c]) * x[c];
+    if (rb + lane < r1) fn(rb + lane, acc);
+  }
+}
+
+// General form for one wave: TR rows per tile, any number of columns (in
+// chunks of 64).  tile: TR x 65 elements private to the wave.
+template <typename T, int TR, typename Fn>
+__device__ __forceinline__ void rows_dot_tile(const T* F, int ld, int r0, int r1, int c0, int nc, const double* x,
+                                              T* tile, Fn&& fn) {
+  static_assert(TR % 16 == 0 && TR <= 64, "tile rows");
+  const int lane = threadIdx.x & 63;
+  for (int rb = r0; rb < r1; rb += TR) {
+    double acc = 0.0;
+    for (int cb = 0; cb < nc; cb += 64) {
+      const int cl = cb + lane;
+      const bool cok = cl < nc;
+      const int cc = c0 + min(cl, nc - 1);
+#pragma unroll
+      for (int b = 0; b < TR / 16; ++b) {
+        T v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int r = min(rb + b * 16 + q, r1 - 1);
+          v[q] = F[(long long)r * ld + cc];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) tile[(b * 16 + q) * 65 + lane] = cok ? v[q] : T(0);
+      }
+      if (lane < TR) {
+        const T* row = tile + lane * 65;
+        const int m = min(64, nc - cb);
+#pragma unroll 16
+        for (int c = 0; c < m; ++c) acc += double(row[c]) * x[cb + c];
+      }
+    }
+    if (lane < TR && rb + lane < r1) fn(rb + lane, acc);
   }
 }
 
@@ -305,6 +373,9 @@ __global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int n_sa
   double* out = L.vec + (long long)s * L.vec_stride + nd.ids_off;
   if (defer_gemv) {
     for (int j = tid; j < G; j += BS) out[g + j] = gt[g + j];
+  } else if constexpr (BS == 64) {
+    T* tile = reinterpret_cast<T*>(dyn + (L.max_U + 1));  // 64 x 65
+    if (G > 0) rows_dot_wave64<T>(F, ld, g, g + G, 0, g, gt, tile, [&](int r, double y) { out[r] = gt[r] - y; });
   } else {
     rows_dot<T, BS>(F, ld, g, g + G, 0, g, gt, [&](int r, double y) { out[r] = gt[r] - y; });
   }
@@ -326,9 +397,14 @@ __global__ void __launch_bounds__(256) k_forward_gemv(DevLevel L, int n_samples)
   const T* F = frame_ptr<T>(L, node, s);
   double* out = L.vec + (long long)s * L.vec_stride + nd.ids_off;
   double* z = dyn;
+  T* tile = reinterpret_cast<T*>(dyn + g) + (threadIdx.x >> 6) * 32 * 65;  // per wave 32 x 65
   for (int i = threadIdx.x; i < g; i += 256) z[i] = out[i];
   __syncthreads();
-  rows_dot<T, 256>(F, ld, g + j0, g + min(G, j0 + 128), 0, g, z, [&](int r, double y) { out[r] -= y; });
+  // wave w takes rows j0 + 32 w .. j0 + 32 w + 31 of the chunk
+  const int rw = g + j0 + (threadIdx.x >> 6) * 32;
+  const int re = g + min(G, j0 + 128);
+  if (rw < re)
+    rows_dot_tile<T, 32>(F, ld, rw, min(rw + 32, re), 0, g, z, tile, [&](int r, double y) { out[r] -= y; });
 }
 
 // ---------------------------------------------------------------------------
@@ -651,7 +727,8 @@ hipError_t launch_forward(const DevLevel& L, const DevLevel& child, int n_sample
     else
       hipLaunchKernelGGL((k_forward<float, 1024>), grid, dim3(1024), lds, st, L, child, n_samples, split);
   } else if (L.gam <= 64) {
-    const size_t lds = solve_lds(L.max_U, L.gam, 64);
+    const size_t tile = size_t(64) * 65 * (L.is_double ? 8 : 4);
+    const size_t lds = sizeof(double) * size_t(L.max_U + 1) + tile;
     if (L.is_double)
       hipLaunchKernelGGL((k_forward<double, 64>), grid, dim3(64), lds, st, L, child, n_samples, split);
     else
@@ -666,7 +743,7 @@ hipError_t launch_forward(const DevLevel& L, const DevLevel& child, int n_sample
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !split) return e;
   dim3 g2(L.n_nodes * n_samples, ceil_div((L.max_U - L.gam), 128));
-  const size_t lds = sizeof(double) * size_t(L.gam);
+  const size_t lds = sizeof(double) * size_t(L.gam) + size_t(4) * 32 * 65 * (L.is_double ? 8 : 4);
   if (L.is_double)
     hipLaunchKernelGGL(k_forward_gemv<double>, g2, dim3(256), lds, st, L, n_samples);
   else
