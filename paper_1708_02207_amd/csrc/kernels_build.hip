@@ -462,6 +462,25 @@ __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[x][y][v] = 0.f;
+  // epilogue reads of accumulator tile q = 2 x + y (issued ahead of use)
+  auto load_old = [&](int q, float* o) {
+    const int x = q >> 1, y = q & 1;
+    const int ib = i0 + wr * 64 + x * 32 + (lane >> 5) * 4;
+    const int j = j0 + wc * 64 + y * 32 + (lane & 31);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) o[v] = syrk_old(F, ld, U, ib + (v >> 2) * 8 + (v & 3), j);
+  };
+  auto store_new = [&](int q, const float* o, const floatx16& c) {
+    const int x = q >> 1, y = q & 1;
+    const int ib = i0 + wr * 64 + x * 32 + (lane >> 5) * 4;
+    const int j = j0 + wc * 64 + y * 32 + (lane & 31);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = ib + (v >> 2) * 8 + (v & 3);
+      if (syrk_in(U, i, j, a, c1e)) F[(long long)i * ld + j] = o[v] - c[v];
+    }
+  };
+  float o0[16], o1[16];
   load(a.k0);
   store(0);
   __syncthreads();
@@ -469,6 +488,7 @@ __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int
   for (int kb = a.k0; kb < a.k1; kb += KC) {
     const bool more = kb + KC < a.k1;  // uniform
     if (more) load(kb + KC);
+    else load_old(0, o0);  // last chunk: the first epilogue reads overlap its MFMAs
 #pragma unroll
     for (int kk = 0; kk < KC; kk += 2) {
       float av[2], bv[2];
@@ -485,22 +505,15 @@ __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int
     __syncthreads();
     buf ^= 1;
   }
-  // one 32 x 32 accumulator at a time: its 16 reads are issued together
-#pragma unroll
-  for (int x = 0; x < 2; ++x)
-#pragma unroll
-    for (int y = 0; y < 2; ++y) {
-      const int ib = i0 + wr * 64 + x * 32 + (lane >> 5) * 4;
-      const int j = j0 + wc * 64 + y * 32 + (lane & 31);
-      float old[16];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) old[v] = syrk_old(F, ld, U, ib + (v >> 2) * 8 + (v & 3), j);
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int i = ib + (v >> 2) * 8 + (v & 3);
-        if (syrk_in(U, i, j, a, c1e)) F[(long long)i * ld + j] = old[v] - acc[x][y][v];
-      }
-    }
+  // epilogue, software pipelined: reads of the next accumulator tile are in
+  // flight while the current one is written
+  load_old(1, o1);
+  store_new(0, o0, acc[0][0]);
+  load_old(2, o0);
+  store_new(1, o1, acc[0][1]);
+  load_old(3, o1);
+  store_new(2, o0, acc[1][0]);
+  store_new(3, o1, acc[1][1]);
 }
 
 // ---------------------------------------------------------------------------
