@@ -19,11 +19,14 @@
 //  k_block_forward   bottom-up propagation of a new load (the residual of the
 //                    refinement) through the block's factors.
 #include <algorithm>
+#include <type_traits>
 
 #include "device.hpp"
 #include "kernels.hpp"
 
 namespace hdd {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 __constant__ int c_mb_local[3][3] = {  // micro-block local node (a, b) -> frame index
     {1, 2, 3},
@@ -152,7 +155,38 @@ __device__ __forceinline__ void build_level(const DevBlocks& B, T* cur, const T*
   crout_columns<T, L, 0>(cur, dg, bad_pivot);
   // Schur update of the boundary block and the load row (rank-g, eq.
   // SchurC1): S[i][l] -= sum_k P[i][k] P[l][k], g <= l <= i <= U.
-  {
+  if constexpr (std::is_same<T, float>::value && g >= 7) {
+    // matrix cores: 32 x 32 tiles of the lower triangle, one wave per tile,
+    // K = g padded to even with zeros; P read from the frame in LDS
+    constexpr int nr = L::U + 1 - g;
+    constexpr int nt = (nr + 31) / 32;
+    constexpr int tiles = L::n * nt * (nt + 1) / 2;
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int q = wv; q < tiles; q += NB / 64) {
+      const int t = q / (nt * (nt + 1) / 2), tq = q % (nt * (nt + 1) / 2);
+      const int ti = tri_row(tq), tj = tq - ti * (ti + 1) / 2;
+      T* F = cur + t * L::fsz;
+      const int ra = g + ti * 32 + (lane & 31), rb = g + tj * 32 + (lane & 31);
+      const T* pa = F + min(ra, L::U) * ld;
+      const T* pb = F + min(rb, L::U) * ld;
+      floatx16 acc;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+#pragma unroll
+      for (int kk = 0; kk < g; kk += 2) {
+        const int k = kk + (lane >> 5);
+        const float av = (k < g && ra <= L::U) ? pa[k] : 0.f;
+        const float bv = (k < g && rb <= L::U) ? pb[k] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+      }
+      const int l = g + tj * 32 + (lane & 31);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int i = g + ti * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        if (i <= L::U && l <= i) F[i * ld + l] -= acc[v];
+      }
+    }
+  } else {
     constexpr int nr = L::U + 1 - g;
     for (int e = tid; e < L::n * nr * nr; e += NB) {
       const int t = e / (nr * nr), p = e % (nr * nr);
