@@ -126,11 +126,19 @@ __device__ __forceinline__ void build_level(const DevBlocks& B, T* cur, const T*
   using L = Lv<S, K>;
   const int tid = threadIdx.x;
   constexpr int NB = NTB;
+  // the next (upper) level's extend-add maps are loaded into registers here
+  // and written to idx after this level's extend-add, hiding their latency
+  constexpr int NN = (K > 0) ? Lv<S, (K > 0 ? K - 1 : 0)>::n * 2 * Lv<S, (K > 0 ? K - 1 : 0)>::ld : 1;
+  constexpr int NP = (NN + NB - 1) / NB;
+  int pre[NP];
+  if constexpr (K > 0) {
+    const int* src = B.maps + B.lv[K - 1].map_off;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) pre[j] = src[min(tid + NB * j, NN - 1)];
+  }
   if constexpr (K < L::Lm) {
     using C = Lv<S, K + 1>;
-    stage_ints(idx, B.maps + B.lv[K].map_off, L::n * 2 * L::ld);
-    __syncthreads();
-    const int* maps = idx;
+    const int* maps = idx;  // this level's maps, staged by the level below
     for (int e = tid; e < L::n * L::ld * L::ld; e += NB) {
       const int t = e / (L::ld * L::ld), rc = e % (L::ld * L::ld);
       const int r = rc / L::ld, c = rc % L::ld;
@@ -147,6 +155,11 @@ __device__ __forceinline__ void build_level(const DevBlocks& B, T* cur, const T*
       cur[t * L::fsz + r * L::ldp + c] = v;
     }
     __syncthreads();
+  }
+  if constexpr (K > 0) {  // idx is free: this level's extend-add is done
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+      if (tid + NB * j < NN) idx[tid + NB * j] = pre[j];
   }
   // Partial Cholesky of the first gam columns (left-looking, column by
   // column): L_jj = sqrt(A_jj - sum_l L_jl^2), then every row below
@@ -362,8 +375,7 @@ __device__ __forceinline__ void topdown_level(const DevBlocks& B, const T* cst, 
   static_assert(L::n * g * P <= NT, "level GEMV does not fit the workgroup");
   const int tid = threadIdx.x;
   const T* base = cst + B.lv[K].cst_off;
-  stage_ints(idx, B.lids + B.lv[K].lid_off, L::n * U);
-  __syncthreads();
+  // idx holds this level's local ids (staged by the caller or the level above)
   const int* lids = idx;
   // rb = z - P^T u_Gamma: P lanes per entry, reduced by shuffles (the P lanes
   // of an entry are consecutive and P divides 64, so they share a wave)
@@ -380,6 +392,16 @@ __device__ __forceinline__ void topdown_level(const DevBlocks& B, const T* cst, 
     if (p == 0) rb[w] = (vz ? vz[B.lv[K].vec_off + w] : double(blk[U * g + i])) - acc;
   }
   __syncthreads();
+  // the next level's local ids are loaded into registers now, so their
+  // latency overlaps the triangular solves
+  constexpr int NN = (K < L::Lm) ? Lv<S, (K < L::Lm ? K + 1 : K)>::n * Lv<S, (K < L::Lm ? K + 1 : K)>::U : 1;
+  constexpr int NP = (NN + NT - 1) / NT;
+  int pre[NP];
+  if constexpr (K < L::Lm) {
+    const int* src = B.lids + B.lv[K + 1].lid_off;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) pre[j] = src[min(tid + NT * j, NN - 1)];
+  }
   // back substitution L^T x = rb, one node per group of g lanes
   {
     constexpr int GPW = Groups<g>::per_wave;
@@ -403,6 +425,12 @@ __device__ __forceinline__ void topdown_level(const DevBlocks& B, const T* cst, 
     }
   }
   __syncthreads();
+  if constexpr (K < L::Lm) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+      if (tid + NT * j < NN) idx[tid + NT * j] = pre[j];
+    __syncthreads();
+  }
 }
 
 template <typename T, int S, int K>
@@ -429,6 +457,7 @@ __global__ void __launch_bounds__(NT) k_block_topdown(DevBlocks B, const int* __
   double* us = u + (long long)s * ustride;
   stage_factors<T>(cs, cst_block<T>(B, q, s), B.cst_size);
   for (int e = tid; e < S1 * S1; e += NT) uL[e] = us[(long long)(Y0 + e / S1) * (nc + 1) + X0 + e % S1];
+  stage_ints(idx, B.lids + B.lv[0].lid_off, Lv<S, 0>::n * Lv<S, 0>::U);
   __syncthreads();
   const double* vz = from_vec ? B.vec + (long long)s * B.vec_stride + (long long)q * B.vec_size : nullptr;
   topdown_levels<T, S, 0>(B, cs, vz, uL, rb, idx);
@@ -447,11 +476,19 @@ __device__ __forceinline__ void forward_level(const DevBlocks& B, const T* cst, 
   using L = Lv<S, K>;
   constexpr int g = L::gam, U = L::U;
   const int tid = threadIdx.x;
+  // the next (upper) level's extend-add maps are loaded into registers now
+  // and written to idx once this level no longer needs it
+  constexpr int NN = (K > 0) ? Lv<S, (K > 0 ? K - 1 : 0)>::n * 2 * (Lv<S, (K > 0 ? K - 1 : 0)>::U + 1) : 1;
+  constexpr int NP = (NN + NT - 1) / NT;
+  int pre[NP];
+  if constexpr (K > 0) {
+    const int* src = B.maps + B.lv[K - 1].map_off;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) pre[j] = src[min(tid + NT * j, NN - 1)];
+  }
   if constexpr (K < L::Lm) {
     using C = Lv<S, K + 1>;
-    stage_ints(idx, B.maps + B.lv[K].map_off, L::n * 2 * (U + 1));
-    __syncthreads();
-    const int* maps = idx;
+    const int* maps = idx;  // this level's maps, staged by the level below
     for (int e = tid; e < L::n * U; e += NT) {
       const int t = e / U, i = e % U;
       const int* mA = maps + t * 2 * (U + 1);
@@ -488,6 +525,11 @@ __device__ __forceinline__ void forward_level(const DevBlocks& B, const T* cst, 
         vz[B.lv[K].vec_off + t * g + i] = v;
       }
     }
+  }
+  if constexpr (K > 0) {  // idx is free: this level's extend-add is done
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+      if (tid + NT * j < NN) idx[tid + NT * j] = pre[j];
   }
   __syncthreads();
   for (int e = tid; e < L::n * L::bnd; e += NT) {  // g_omega = g_Gamma - P z
