@@ -64,6 +64,54 @@ template <int S, int K> constexpr int idx_max_from() {
 }
 template <int S> constexpr int kIdxMax = idx_max_from<S, 0>();
 
+// Extend-add gather table of the build kernel.  Every block shares the
+// sub-tree, so the LDS addresses of the extend-add are the same for all of
+// them: entry e of level K (K above the micro level) names one lower-triangle
+// element (t, r, c) of the level's frames and the two son elements merged into
+// it, as element offsets from the start of the kernel's LDS frame buffers:
+// x = dst | a << 16, y = b, with a (b) the son-A (son-B) element or the zero
+// slot 2 * max_buf when the row or column is not in that son (Section 2.4,
+// eq. S_omega).  Level K's frames live in buffer (Lm - K) & 1.
+template <int S, int K> constexpr int ext_count() {
+  using L = Lv<S, K>;
+  return (K < L::Lm) ? L::n * L::ld * (L::ld + 1) / 2 : 0;
+}
+template <int S, int K> constexpr int ext_off() {
+  if constexpr (K == 0) return 0;
+  else return ext_off<S, K - 1>() + ext_count<S, K - 1>();
+}
+template <int S> constexpr int ext_total() { return ext_off<S, Lv<S, 0>::Lm>(); }
+
+template <int S, int K>
+__device__ __forceinline__ void ext_entry(const DevBlocks& B, int e, uint2* out) {
+  using L = Lv<S, K>;
+  if constexpr (K < L::Lm) {
+    if (e >= ext_count<S, K>()) {
+      ext_entry<S, K + 1>(B, e - ext_count<S, K>(), out);
+      return;
+    }
+    using C = Lv<S, K + 1>;
+    constexpr int tri = L::ld * (L::ld + 1) / 2;
+    const int t = e / tri, rc = e % tri;
+    const int r = tri_row(rc), c = rc - r * (r + 1) / 2;
+    const int zero = 2 * B.max_buf;
+    const int cur = ((L::Lm - K) & 1) * B.max_buf, prev = ((L::Lm - K + 1) & 1) * B.max_buf;
+    const int* mA = B.maps + B.lv[K].map_off + t * 2 * L::ld;
+    const int* mB = mA + L::ld;
+    const int sa = prev + (2 * t) * C::fsz + C::gam * C::ldp + C::gam, sb = sa + C::fsz;
+    const int ar = mA[r], ac = mA[c], br = mB[r], bc = mB[c];
+    const int a = (ar >= 0 && ac >= 0) ? sa + max(ar, ac) * C::ldp + min(ar, ac) : zero;
+    const int b = (br >= 0 && bc >= 0) ? sb + max(br, bc) * C::ldp + min(br, bc) : zero;
+    const int dst = cur + t * L::fsz + r * L::ldp + c;
+    out[ext_off<S, K>() + e] = make_uint2(unsigned(dst) | (unsigned(a) << 16), unsigned(b));
+  }
+}
+
+template <int S> __global__ void k_block_ext(DevBlocks B, uint2* __restrict__ ext) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ext_total<S>()) ext_entry<S, 0>(B, e, ext);
+}
+
 __device__ __forceinline__ void stage_ints(int* dst, const int* src, int n) {
   for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
 }
@@ -120,46 +168,30 @@ __device__ __forceinline__ void crout_columns(T* cur, T* dg, int& bad_pivot) {
 
 // ---------------------------------------------------------------------------
 // Build: one level (extend-add from the sons in `prev`, eliminate in `cur`).
+template <typename T, int S, int K> constexpr int ext_regs() {
+  return ext_count<S, K>() > 0 ? (ext_count<S, K>() + NTB - 1) / NTB : 1;
+}
+
+// Build: one level (extend-add from the sons in `prev`, eliminate in `cur`).
+// `tab` holds this thread's entries of the level's gather table, loaded into
+// registers while the level below was being eliminated.
 template <typename T, int S, int K>
-__device__ __forceinline__ void build_level(const DevBlocks& B, T* cur, const T* prev, T* cst, int* idx, T* dg,
-                                            int& bad_pivot) {
+__device__ __forceinline__ void build_level(T* base, T* cur, T* cst, const DevBlocks& B, T* dg, int& bad_pivot,
+                                            const uint2 (&tab)[ext_regs<T, S, K>()]) {
   using L = Lv<S, K>;
   const int tid = threadIdx.x;
   constexpr int NB = NTB;
-  // the next (upper) level's extend-add maps are loaded into registers here
-  // and written to idx after this level's extend-add, hiding their latency
-  constexpr int NN = (K > 0) ? Lv<S, (K > 0 ? K - 1 : 0)>::n * 2 * Lv<S, (K > 0 ? K - 1 : 0)>::ld : 1;
-  constexpr int NP = (NN + NB - 1) / NB;
-  int pre[NP];
-  if constexpr (K > 0) {
-    const int* src = B.maps + B.lv[K - 1].map_off;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) pre[j] = src[min(tid + NB * j, NN - 1)];
-  }
   if constexpr (K < L::Lm) {
-    using C = Lv<S, K + 1>;
-    const int* maps = idx;  // this level's maps, staged by the level below
-    for (int e = tid; e < L::n * L::ld * L::ld; e += NB) {
-      const int t = e / (L::ld * L::ld), rc = e % (L::ld * L::ld);
-      const int r = rc / L::ld, c = rc % L::ld;
-      if (c > r) continue;
-      const int* mA = maps + t * 2 * L::ld;
-      const int* mB = mA + L::ld;
-      const T* SA = prev + (2 * t) * C::fsz + C::gam * C::ldp + C::gam;
-      const T* SB = SA + C::fsz;
-      T v = T(0);
-      const int ar = mA[r], ac = mA[c];
-      if (ar >= 0 && ac >= 0) v += ar >= ac ? SA[ar * C::ldp + ac] : SA[ac * C::ldp + ar];
-      const int br = mB[r], bc = mB[c];
-      if (br >= 0 && bc >= 0) v += br >= bc ? SB[br * C::ldp + bc] : SB[bc * C::ldp + br];
-      cur[t * L::fsz + r * L::ldp + c] = v;
-    }
-    __syncthreads();
-  }
-  if constexpr (K > 0) {  // idx is free: this level's extend-add is done
+    // S_omega = S~_A + S~_B (eq. S_omega): all gathers of the thread, then
+    // all stores (the table's elements of one level never overlap)
+    constexpr int E = ext_count<S, K>(), NP = ext_regs<T, S, K>();
+    T v[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) v[j] = base[tab[j].x >> 16] + base[tab[j].y];
 #pragma unroll
     for (int j = 0; j < NP; ++j)
-      if (tid + NB * j < NN) idx[tid + NB * j] = pre[j];
+      if (j + 1 < NP || tid + NB * j < E) base[tab[j].x & 0xffffu] = v[j];
+    __syncthreads();
   }
   // Partial Cholesky of the first gam columns (left-looking, column by
   // column): L_jj = sqrt(A_jj - sum_l L_jl^2), then every row below
@@ -223,11 +255,28 @@ __device__ __forceinline__ void build_level(const DevBlocks& B, T* cur, const T*
   __syncthreads();
 }
 
+// Loads this thread's entries of level K's gather table.
 template <typename T, int S, int K>
-__device__ __forceinline__ void build_levels(const DevBlocks& B, T* cur, T* prev, T* cst, int* idx, T* dg,
-                                             int& bad_pivot) {
-  build_level<T, S, K>(B, cur, prev, cst, idx, dg, bad_pivot);
-  if constexpr (K > 0) build_levels<T, S, K - 1>(B, prev, cur, cst, idx, dg, bad_pivot);
+__device__ __forceinline__ void load_ext(const DevBlocks& B, uint2 (&tab)[ext_regs<T, S, K>()]) {
+  constexpr int E = ext_count<S, K>();
+  if constexpr (E > 0) {
+    const uint2* src = B.ext + ext_off<S, K>();
+#pragma unroll
+    for (int j = 0; j < ext_regs<T, S, K>(); ++j) tab[j] = src[min(int(threadIdx.x) + NTB * j, E - 1)];
+  }
+}
+
+template <typename T, int S, int K>
+__device__ __forceinline__ void build_levels(T* base, T* cur, T* prev, T* cst, const DevBlocks& B, T* dg,
+                                             int& bad_pivot, const uint2 (&tab)[ext_regs<T, S, K>()]) {
+  if constexpr (K > 0) {
+    uint2 nxt[ext_regs<T, S, K - 1>()];
+    load_ext<T, S, K - 1>(B, nxt);
+    build_level<T, S, K>(base, cur, cst, B, dg, bad_pivot, tab);
+    build_levels<T, S, K - 1>(base, prev, cur, cst, B, dg, bad_pivot, nxt);
+  } else {
+    build_level<T, S, K>(base, cur, cst, B, dg, bad_pivot, tab);
+  }
 }
 
 // Largest n * gam over the levels of a block (pivots recorded per column).
@@ -252,13 +301,18 @@ __global__ void __launch_bounds__(NTB) k_block_build(DevBlocks B, int n_samples,
   T* buf0 = reinterpret_cast<T*>(smem);
   T* buf1 = buf0 + B.max_buf;
   __shared__ int bad_pivot;
-  __shared__ int idx[kIdxMax<S>];
   __shared__ T dg[gam_nodes_from<S, 0>()];
   const int q = blockIdx.x / n_samples;
   const int s = blockIdx.x % n_samples;
   const int X0 = B.origin[2 * q], Y0 = B.origin[2 * q + 1];
   const int tid = threadIdx.x;
-  if (tid == 0) bad_pivot = 0;
+  // the first extend-add's gather entries are in flight during the assembly
+  uint2 first[ext_regs<T, S, (Lm > 0 ? Lm - 1 : 0)>()];
+  if constexpr (Lm > 0) load_ext<T, S, Lm - 1>(B, first);
+  if (tid == 0) {
+    bad_pivot = 0;
+    buf0[2 * B.max_buf] = T(0);  // zero slot of the gather table
+  }
   // The block's coefficients (S x S cells x 2 triangles) and nodal load
   // ((S+1)^2) are staged in the still unused second frame buffer.
   constexpr int S1 = S + 1;
@@ -315,7 +369,11 @@ __global__ void __launch_bounds__(NTB) k_block_build(DevBlocks B, int n_samples,
   __syncthreads();
   T* cst = cst_block<T>(B, q, s);
   int bp = 0;
-  build_levels<T, S, Lm>(B, buf0, buf1, cst, idx, dg, bp);
+  {
+    const uint2 none[1] = {make_uint2(0u, 0u)};
+    build_level<T, S, Lm>(buf0, buf0, cst, B, dg, bp, none);
+    if constexpr (Lm > 0) build_levels<T, S, Lm - 1>(buf0, buf1, buf0, cst, B, dg, bp, first);
+  }
   if (bp) bad_pivot = 1;
   __syncthreads();
   // block root frame -> global frame store (lower triangle)
@@ -595,7 +653,36 @@ __global__ void __launch_bounds__(NT) k_block_forward(DevBlocks B, int n_samples
 }
 
 // ---------------------------------------------------------------------------
-size_t block_build_lds(const DevBlocks& B, bool dbl) { return size_t(2) * B.max_buf * (dbl ? 8 : 4); }
+// two frame buffers and the gather table's zero slot
+size_t block_build_lds(const DevBlocks& B, bool dbl) { return (size_t(2) * B.max_buf + 2) * (dbl ? 8 : 4); }
+
+size_t block_ext_entries(int s) {
+  switch (s) {
+    case 2: return ext_total<2>();
+    case 4: return ext_total<4>();
+    case 8: return ext_total<8>();
+    case 16: return ext_total<16>();
+    default: return 0;
+  }
+}
+
+template <int S> static void launch_ext_t(const DevBlocks& B, uint2* ext, hipStream_t st) {
+  constexpr int n = ext_total<S>();
+  if (n > 0) hipLaunchKernelGGL((k_block_ext<S>), dim3((n + 255) / 256), dim3(256), 0, st, B, ext);
+}
+
+hipError_t launch_block_ext(const DevBlocks& B, uint2* ext, hipStream_t st) {
+  // every offset (and the zero slot) must fit the table's 16-bit fields
+  if (2 * B.max_buf >= 65536) return hipErrorInvalidValue;
+  switch (B.s) {
+    case 2: launch_ext_t<2>(B, ext, st); break;
+    case 4: launch_ext_t<4>(B, ext, st); break;
+    case 8: launch_ext_t<8>(B, ext, st); break;
+    case 16: launch_ext_t<16>(B, ext, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 static size_t stage_bytes(const DevBlocks& B, bool dbl) { return (size_t(B.cst_size) * (dbl ? 8 : 4) + 15) / 16 * 16; }
 
