@@ -10,14 +10,17 @@
 //  k_block_build     Section 3.1 (leaf assembly, eq. coefA, eq. coefc) and
 //                    Sections 2.4 / 3.3 (Schur elimination and merge of
 //                    sons) for every level of the block, bottom-up.  Frames
-//                    live in two ping-pong LDS buffers; each node's retained
-//                    columns [L ; P ; z] (the factored Phi of the node) go to
-//                    a compact HBM store; the block root's full frame (with
-//                    S_omega and g_omega) goes to the global frame store.
+//                    live in two ping-pong LDS buffers; from each node's
+//                    factored columns [L ; P ; z] the kernel forms the node's
+//                    local operators M = A_gg^-1, W = A_gg^-1 A_gG and
+//                    y = A_gg^-1 b_gamma and writes them to a compact HBM
+//                    store; the block root's full frame (with S_omega and
+//                    g_omega) goes to the global frame store.
 //  k_block_topdown   Root to Leaves inside the block (Section 3.4): from u on
-//                    the block boundary, solve every interface of the block.
+//                    the block boundary, every interface of the block, one
+//                    GEMV per level (u_gamma = y - W u_Gamma).
 //  k_block_forward   bottom-up propagation of a new load (the residual of the
-//                    refinement) through the block's factors.
+//                    refinement) through the block's operators.
 #include <algorithm>
 #include <type_traits>
 
@@ -49,20 +52,6 @@ template <int S, int K> struct Lv {
   static constexpr int per = ld * gam;            // compact elements per node
 };
 
-// Largest per-level index table (maps: n * 2 * (U+1), local ids: n * U).
-template <int S, int K> constexpr int idx_max_from() {
-  using L = Lv<S, K>;
-  constexpr int a = (K < L::Lm) ? L::n * 2 * L::ld : 0;
-  constexpr int b = L::n * L::U;
-  constexpr int m = a > b ? a : b;
-  if constexpr (K < L::Lm) {
-    constexpr int rest = idx_max_from<S, K + 1>();
-    return m > rest ? m : rest;
-  } else {
-    return m;
-  }
-}
-template <int S> constexpr int kIdxMax = idx_max_from<S, 0>();
 
 // Extend-add gather table of the build kernel.  Every block shares the
 // sub-tree, so the LDS addresses of the extend-add are the same for all of
@@ -107,17 +96,62 @@ __device__ __forceinline__ void ext_entry(const DevBlocks& B, int e, uint2* out)
   }
 }
 
+// Merge table of the forward sweep: entry e = t * U + i of level K adds the
+// sons' condensed loads, x = a, y = b as offsets from the start of the
+// kernel's two LDS value buffers (max_bnd_nodes each; level K's values live
+// in buffer (Lm - K) & 1), the zero slot 2 * max_bnd_nodes where row i is not
+// in that son.  Stored after the build's table.
+template <int S, int K> constexpr int fext_count() {
+  using L = Lv<S, K>;
+  return (K < L::Lm) ? L::n * L::U : 0;
+}
+template <int S, int K> constexpr int fext_off() {
+  if constexpr (K == 0) return 0;
+  else return fext_off<S, K - 1>() + fext_count<S, K - 1>();
+}
+template <int S> constexpr int fext_total() { return fext_off<S, Lv<S, 0>::Lm>(); }
+
+template <int S, int K>
+__device__ __forceinline__ void fext_entry(const DevBlocks& B, int e, uint2* out) {
+  using L = Lv<S, K>;
+  if constexpr (K < L::Lm) {
+    if (e >= fext_count<S, K>()) {
+      fext_entry<S, K + 1>(B, e - fext_count<S, K>(), out);
+      return;
+    }
+    using C = Lv<S, K + 1>;
+    const int t = e / L::U, i = e % L::U;
+    const int zero = 2 * B.max_bnd_nodes;
+    const int prev = ((L::Lm - K + 1) & 1) * B.max_bnd_nodes;
+    const int* mA = B.maps + B.lv[K].map_off + t * 2 * L::ld;
+    const int* mB = mA + L::ld;
+    const int a = mA[i] >= 0 ? prev + (2 * t) * C::U + C::gam + mA[i] : zero;
+    const int b = mB[i] >= 0 ? prev + (2 * t + 1) * C::U + C::gam + mB[i] : zero;
+    out[ext_total<S>() + fext_off<S, K>() + e] = make_uint2(unsigned(a), unsigned(b));
+  }
+}
+
 template <int S> __global__ void k_block_ext(DevBlocks B, uint2* __restrict__ ext) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < ext_total<S>()) ext_entry<S, 0>(B, e, ext);
+  else if (e < ext_total<S>() + fext_total<S>()) fext_entry<S, 0>(B, e - ext_total<S>(), ext);
 }
 
-__device__ __forceinline__ void stage_ints(int* dst, const int* src, int n) {
-  for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
-}
 
 template <typename T> __device__ __forceinline__ T* cst_block(const DevBlocks& B, int q, int s) {
   return reinterpret_cast<T*>(B.cst) + (long long)s * B.cst_stride + (long long)q * B.cst_size;
+}
+
+// Largest n * gam over the levels of a block (pivots recorded per column).
+template <int S, int K> constexpr int gam_nodes_from() {
+  using L = Lv<S, K>;
+  constexpr int m = L::n * L::gam;
+  if constexpr (K < L::Lm) {
+    constexpr int rest = gam_nodes_from<S, K + 1>();
+    return m > rest ? m : rest;
+  } else {
+    return m;
+  }
 }
 
 constexpr int NT = 256;   // threads of the top-down / forward kernels
@@ -133,7 +167,7 @@ constexpr int NTB = 512;  // threads of the build kernel
 // the diagonal after the last column.  Unrolled over the (compile-time)
 // columns so every inner loop has a fixed length.
 template <typename T, typename L, int J>
-__device__ __forceinline__ void crout_columns(T* cur, T* dg, int& bad_pivot) {
+__device__ __forceinline__ void crout_columns(T* cur, T* dg, T* rdg, int& bad_pivot) {
   if constexpr (J < L::gam) {
     constexpr int ld = L::ldp;
     constexpr int m = L::U + 1 - J;  // rows J .. U
@@ -156,11 +190,12 @@ __device__ __forceinline__ void crout_columns(T* cur, T* dg, int& bad_pivot) {
       }
     }
     __syncthreads();
-    crout_columns<T, L, J + 1>(cur, dg, bad_pivot);
+    crout_columns<T, L, J + 1>(cur, dg, rdg, bad_pivot);
   } else {
     for (int e = threadIdx.x; e < L::n * L::gam; e += NTB) {
       const int t = e / L::gam, j = e % L::gam;
       cur[t * L::fsz + j * L::ldp + j] = dg[e];
+      rdg[e] = T(1) / dg[e];
     }
     __syncthreads();
   }
@@ -197,7 +232,8 @@ __device__ __forceinline__ void build_level(T* base, T* cur, T* cst, const DevBl
   // column): L_jj = sqrt(A_jj - sum_l L_jl^2), then every row below
   // (interface, boundary and load rows) L_ij = (A_ij - sum_l L_il L_jl) / L_jj.
   constexpr int g = L::gam, ld = L::ldp;
-  crout_columns<T, L, 0>(cur, dg, bad_pivot);
+  T* rdg = dg + gam_nodes_from<S, 0>();
+  crout_columns<T, L, 0>(cur, dg, rdg, bad_pivot);
   // Schur update of the boundary block and the load row (rank-g, eq.
   // SchurC1): S[i][l] -= sum_k P[i][k] P[l][k], g <= l <= i <= U.
   if constexpr (std::is_same<T, float>::value && g >= 7) {
@@ -245,12 +281,41 @@ __device__ __forceinline__ void build_level(T* base, T* cur, T* cst, const DevBl
     }
   }
   __syncthreads();
-  // retained columns [L ; P ; z] of every node -> compact store
+  // Local operators of every node -> compact store, g values per row
+  // (Section 3.4: the interface values of a node follow from its boundary
+  // values and its load as u_gamma = A_gg^-1 (b_gamma - A_gG u_Gamma)):
+  //   rows 0 .. g-1   M = A_gg^-1, row c = L^-T L^-1 e_c
+  //   rows g .. U-1   W^T with W = A_gg^-1 A_gG, row j = L^-T p_j (p_j row j of P)
+  //   row  U          y = A_gg^-1 b_gamma = L^-T z
+  // One row per thread, both substitutions in registers.
   T* out = cst + B.lv[K].cst_off;
-  for (int e = tid; e < L::n * L::per; e += NB) {
-    const int t = e / L::per, rc = e % L::per;
-    const int r = rc / g, c = rc % g;
-    out[e] = (c <= r) ? cur[t * L::fsz + r * ld + c] : T(0);  // ld = physical stride here
+  for (int e = tid; e < L::n * L::ld; e += NB) {
+    const int t = e / L::ld, r = e % L::ld;
+    const T* F = cur + t * L::fsz;
+    const T* rd = rdg + t * g;
+    T w[g];
+    if (r < g) {
+#pragma unroll
+      for (int i = 0; i < g; ++i) {
+        T v = (i == r) ? T(1) : T(0);
+#pragma unroll
+        for (int l = 0; l < i; ++l) v -= F[i * ld + l] * w[l];
+        w[i] = v * rd[i];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < g; ++i) w[i] = F[r * ld + i];
+    }
+#pragma unroll
+    for (int i = g - 1; i >= 0; --i) {
+      T v = w[i];
+#pragma unroll
+      for (int l = i + 1; l < g; ++l) v -= F[l * ld + i] * w[l];
+      w[i] = v * rd[i];
+    }
+    T* o = out + t * L::per + r * g;
+#pragma unroll
+    for (int i = 0; i < g; ++i) o[i] = w[i];
   }
   __syncthreads();
 }
@@ -279,18 +344,6 @@ __device__ __forceinline__ void build_levels(T* base, T* cur, T* prev, T* cst, c
   }
 }
 
-// Largest n * gam over the levels of a block (pivots recorded per column).
-template <int S, int K> constexpr int gam_nodes_from() {
-  using L = Lv<S, K>;
-  constexpr int m = L::n * L::gam;
-  if constexpr (K < L::Lm) {
-    constexpr int rest = gam_nodes_from<S, K + 1>();
-    return m > rest ? m : rest;
-  } else {
-    return m;
-  }
-}
-
 template <typename T, int S>
 __global__ void __launch_bounds__(NTB) k_block_build(DevBlocks B, int n_samples, int nc,
                                                     const double* __restrict__ kappa, const double* __restrict__ f,
@@ -301,7 +354,7 @@ __global__ void __launch_bounds__(NTB) k_block_build(DevBlocks B, int n_samples,
   T* buf0 = reinterpret_cast<T*>(smem);
   T* buf1 = buf0 + B.max_buf;
   __shared__ int bad_pivot;
-  __shared__ T dg[gam_nodes_from<S, 0>()];
+  __shared__ T dg[2 * gam_nodes_from<S, 0>()];  // pivots, then their reciprocals
   const int q = blockIdx.x / n_samples;
   const int s = blockIdx.x % n_samples;
   const int X0 = B.origin[2 * q], Y0 = B.origin[2 * q + 1];
@@ -391,222 +444,233 @@ __global__ void __launch_bounds__(NTB) k_block_build(DevBlocks B, int n_samples,
 }
 
 // ---------------------------------------------------------------------------
-// Shared pieces of the block solves.
-//
-// Staging of a block's compact factors into LDS with 16-byte loads (the
-// per-block store is a multiple of 16 bytes whenever cst_size * sizeof(T) is).
-template <typename T>
-__device__ __forceinline__ void stage_factors(T* dst, const T* src, int n_elems) {
-  const int bytes = n_elems * int(sizeof(T));
-  if ((bytes & 15) == 0 && ((reinterpret_cast<uintptr_t>(src) & 15) == 0)) {
-    const uint4* s4 = reinterpret_cast<const uint4*>(src);
-    uint4* d4 = reinterpret_cast<uint4*>(dst);
-    for (int e = threadIdx.x; e < bytes / 16; e += NT) d4[e] = s4[e];
-  } else {
-    for (int e = threadIdx.x; e < n_elems; e += NT) dst[e] = src[e];
-  }
-}
+// Block solves.  Both run on the local operators the build leaves in the
+// compact store (M, W^T, y per node), so every level is one matrix-vector
+// product with no substitution chain.  Each thread's operator entries for
+// ALL levels are loaded from HBM into registers when the kernel starts; LDS
+// holds only the node values.
 
 // Lanes per dot product of a level's GEMV: the largest power of two (at most
-// 16) such that n * gam * P threads fit in the workgroup.
+// 16) such that work * P threads fit in the workgroup (1 if work > NT).
 constexpr int gemv_split(int work) {
   int p = 1;
   while (p < 16 && work * p * 2 <= NT) p *= 2;
   return p;
 }
 
-// The triangular solves of a level run one node per group of gam lanes,
-// floor(64 / gam) groups per wave, with the pivot values broadcast by shuffles.
-template <int G> struct Groups {
-  static constexpr int per_wave = 64 / G;
+// ---------------------------------------------------------------------------
+// Top-down (Root to Leaves inside the block, Section 3.4): from u on the
+// block boundary, every level's interfaces in one GEMV per node,
+//   u_gamma = y - W u_Gamma            (the build's load), or
+//   u_gamma = M g_gamma - W u_Gamma    (a load propagated by k_block_forward,
+//                                       g_gamma read from the vector store).
+// Thread (w = t * g + i, p) of a level sums the columns j = p (mod P).
+template <typename T, int S, int K> struct TdLevel {
+  using L = Lv<S, K>;
+  static constexpr int g = L::gam, nbd = L::bnd, U = L::U;
+  static constexpr int P = gemv_split(L::n * g);
+  static constexpr int NJ = (nbd + P - 1) / P;
+  static constexpr int NL = (g + P - 1) / P;
+  static constexpr int act = L::n * g * P;
+  static_assert(act <= NT, "level GEMV does not fit the workgroup");
 };
 
-// ---------------------------------------------------------------------------
-// Top-down: the block's compact factors are staged in LDS, u on the block's
-// (S+1)^2 nodes lives in LDS; levels are solved root first.
+template <typename T, int S, int K> struct TdRegs {
+  using C = TdLevel<T, S, K>;
+  T w[C::NJ];
+  int lj[C::NJ];
+  T m[C::NL];
+  double z[C::NL];
+  T y;
+  int li;
+};
+
+template <typename T, int S, int K, bool Last = (K == Lv<S, 0>::Lm)> struct TdAll;
+template <typename T, int S, int K> struct TdAll<T, S, K, true> {
+  TdRegs<T, S, K> r;
+};
+template <typename T, int S, int K> struct TdAll<T, S, K, false> {
+  TdRegs<T, S, K> r;
+  TdAll<T, S, K + 1> next;
+};
+
 template <typename T, int S, int K>
-__device__ __forceinline__ void topdown_level(const DevBlocks& B, const T* cst, const double* vz, double* uL,
-                                              double* rb, int* idx) {
+__device__ __forceinline__ void td_load(const DevBlocks& B, const T* cst, const double* vz, TdAll<T, S, K>& a) {
+  using C = TdLevel<T, S, K>;
   using L = Lv<S, K>;
-  constexpr int g = L::gam, U = L::U, nbd = L::bnd;
-  constexpr int P = gemv_split(L::n * g);
-  static_assert(L::n * g * P <= NT, "level GEMV does not fit the workgroup");
+  constexpr int g = C::g, P = C::P;
   const int tid = threadIdx.x;
-  const T* base = cst + B.lv[K].cst_off;
-  // idx holds this level's local ids (staged by the caller or the level above)
-  const int* lids = idx;
-  // rb = z - P^T u_Gamma: P lanes per entry, reduced by shuffles (the P lanes
-  // of an entry are consecutive and P divides 64, so they share a wave)
-  if (tid < L::n * g * P) {
-    const int w = tid / P, p = tid % P;
-    const int t = w / g, i = w % g;
-    const T* blk = base + t * L::per;
-    const int* lid = lids + t * U;
-    double acc = 0.0;
+  const int w = min(tid / P, L::n * g - 1);  // idle threads load a valid entry
+  const int p = tid % P;
+  const int t = w / g, i = w % g;
+  const T* blk = cst + B.lv[K].cst_off + t * L::per;
+  const int* lid = B.lids + B.lv[K].lid_off + t * C::U;
 #pragma unroll
-    for (int j = p; j < nbd; j += P) acc += double(blk[(g + j) * g + i]) * uL[lid[g + j]];
-#pragma unroll
-    for (int o = P / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (p == 0) rb[w] = (vz ? vz[B.lv[K].vec_off + w] : double(blk[U * g + i])) - acc;
+  for (int jj = 0; jj < C::NJ; ++jj) {
+    const int j = p + P * jj, jc = min(j, C::nbd - 1);
+    const T v = blk[(g + jc) * g + i];
+    a.r.w[jj] = j < C::nbd ? v : T(0);
+    a.r.lj[jj] = lid[g + jc];
   }
-  __syncthreads();
-  // the next level's local ids are loaded into registers now, so their
-  // latency overlaps the triangular solves
-  constexpr int NN = (K < L::Lm) ? Lv<S, (K < L::Lm ? K + 1 : K)>::n * Lv<S, (K < L::Lm ? K + 1 : K)>::U : 1;
-  constexpr int NP = (NN + NT - 1) / NT;
-  int pre[NP];
-  if constexpr (K < L::Lm) {
-    const int* src = B.lids + B.lv[K + 1].lid_off;
+  if (vz) {
+    const double* zt = vz + B.lv[K].vec_off + t * g;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) pre[j] = src[min(tid + NT * j, NN - 1)];
-  }
-  // back substitution L^T x = rb, one node per group of g lanes
-  {
-    constexpr int GPW = Groups<g>::per_wave;
-    constexpr int NW = (L::n + GPW - 1) / GPW;
-    static_assert(NW * 64 <= NT, "level solve does not fit the workgroup");
-    const int wv = tid >> 6, lane = tid & 63;
-    const int grp = lane / g, i = lane % g;
-    const int t = wv * GPW + grp;
-    const bool act = grp < GPW && t < L::n;
-    if (wv < NW) {
-      const T* blk = base + (act ? t : 0) * L::per;
-      const int gb = grp * g;
-      double v = act ? rb[t * g + i] : 0.0;
-#pragma unroll
-      for (int l = g - 1; l >= 0; --l) {
-        const double xl = __shfl(v, gb + l) / double(blk[l * g + l]);
-        if (i == l) v = xl;
-        else if (i < l) v -= double(blk[l * g + i]) * xl;
-      }
-      if (act) uL[lids[t * U + i]] = v;
+    for (int ll = 0; ll < C::NL; ++ll) {
+      const int l = p + P * ll, lc = min(l, g - 1);
+      const T v = blk[lc * g + i];
+      a.r.m[ll] = l < g ? v : T(0);
+      a.r.z[ll] = zt[lc];
     }
-  }
-  __syncthreads();
-  if constexpr (K < L::Lm) {
+    a.r.y = T(0);
+  } else {
 #pragma unroll
-    for (int j = 0; j < NP; ++j)
-      if (tid + NT * j < NN) idx[tid + NT * j] = pre[j];
-    __syncthreads();
+    for (int ll = 0; ll < C::NL; ++ll) {
+      a.r.m[ll] = T(0);
+      a.r.z[ll] = 0.0;
+    }
+    a.r.y = blk[C::U * g + i];
   }
+  a.r.li = lid[i];
+  if constexpr (K < L::Lm) td_load<T, S, K + 1>(B, cst, vz, a.next);
 }
 
 template <typename T, int S, int K>
-__device__ __forceinline__ void topdown_levels(const DevBlocks& B, const T* cst, const double* vz, double* uL,
-                                               double* rb, int* idx) {
-  topdown_level<T, S, K>(B, cst, vz, uL, rb, idx);
-  if constexpr (K < Lv<S, 0>::Lm) topdown_levels<T, S, K + 1>(B, cst, vz, uL, rb, idx);
+__device__ __forceinline__ void td_solve(const TdAll<T, S, K>& a, double* uL) {
+  using C = TdLevel<T, S, K>;
+  const int tid = threadIdx.x;
+  if (tid < C::act) {
+    const int p = tid % C::P;
+    double acc = p == 0 ? double(a.r.y) : 0.0;
+#pragma unroll
+    for (int ll = 0; ll < C::NL; ++ll) acc += double(a.r.m[ll]) * a.r.z[ll];
+#pragma unroll
+    for (int jj = 0; jj < C::NJ; ++jj) acc -= double(a.r.w[jj]) * uL[a.r.lj[jj]];
+    // the P lanes of an entry are consecutive and P divides 64
+#pragma unroll
+    for (int o = C::P / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (p == 0) uL[a.r.li] = acc;  // gamma of this node: read by no other node of the level
+  }
+  __syncthreads();
+  if constexpr (K < Lv<S, 0>::Lm) td_solve<T, S, K + 1>(a.next, uL);
 }
 
 template <typename T, int S>
 __global__ void __launch_bounds__(NT) k_block_topdown(DevBlocks B, const int* __restrict__ list, int n_samples,
                                                       int nc, double* __restrict__ u, long long ustride,
                                                       int from_vec) {
-  extern __shared__ __align__(16) unsigned char smem[];
   constexpr int S1 = S + 1;
-  T* cs = reinterpret_cast<T*>(smem);                                    // cst_size
-  double* uL = reinterpret_cast<double*>(smem + ((size_t(B.cst_size) * sizeof(T) + 15) / 16) * 16);
-  double* rb = uL + S1 * S1;                                             // max n * gam
-  __shared__ int idx[kIdxMax<S>];
+  __shared__ double uL[S1 * S1];
   const int q = list[blockIdx.x / n_samples];
   const int s = blockIdx.x % n_samples;
   const int X0 = B.origin[2 * q], Y0 = B.origin[2 * q + 1];
   const int tid = threadIdx.x;
   double* us = u + (long long)s * ustride;
-  stage_factors<T>(cs, cst_block<T>(B, q, s), B.cst_size);
-  for (int e = tid; e < S1 * S1; e += NT) uL[e] = us[(long long)(Y0 + e / S1) * (nc + 1) + X0 + e % S1];
-  stage_ints(idx, B.lids + B.lv[0].lid_off, Lv<S, 0>::n * Lv<S, 0>::U);
-  __syncthreads();
   const double* vz = from_vec ? B.vec + (long long)s * B.vec_stride + (long long)q * B.vec_size : nullptr;
-  topdown_levels<T, S, 0>(B, cs, vz, uL, rb, idx);
+  TdAll<T, S, 0> a;
+  td_load<T, S, 0>(B, cst_block<T>(B, q, s), vz, a);
+  for (int e = tid; e < S1 * S1; e += NT) uL[e] = us[(long long)(Y0 + e / S1) * (nc + 1) + X0 + e % S1];
+  __syncthreads();
+  td_solve<T, S, 0>(a, uL);
   constexpr int si = S - 1;
   for (int e = tid; e < si * si; e += NT) {
-    const int a = 1 + e % si, b = 1 + e / si;
-    us[(long long)(Y0 + b) * (nc + 1) + X0 + a] = uL[b * S1 + a];
+    const int a0 = 1 + e % si, b0 = 1 + e / si;
+    us[(long long)(Y0 + b0) * (nc + 1) + X0 + a0] = uL[b0 * S1 + a0];
   }
 }
 
 // ---------------------------------------------------------------------------
-// Forward: new load propagated bottom-up through the block's factors.
-template <typename T, int S, int K>
-__device__ __forceinline__ void forward_level(const DevBlocks& B, const T* cst, double* vz, double* cur,
-                                              const double* prev, int* idx) {
+// Forward: a new load (the refinement's residual) propagated bottom-up
+// through the block.  Per level: the sons' condensed loads are merged
+// (g = [g_gamma ; g_Gamma], eq. g_omega of Section 2.4, with the gather table
+// of k_block_ext), g_gamma goes to the block vector store for the top-down,
+// and the condensed load is g_omega = g_Gamma - W^T g_gamma.
+// Output j of a level is summed by P lanes, lane p taking i = p (mod P).
+template <typename T, int S, int K> struct FwLevel {
   using L = Lv<S, K>;
-  constexpr int g = L::gam, U = L::U;
+  static constexpr int g = L::gam, nbd = L::bnd, U = L::U;
+  static constexpr int P = gemv_split(L::n * nbd);
+  static constexpr int NI = (g + P - 1) / P;
+  static constexpr int R = (L::n * nbd * P + NT - 1) / NT;  // rounds of NT / P outputs
+  static constexpr int NE = (K < L::Lm) ? (L::n * U + NT - 1) / NT : 1;  // merge entries
+};
+
+template <typename T, int S, int K> struct FwRegs {
+  using C = FwLevel<T, S, K>;
+  T w[C::R][C::NI];
+  uint2 e[C::NE];
+};
+
+template <typename T, int S, int K, bool First = (K == 0)> struct FwAll;
+template <typename T, int S, int K> struct FwAll<T, S, K, true> {
+  FwRegs<T, S, K> r;
+};
+template <typename T, int S, int K> struct FwAll<T, S, K, false> {
+  FwRegs<T, S, K> r;
+  FwAll<T, S, K - 1> next;
+};
+
+
+template <typename T, int S, int K>
+__device__ __forceinline__ void fw_load(const DevBlocks& B, const T* cst, FwAll<T, S, K>& a) {
+  using C = FwLevel<T, S, K>;
+  using L = Lv<S, K>;
+  constexpr int g = C::g, P = C::P;
   const int tid = threadIdx.x;
-  // the next (upper) level's extend-add maps are loaded into registers now
-  // and written to idx once this level no longer needs it
-  constexpr int NN = (K > 0) ? Lv<S, (K > 0 ? K - 1 : 0)>::n * 2 * (Lv<S, (K > 0 ? K - 1 : 0)>::U + 1) : 1;
-  constexpr int NP = (NN + NT - 1) / NT;
-  int pre[NP];
-  if constexpr (K > 0) {
-    const int* src = B.maps + B.lv[K - 1].map_off;
+  const T* base = cst + B.lv[K].cst_off;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) pre[j] = src[min(tid + NT * j, NN - 1)];
+  for (int rr = 0; rr < C::R; ++rr) {
+    const int o = min(tid / P + rr * (NT / P), L::n * C::nbd - 1);
+    const int p = tid % P;
+    const int t = o / C::nbd, j = o % C::nbd;
+    const T* row = base + t * L::per + (g + j) * g;
+#pragma unroll
+    for (int ii = 0; ii < C::NI; ++ii) {
+      const int i = p + P * ii;
+      const T v = row[min(i, g - 1)];
+      a.r.w[rr][ii] = i < g ? v : T(0);
+    }
   }
   if constexpr (K < L::Lm) {
-    using C = Lv<S, K + 1>;
-    const int* maps = idx;  // this level's maps, staged by the level below
-    for (int e = tid; e < L::n * U; e += NT) {
-      const int t = e / U, i = e % U;
-      const int* mA = maps + t * 2 * (U + 1);
-      const int* mB = mA + (U + 1);
-      double v = 0.0;
-      if (mA[i] >= 0) v += prev[(2 * t) * C::U + C::gam + mA[i]];
-      if (mB[i] >= 0) v += prev[(2 * t + 1) * C::U + C::gam + mB[i]];
-      cur[e] = v;
-    }
-    __syncthreads();
-  }
-  const T* base = cst + B.lv[K].cst_off;
-  // z = L^-1 g_gamma, one node per group of g lanes
-  {
-    constexpr int GPW = Groups<g>::per_wave;
-    constexpr int NW = (L::n + GPW - 1) / GPW;
-    static_assert(NW * 64 <= NT, "level solve does not fit the workgroup");
-    const int wv = tid >> 6, lane = tid & 63;
-    const int grp = lane / g, i = lane % g;
-    const int t = wv * GPW + grp;
-    const bool act = grp < GPW && t < L::n;
-    if (wv < NW) {
-      const T* blk = base + (act ? t : 0) * L::per;
-      const int gb = grp * g;
-      double v = act ? cur[t * U + i] : 0.0;
+    const uint2* src = B.ext + ext_total<S>() + fext_off<S, K>();
 #pragma unroll
-      for (int l = 0; l < g; ++l) {
-        const double xl = __shfl(v, gb + l) / double(blk[l * g + l]);
-        if (i == l) v = xl;
-        else if (i > l) v -= double(blk[i * g + l]) * xl;
-      }
-      if (act) {
-        cur[t * U + i] = v;
-        vz[B.lv[K].vec_off + t * g + i] = v;
-      }
-    }
+    for (int k = 0; k < C::NE; ++k) a.r.e[k] = src[min(tid + NT * k, fext_count<S, K>() - 1)];
   }
-  if constexpr (K > 0) {  // idx is free: this level's extend-add is done
-#pragma unroll
-    for (int j = 0; j < NP; ++j)
-      if (tid + NT * j < NN) idx[tid + NT * j] = pre[j];
-  }
-  __syncthreads();
-  for (int e = tid; e < L::n * L::bnd; e += NT) {  // g_omega = g_Gamma - P z
-    const int t = e / L::bnd, j = e % L::bnd;
-    const T* blk = base + t * L::per;
-    const double* x = cur + t * U;
-    double v = x[g + j];
-#pragma unroll
-    for (int i = 0; i < g; ++i) v -= double(blk[(g + j) * g + i]) * x[i];
-    cur[t * U + g + j] = v;  // own slot; other threads read only x[0..g)
-  }
-  __syncthreads();
+  if constexpr (K > 0) fw_load<T, S, K - 1>(B, cst, a.next);
 }
 
 template <typename T, int S, int K>
-__device__ __forceinline__ void forward_levels(const DevBlocks& B, const T* cst, double* vz, double* cur,
-                                               double* prev, int* idx) {
-  forward_level<T, S, K>(B, cst, vz, cur, prev, idx);
-  if constexpr (K > 0) forward_levels<T, S, K - 1>(B, cst, vz, prev, cur, idx);
+__device__ __forceinline__ void fw_level(const FwAll<T, S, K>& a, const DevBlocks& B, double* gb, double* vz) {
+  using C = FwLevel<T, S, K>;
+  using L = Lv<S, K>;
+  constexpr int g = C::g, U = C::U, P = C::P;
+  const int tid = threadIdx.x;
+  double* cur = gb + ((L::Lm - K) & 1) * B.max_bnd_nodes;
+  if constexpr (K < L::Lm) {
+    double v[C::NE];
+#pragma unroll
+    for (int k = 0; k < C::NE; ++k) v[k] = gb[a.r.e[k].x] + gb[a.r.e[k].y];
+#pragma unroll
+    for (int k = 0; k < C::NE; ++k)
+      if (k + 1 < C::NE || tid + NT * k < L::n * U) cur[tid + NT * k] = v[k];
+    __syncthreads();
+  }
+  for (int e = tid; e < L::n * g; e += NT) vz[B.lv[K].vec_off + e] = cur[(e / g) * U + e % g];
+#pragma unroll
+  for (int rr = 0; rr < C::R; ++rr) {
+    const int o = tid / P + rr * (NT / P), p = tid % P;
+    const int oc = min(o, L::n * C::nbd - 1);
+    const int t = oc / C::nbd, j = oc % C::nbd;
+    const double* x = cur + t * U;
+    double acc = 0.0;
+#pragma unroll
+    for (int ii = 0; ii < C::NI; ++ii) acc += double(a.r.w[rr][ii]) * x[min(p + P * ii, g - 1)];
+#pragma unroll
+    for (int sh = P / 2; sh > 0; sh >>= 1) acc += __shfl_xor(acc, sh);
+    // own slot: other threads read only x[0 .. g)
+    if (p == 0 && o < L::n * C::nbd) cur[t * U + g + j] = x[g + j] - acc;
+  }
+  __syncthreads();
+  if constexpr (K > 0) fw_level<T, S, K - 1>(a.next, B, gb, vz);
 }
 
 template <typename T, int S>
@@ -616,37 +680,34 @@ __global__ void __launch_bounds__(NT) k_block_forward(DevBlocks B, int n_samples
   constexpr int Lm = M::Lm;
   constexpr int S1 = S + 1;
   extern __shared__ __align__(16) unsigned char smem[];
-  T* cs = reinterpret_cast<T*>(smem);
-  double* g0 = reinterpret_cast<double*>(smem + ((size_t(B.cst_size) * sizeof(T) + 15) / 16) * 16);
-  double* g1 = g0 + B.max_bnd_nodes;
-  __shared__ int idx[kIdxMax<S>];
+  double* gb = reinterpret_cast<double*>(smem);  // two buffers of max_bnd_nodes, then the zero slot
   const int q = blockIdx.x / n_samples;
   const int s = blockIdx.x % n_samples;
   const int X0 = B.origin[2 * q], Y0 = B.origin[2 * q + 1];
   const int tid = threadIdx.x;
-  stage_factors<T>(cs, cst_block<T>(B, q, s), B.cst_size);
+  FwAll<T, S, Lm> a;
+  fw_load<T, S, Lm>(B, cst_block<T>(B, q, s), a);
   double* vz = B.vec + (long long)s * B.vec_stride + (long long)q * B.vec_size;
   const double* rs = res + (long long)s * rstride;
+  if (tid == 0) gb[2 * B.max_bnd_nodes] = 0.0;
   // micro-blocks: node (i, j) of the residual belongs to the micro-block that
   // contains cell (i, j), so each global entry is counted exactly once
   {
-    stage_ints(idx, B.lids + B.lv[Lm].lid_off, M::n * M::U);
-    __syncthreads();
-    const int* lids = idx;
+    const int* lids = B.lids + B.lv[Lm].lid_off;
     for (int e = tid; e < M::n * M::U; e += NT) {
       const int t = e / M::U;
       const int lid = lids[e];
-      const int a = lid % S1, b = lid / S1;
-      const int a0 = B.micro_xy[2 * t], b0 = B.micro_xy[2 * t + 1];
-      const bool own = a >= a0 && a < a0 + 2 && b >= b0 && b < b0 + 2;
-      g0[e] = own ? rs[(long long)(Y0 + b) * (nc + 1) + X0 + a] : 0.0;
+      const int a0 = lid % S1, b0 = lid / S1;
+      const int ax = B.micro_xy[2 * t], by = B.micro_xy[2 * t + 1];
+      const bool own = a0 >= ax && a0 < ax + 2 && b0 >= by && b0 < by + 2;
+      gb[e] = own ? rs[(long long)(Y0 + b0) * (nc + 1) + X0 + a0] : 0.0;
     }
   }
   __syncthreads();
-  forward_levels<T, S, Lm>(B, cs, vz, g0, g1, idx);
-  // block root [z ; g_omega] -> the global vector store of the block level
+  fw_level<T, S, Lm>(a, B, gb, vz);
+  // block root [g_gamma ; g_omega] -> the global vector store of the block level
   using R = Lv<S, 0>;
-  const double* root = (Lm % 2 == 0) ? g0 : g1;
+  const double* root = gb + (Lm & 1) * B.max_bnd_nodes;
   const DevNode nd = B.top.nodes[q];
   double* out = B.top.vec + (long long)s * B.top.vec_stride + nd.ids_off;
   for (int e = tid; e < R::U; e += NT) out[e] = root[e];
@@ -658,21 +719,21 @@ size_t block_build_lds(const DevBlocks& B, bool dbl) { return (size_t(2) * B.max
 
 size_t block_ext_entries(int s) {
   switch (s) {
-    case 2: return ext_total<2>();
-    case 4: return ext_total<4>();
-    case 8: return ext_total<8>();
-    case 16: return ext_total<16>();
+    case 2: return ext_total<2>() + fext_total<2>();
+    case 4: return ext_total<4>() + fext_total<4>();
+    case 8: return ext_total<8>() + fext_total<8>();
+    case 16: return ext_total<16>() + fext_total<16>();
     default: return 0;
   }
 }
 
 template <int S> static void launch_ext_t(const DevBlocks& B, uint2* ext, hipStream_t st) {
-  constexpr int n = ext_total<S>();
+  constexpr int n = ext_total<S>() + fext_total<S>();
   if (n > 0) hipLaunchKernelGGL((k_block_ext<S>), dim3((n + 255) / 256), dim3(256), 0, st, B, ext);
 }
 
 hipError_t launch_block_ext(const DevBlocks& B, uint2* ext, hipStream_t st) {
-  // every offset (and the zero slot) must fit the table's 16-bit fields
+  // every offset (and the zero slot) must fit the build table's 16-bit fields
   if (2 * B.max_buf >= 65536) return hipErrorInvalidValue;
   switch (B.s) {
     case 2: launch_ext_t<2>(B, ext, st); break;
@@ -684,15 +745,10 @@ hipError_t launch_block_ext(const DevBlocks& B, uint2* ext, hipStream_t st) {
   return hipGetLastError();
 }
 
-static size_t stage_bytes(const DevBlocks& B, bool dbl) { return (size_t(B.cst_size) * (dbl ? 8 : 4) + 15) / 16 * 16; }
+size_t block_topdown_lds(const DevBlocks& B, bool) { return sizeof(double) * size_t((B.s + 1) * (B.s + 1)); }
 
-size_t block_topdown_lds(const DevBlocks& B, bool dbl) {
-  return stage_bytes(B, dbl) + sizeof(double) * size_t((B.s + 1) * (B.s + 1) + B.max_gam_nodes);
-}
-
-size_t block_forward_lds(const DevBlocks& B, bool dbl) {
-  return stage_bytes(B, dbl) + sizeof(double) * size_t(2 * B.max_bnd_nodes);
-}
+// two buffers of node values and the gather table's zero slot
+size_t block_forward_lds(const DevBlocks& B, bool) { return sizeof(double) * size_t(2 * B.max_bnd_nodes + 1); }
 
 template <int S, int K> static bool shape_ok_from(const DevBlocks& B) {
   using L = Lv<S, K>;
@@ -726,8 +782,7 @@ static void launch_build_t(const DevBlocks& B, int n_samples, int nc, const doub
 template <typename T, int S>
 static void launch_topdown_t(const DevBlocks& B, const int* list, int n_list, int n_samples, int nc, double* u,
                              long long ustride, bool from_vec, hipStream_t st) {
-  const size_t lds = block_topdown_lds(B, sizeof(T) == 8);
-  hipLaunchKernelGGL((k_block_topdown<T, S>), dim3(n_list * n_samples), dim3(NT), lds, st, B, list, n_samples, nc, u,
+  hipLaunchKernelGGL((k_block_topdown<T, S>), dim3(n_list * n_samples), dim3(NT), 0, st, B, list, n_samples, nc, u,
                      ustride, from_vec ? 1 : 0);
 }
 
