@@ -494,7 +494,7 @@ template <typename T, int S, int K> struct TdAll<T, S, K, false> {
   TdAll<T, S, K + 1> next;
 };
 
-template <typename T, int S, int K>
+template <typename T, int S, int K, bool FV>
 __device__ __forceinline__ void td_load(const DevBlocks& B, const T* cst, const double* vz, TdAll<T, S, K>& a) {
   using C = TdLevel<T, S, K>;
   using L = Lv<S, K>;
@@ -505,59 +505,58 @@ __device__ __forceinline__ void td_load(const DevBlocks& B, const T* cst, const 
   const int t = w / g, i = w % g;
   const T* blk = cst + B.lv[K].cst_off + t * L::per;
   const int* lid = B.lids + B.lv[K].lid_off + t * C::U;
+  // loaded values are masked where they are used, never here: a select on a
+  // loaded value would wait for that load and serialise the whole prologue
 #pragma unroll
   for (int jj = 0; jj < C::NJ; ++jj) {
-    const int j = p + P * jj, jc = min(j, C::nbd - 1);
-    const T v = blk[(g + jc) * g + i];
-    a.r.w[jj] = j < C::nbd ? v : T(0);
+    const int jc = min(p + P * jj, C::nbd - 1);
+    a.r.w[jj] = blk[(g + jc) * g + i];
     a.r.lj[jj] = lid[g + jc];
   }
-  if (vz) {
+  if constexpr (FV) {
     const double* zt = vz + B.lv[K].vec_off + t * g;
 #pragma unroll
     for (int ll = 0; ll < C::NL; ++ll) {
-      const int l = p + P * ll, lc = min(l, g - 1);
-      const T v = blk[lc * g + i];
-      a.r.m[ll] = l < g ? v : T(0);
+      const int lc = min(p + P * ll, g - 1);
+      a.r.m[ll] = blk[lc * g + i];
       a.r.z[ll] = zt[lc];
     }
-    a.r.y = T(0);
   } else {
-#pragma unroll
-    for (int ll = 0; ll < C::NL; ++ll) {
-      a.r.m[ll] = T(0);
-      a.r.z[ll] = 0.0;
-    }
     a.r.y = blk[C::U * g + i];
   }
   a.r.li = lid[i];
-  if constexpr (K < L::Lm) td_load<T, S, K + 1>(B, cst, vz, a.next);
+  if constexpr (K < L::Lm) td_load<T, S, K + 1, FV>(B, cst, vz, a.next);
 }
 
-template <typename T, int S, int K>
+template <typename T, int S, int K, bool FV>
 __device__ __forceinline__ void td_solve(const TdAll<T, S, K>& a, double* uL) {
   using C = TdLevel<T, S, K>;
   const int tid = threadIdx.x;
   if (tid < C::act) {
     const int p = tid % C::P;
-    double acc = p == 0 ? double(a.r.y) : 0.0;
+    double acc = 0.0;
+    if constexpr (FV) {
 #pragma unroll
-    for (int ll = 0; ll < C::NL; ++ll) acc += double(a.r.m[ll]) * a.r.z[ll];
+      for (int ll = 0; ll < C::NL; ++ll)
+        if (p + C::P * ll < C::g) acc += double(a.r.m[ll]) * a.r.z[ll];
+    } else {
+      if (p == 0) acc = double(a.r.y);
+    }
 #pragma unroll
-    for (int jj = 0; jj < C::NJ; ++jj) acc -= double(a.r.w[jj]) * uL[a.r.lj[jj]];
+    for (int jj = 0; jj < C::NJ; ++jj)
+      if (p + C::P * jj < C::nbd) acc -= double(a.r.w[jj]) * uL[a.r.lj[jj]];
     // the P lanes of an entry are consecutive and P divides 64
 #pragma unroll
     for (int o = C::P / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if (p == 0) uL[a.r.li] = acc;  // gamma of this node: read by no other node of the level
   }
   __syncthreads();
-  if constexpr (K < Lv<S, 0>::Lm) td_solve<T, S, K + 1>(a.next, uL);
+  if constexpr (K < Lv<S, 0>::Lm) td_solve<T, S, K + 1, FV>(a.next, uL);
 }
 
-template <typename T, int S>
+template <typename T, int S, bool FV>
 __global__ void __launch_bounds__(NT) k_block_topdown(DevBlocks B, const int* __restrict__ list, int n_samples,
-                                                      int nc, double* __restrict__ u, long long ustride,
-                                                      int from_vec) {
+                                                      int nc, double* __restrict__ u, long long ustride) {
   constexpr int S1 = S + 1;
   __shared__ double uL[S1 * S1];
   const int q = list[blockIdx.x / n_samples];
@@ -565,12 +564,12 @@ __global__ void __launch_bounds__(NT) k_block_topdown(DevBlocks B, const int* __
   const int X0 = B.origin[2 * q], Y0 = B.origin[2 * q + 1];
   const int tid = threadIdx.x;
   double* us = u + (long long)s * ustride;
-  const double* vz = from_vec ? B.vec + (long long)s * B.vec_stride + (long long)q * B.vec_size : nullptr;
+  const double* vz = FV ? B.vec + (long long)s * B.vec_stride + (long long)q * B.vec_size : nullptr;
   TdAll<T, S, 0> a;
-  td_load<T, S, 0>(B, cst_block<T>(B, q, s), vz, a);
+  td_load<T, S, 0, FV>(B, cst_block<T>(B, q, s), vz, a);
   for (int e = tid; e < S1 * S1; e += NT) uL[e] = us[(long long)(Y0 + e / S1) * (nc + 1) + X0 + e % S1];
   __syncthreads();
-  td_solve<T, S, 0>(a, uL);
+  td_solve<T, S, 0, FV>(a, uL);
   constexpr int si = S - 1;
   for (int e = tid; e < si * si; e += NT) {
     const int a0 = 1 + e % si, b0 = 1 + e / si;
@@ -624,11 +623,7 @@ __device__ __forceinline__ void fw_load(const DevBlocks& B, const T* cst, FwAll<
     const int t = o / C::nbd, j = o % C::nbd;
     const T* row = base + t * L::per + (g + j) * g;
 #pragma unroll
-    for (int ii = 0; ii < C::NI; ++ii) {
-      const int i = p + P * ii;
-      const T v = row[min(i, g - 1)];
-      a.r.w[rr][ii] = i < g ? v : T(0);
-    }
+    for (int ii = 0; ii < C::NI; ++ii) a.r.w[rr][ii] = row[min(p + P * ii, g - 1)];  // masked at use
   }
   if constexpr (K < L::Lm) {
     const uint2* src = B.ext + ext_total<S>() + fext_off<S, K>();
@@ -663,7 +658,8 @@ __device__ __forceinline__ void fw_level(const FwAll<T, S, K>& a, const DevBlock
     const double* x = cur + t * U;
     double acc = 0.0;
 #pragma unroll
-    for (int ii = 0; ii < C::NI; ++ii) acc += double(a.r.w[rr][ii]) * x[min(p + P * ii, g - 1)];
+    for (int ii = 0; ii < C::NI; ++ii)
+      if (p + P * ii < g) acc += double(a.r.w[rr][ii]) * x[p + P * ii];
 #pragma unroll
     for (int sh = P / 2; sh > 0; sh >>= 1) acc += __shfl_xor(acc, sh);
     // own slot: other threads read only x[0 .. g)
@@ -685,23 +681,39 @@ __global__ void __launch_bounds__(NT) k_block_forward(DevBlocks B, int n_samples
   const int s = blockIdx.x % n_samples;
   const int X0 = B.origin[2 * q], Y0 = B.origin[2 * q + 1];
   const int tid = threadIdx.x;
+  // micro-blocks: node (i, j) of the residual belongs to the micro-block that
+  // contains cell (i, j), so each global entry is counted exactly once.  The
+  // index loads go first, the operator loads next, the residual loads (which
+  // need the indices) last, so the prologue waits for memory once.
+  constexpr int NM = (M::n * M::U + NT - 1) / NT;
+  int lid[NM], ax[NM], by[NM];
+  {
+    const int* lids = B.lids + B.lv[Lm].lid_off;
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+      const int e = min(tid + NT * k, M::n * M::U - 1);
+      const int t = e / M::U;
+      lid[k] = lids[e];
+      ax[k] = B.micro_xy[2 * t];
+      by[k] = B.micro_xy[2 * t + 1];
+    }
+  }
   FwAll<T, S, Lm> a;
   fw_load<T, S, Lm>(B, cst_block<T>(B, q, s), a);
   double* vz = B.vec + (long long)s * B.vec_stride + (long long)q * B.vec_size;
   const double* rs = res + (long long)s * rstride;
   if (tid == 0) gb[2 * B.max_bnd_nodes] = 0.0;
-  // micro-blocks: node (i, j) of the residual belongs to the micro-block that
-  // contains cell (i, j), so each global entry is counted exactly once
   {
-    const int* lids = B.lids + B.lv[Lm].lid_off;
-    for (int e = tid; e < M::n * M::U; e += NT) {
-      const int t = e / M::U;
-      const int lid = lids[e];
-      const int a0 = lid % S1, b0 = lid / S1;
-      const int ax = B.micro_xy[2 * t], by = B.micro_xy[2 * t + 1];
-      const bool own = a0 >= ax && a0 < ax + 2 && b0 >= by && b0 < by + 2;
-      gb[e] = own ? rs[(long long)(Y0 + b0) * (nc + 1) + X0 + a0] : 0.0;
+    double v[NM];
+#pragma unroll
+    for (int k = 0; k < NM; ++k) {
+      const int a0 = lid[k] % S1, b0 = lid[k] / S1;
+      const bool own = a0 >= ax[k] && a0 < ax[k] + 2 && b0 >= by[k] && b0 < by[k] + 2;
+      v[k] = own ? rs[(long long)(Y0 + b0) * (nc + 1) + X0 + a0] : 0.0;
     }
+#pragma unroll
+    for (int k = 0; k < NM; ++k)
+      if (tid + NT * k < M::n * M::U) gb[tid + NT * k] = v[k];
   }
   __syncthreads();
   fw_level<T, S, Lm>(a, B, gb, vz);
@@ -782,8 +794,12 @@ static void launch_build_t(const DevBlocks& B, int n_samples, int nc, const doub
 template <typename T, int S>
 static void launch_topdown_t(const DevBlocks& B, const int* list, int n_list, int n_samples, int nc, double* u,
                              long long ustride, bool from_vec, hipStream_t st) {
-  hipLaunchKernelGGL((k_block_topdown<T, S>), dim3(n_list * n_samples), dim3(NT), 0, st, B, list, n_samples, nc, u,
-                     ustride, from_vec ? 1 : 0);
+  if (from_vec)
+    hipLaunchKernelGGL((k_block_topdown<T, S, true>), dim3(n_list * n_samples), dim3(NT), 0, st, B, list, n_samples,
+                       nc, u, ustride);
+  else
+    hipLaunchKernelGGL((k_block_topdown<T, S, false>), dim3(n_list * n_samples), dim3(NT), 0, st, B, list, n_samples,
+                       nc, u, ustride);
 }
 
 template <typename T, int S>
