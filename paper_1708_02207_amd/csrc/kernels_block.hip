@@ -158,47 +158,94 @@ constexpr int NT = 256;   // threads of the top-down / forward kernels
 constexpr int NTB = 512;  // threads of the build kernel
 
 // ---------------------------------------------------------------------------
-// Column J of the left-looking partial Cholesky for all n frames of a level,
-// one barrier per column: every thread of a node recomputes the pivot
-// L_JJ = sqrt(A_JJ - sum_l L_Jl^2) from row J (whose diagonal entry is left
-// untouched until the end), the thread of row J records it in dg, and the
-// rows below (interface, boundary and load rows) take
-// L_iJ = (A_iJ - sum_l L_il L_Jl) / L_JJ.  The recorded pivots are written to
-// the diagonal after the last column.  Unrolled over the (compile-time)
-// columns so every inner loop has a fixed length.
-template <typename T, typename L, int J>
-__device__ __forceinline__ void crout_columns(T* cur, T* dg, T* rdg, int& bad_pivot) {
-  if constexpr (J < L::gam) {
-    constexpr int ld = L::ldp;
-    constexpr int m = L::U + 1 - J;  // rows J .. U
-    for (int e = threadIdx.x; e < L::n * m; e += NTB) {
-      const int t = e / m, i = J + e % m;
-      T* F = cur + t * L::fsz;
-      T d = F[J * ld + J];
+// Partial Cholesky of the first gam columns of every frame of a level in
+// registers (Section 2.4, eq. SchurC1 with the pivots of eq. Phi): a group
+// of GS lanes per node, lane j holding rows j, j + GS, ... (first gam
+// entries).  Right-looking: column J is scaled by 1 / L_JJ, then the later
+// columns k of every row take A_rk -= L_rJ L_kJ, with L_JJ and L_kJ sent to
+// the group by cross-lane reads (rows J, k < gam sit in the group's first
+// lanes).  No barriers; the frames are read from and written back to LDS.
+// The pivots go to dg, their reciprocals to rdg.
+template <typename L> struct CholCfg {
+  static constexpr int R = L::U + 1;  // rows: gamma, Gamma, load
+  static constexpr int GS = R >= 64 ? 64 : (R > 32 ? 64 : (R > 16 ? 32 : (R > 8 ? 16 : (R > 4 ? 8 : 4))));
+  static constexpr int RPL = (R + GS - 1) / GS;  // rows per lane
+  static constexpr int NPW = 64 / GS;            // nodes per wave
+  static constexpr int WAVES = (L::n + NPW - 1) / NPW;
+};
+
+template <typename T, int GS>
+__device__ __forceinline__ T group_read(T v, int src_lane) {
+  if constexpr (GS == 64) {  // wave-uniform source: through the scalar unit
+    if constexpr (sizeof(T) == 8) {
+      const long long b = __double_as_longlong(double(v));
+      const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), src_lane);
+      const int hi = __builtin_amdgcn_readlane(int(b >> 32), src_lane);
+      return T(__longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo)));
+    } else {
+      return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(float(v)), src_lane));
+    }
+  } else {
+    return __shfl(v, src_lane);
+  }
+}
+
+template <typename T, typename L>
+__device__ __forceinline__ void chol_regs(T* cur, T* dg, T* rdg, int& bad_pivot) {
+  using C = CholCfg<L>;
+  constexpr int g = L::gam, ld = L::ldp, R = C::R, GS = C::GS, RPL = C::RPL;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j = lane % GS;
+  const int gbase = lane - j;
+  for (int w0 = 0; w0 < C::WAVES; w0 += NTB / 64) {  // uniform
+    const int t = (w0 + wv) * C::NPW + lane / GS;
+    if (w0 + wv >= C::WAVES) break;  // wave-uniform
+    const bool act = t < L::n;
+    T* F = cur + (act ? t : 0) * L::fsz;
+    T a[RPL][g];
 #pragma unroll
-      for (int l = 0; l < J; ++l) d -= F[J * ld + l] * F[J * ld + l];
+    for (int q = 0; q < RPL; ++q) {
+      const int r = min(j + GS * q, R - 1);
+#pragma unroll
+      for (int c = 0; c < g; ++c) a[q][c] = F[r * ld + c];
+    }
+#pragma unroll
+    for (int J = 0; J < g; ++J) {
+      T d = group_read<T, GS>(a[0][J], GS == 64 ? J : gbase + J);
       const bool ok = (d > T(0)) && (d < T(1e300));
-      d = ok ? sqrt(d) : T(1);
-      if (i == J) {
-        if (!ok) bad_pivot = 1;
-        dg[t * L::gam + J] = d;
-      } else {
-        T v = F[i * ld + J];
+      if (!ok && act) bad_pivot = 1;
+      d = ok ? T(sqrt(d)) : T(1);
+      const T rd = T(1) / d;
 #pragma unroll
-        for (int l = 0; l < J; ++l) v -= F[i * ld + l] * F[J * ld + l];
-        F[i * ld + J] = v / d;
+      for (int q = 0; q < RPL; ++q) {
+        const int r = j + GS * q;
+        a[q][J] = r == J ? d : (r > J ? a[q][J] * rd : a[q][J]);
+      }
+      if (j == J && act) {
+        dg[t * g + J] = d;
+        rdg[t * g + J] = rd;
+      }
+#pragma unroll
+      for (int k = J + 1; k < g; ++k) {
+        const T lk = group_read<T, GS>(a[0][J], GS == 64 ? k : gbase + k);  // L_kJ
+#pragma unroll
+        for (int q = 0; q < RPL; ++q)
+          if (j + GS * q >= k) a[q][k] -= a[q][J] * lk;
       }
     }
-    __syncthreads();
-    crout_columns<T, L, J + 1>(cur, dg, rdg, bad_pivot);
-  } else {
-    for (int e = threadIdx.x; e < L::n * L::gam; e += NTB) {
-      const int t = e / L::gam, j = e % L::gam;
-      cur[t * L::fsz + j * L::ldp + j] = dg[e];
-      rdg[e] = T(1) / dg[e];
+    if (act) {
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int r = j + GS * q;
+        if (r < R) {
+#pragma unroll
+          for (int c = 0; c < g; ++c)
+            if (c <= r) F[r * ld + c] = a[q][c];
+        }
+      }
     }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -228,12 +275,11 @@ __device__ __forceinline__ void build_level(T* base, T* cur, T* cst, const DevBl
       if (j + 1 < NP || tid + NB * j < E) base[tab[j].x & 0xffffu] = v[j];
     __syncthreads();
   }
-  // Partial Cholesky of the first gam columns (left-looking, column by
-  // column): L_jj = sqrt(A_jj - sum_l L_jl^2), then every row below
-  // (interface, boundary and load rows) L_ij = (A_ij - sum_l L_il L_jl) / L_jj.
+  // Partial Cholesky of the first gam columns: L (interface rows), P
+  // (boundary rows) and z (load row) of every node.
   constexpr int g = L::gam, ld = L::ldp;
   T* rdg = dg + gam_nodes_from<S, 0>();
-  crout_columns<T, L, 0>(cur, dg, rdg, bad_pivot);
+  chol_regs<T, L>(cur, dg, rdg, bad_pivot);
   // Schur update of the boundary block and the load row (rank-g, eq.
   // SchurC1): S[i][l] -= sum_k P[i][k] P[l][k], g <= l <= i <= U.
   if constexpr (std::is_same<T, float>::value && g >= 7) {
