@@ -114,7 +114,7 @@ Layout make_layout(const Plan& p, const hdd_opts& o, int ms) {
   L.tlids = take(int64_t(T.lids.size()) * 4);
   L.tmicro = take(int64_t(T.micro_xy.size()) * 4);
   L.origin = take(nb * 8);
-  L.text = take(int64_t(hdd::block_ext_entries(T.s)) * 8);
+  L.text = take(int64_t(hdd::block_ext_entries(T.s)) * 4);
   L.total = off;
   return L;
 }
@@ -511,7 +511,7 @@ int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* works
     B.maps = reinterpret_cast<const int*>(h->ws + L.tmaps);
     B.lids = reinterpret_cast<const int*>(h->ws + L.tlids);
     B.micro_xy = reinterpret_cast<const int*>(h->ws + L.tmicro);
-    B.ext = reinterpret_cast<const uint2*>(h->ws + L.text);
+    B.ext = reinterpret_cast<const unsigned*>(h->ws + L.text);
     B.origin = reinterpret_cast<const int*>(h->ws + L.origin);
     B.cst = h->ws + L.cst;
     B.cst_stride = (long long)B.nb * T.cst_size;
@@ -531,7 +531,7 @@ int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* works
       return fail(HDD_EDEVICE);
     const bool bdbl = B.top.is_double != 0;
     if (!hdd::block_shape_ok(B)) return fail(HDD_EINVAL);
-    if (hdd::launch_block_ext(B, const_cast<uint2*>(B.ext), h->st) != hipSuccess ||
+    if (hdd::launch_block_ext(B, const_cast<unsigned*>(B.ext), h->st) != hipSuccess ||
         hipStreamSynchronize(h->st) != hipSuccess)
       return fail(HDD_EDEVICE);
     // the build stages the block's coefficients and load in its second frame buffer

@@ -65,7 +65,7 @@ struct DevBlocks {
   const int* maps;
   const int* lids;
   const int* micro_xy;
-  const uint2* ext;   // extend-add gather table of the build kernel (see k_block_ext)
+  const unsigned* ext;  // merge tables of the block build and forward kernels (see k_block_ext)
   const int* origin;  // [nb][2] lower-left cell of every block
   void* cst;          // [sample][block][cst_size], float or double
   long long cst_stride;

@@ -27,7 +27,7 @@ size_t block_topdown_lds(const DevBlocks& B, bool dbl);
 size_t block_forward_lds(const DevBlocks& B, bool dbl);
 bool block_shape_ok(const DevBlocks& B);  // template sizes match the compiled shapes
 size_t block_ext_entries(int s);          // entries of the extend-add gather table
-hipError_t launch_block_ext(const DevBlocks& B, uint2* ext, hipStream_t st);
+hipError_t launch_block_ext(const DevBlocks& B, unsigned* ext, hipStream_t st);
 hipError_t launch_block_build(const DevBlocks& B, int n_samples, int nc, const double* kappa, const double* f,
                               int* bad, int* info, hipStream_t st);
 hipError_t launch_block_topdown(const DevBlocks& B, const int* list, int n_list, int n_samples, int nc, double* u,

@@ -46,21 +46,22 @@ template <int S, int K> struct Lv {
   static constexpr int gam = (K == Lm) ? 1 : (w >= h ? h - 1 : w - 1);
   static constexpr int bnd = 2 * (w + h);
   static constexpr int U = gam + bnd;
-  static constexpr int ld = U + 1;              // logical frame size
-  static constexpr int ldp = ld | 1;              // odd LDS row stride (no bank conflicts on columns)
-  static constexpr int fsz = ld * ldp;            // LDS elements per frame
+  static constexpr int ld = U + 1;              // frame rows
+  static constexpr int fsz = ld * (ld + 1) / 2;   // LDS elements per frame: packed lower triangle
+  __host__ __device__ static constexpr int row(int r) { return r * (r + 1) / 2; }  // start of row r
   static constexpr int per = ld * gam;            // compact elements per node
 };
 
 
 // Extend-add gather table of the build kernel.  Every block shares the
 // sub-tree, so the LDS addresses of the extend-add are the same for all of
-// them: entry e of level K (K above the micro level) names one lower-triangle
-// element (t, r, c) of the level's frames and the two son elements merged into
-// it, as element offsets from the start of the kernel's LDS frame buffers:
-// x = dst | a << 16, y = b, with a (b) the son-A (son-B) element or the zero
-// slot 2 * max_buf when the row or column is not in that son (Section 2.4,
-// eq. S_omega).  Level K's frames live in buffer (Lm - K) & 1.
+// them.  Entry e of level K (K above the micro level) is element e of the
+// level's packed frames (node t, row r, column c <= r, in that order) and
+// holds the two son elements merged into it, a | b << 16, as element offsets
+// from the start of the kernel's LDS frame buffers: a (b) the son-A (son-B)
+// element, or the zero slot 2 * max_buf when the row or column is not in that
+// son (Section 2.4, eq. S_omega).  Level K's frames live in buffer
+// (Lm - K) & 1.
 template <int S, int K> constexpr int ext_count() {
   using L = Lv<S, K>;
   return (K < L::Lm) ? L::n * L::ld * (L::ld + 1) / 2 : 0;
@@ -72,7 +73,7 @@ template <int S, int K> constexpr int ext_off() {
 template <int S> constexpr int ext_total() { return ext_off<S, Lv<S, 0>::Lm>(); }
 
 template <int S, int K>
-__device__ __forceinline__ void ext_entry(const DevBlocks& B, int e, uint2* out) {
+__device__ __forceinline__ void ext_entry(const DevBlocks& B, int e, unsigned* out) {
   using L = Lv<S, K>;
   if constexpr (K < L::Lm) {
     if (e >= ext_count<S, K>()) {
@@ -84,20 +85,19 @@ __device__ __forceinline__ void ext_entry(const DevBlocks& B, int e, uint2* out)
     const int t = e / tri, rc = e % tri;
     const int r = tri_row(rc), c = rc - r * (r + 1) / 2;
     const int zero = 2 * B.max_buf;
-    const int cur = ((L::Lm - K) & 1) * B.max_buf, prev = ((L::Lm - K + 1) & 1) * B.max_buf;
+    const int prev = ((L::Lm - K + 1) & 1) * B.max_buf;
     const int* mA = B.maps + B.lv[K].map_off + t * 2 * L::ld;
     const int* mB = mA + L::ld;
-    const int sa = prev + (2 * t) * C::fsz + C::gam * C::ldp + C::gam, sb = sa + C::fsz;
+    const int sa = prev + (2 * t) * C::fsz + C::gam, sb = sa + C::fsz;  // + row(gam + r') + c' of S~
     const int ar = mA[r], ac = mA[c], br = mB[r], bc = mB[c];
-    const int a = (ar >= 0 && ac >= 0) ? sa + max(ar, ac) * C::ldp + min(ar, ac) : zero;
-    const int b = (br >= 0 && bc >= 0) ? sb + max(br, bc) * C::ldp + min(br, bc) : zero;
-    const int dst = cur + t * L::fsz + r * L::ldp + c;
-    out[ext_off<S, K>() + e] = make_uint2(unsigned(dst) | (unsigned(a) << 16), unsigned(b));
+    const int a = (ar >= 0 && ac >= 0) ? sa + C::row(C::gam + max(ar, ac)) + min(ar, ac) : zero;
+    const int b = (br >= 0 && bc >= 0) ? sb + C::row(C::gam + max(br, bc)) + min(br, bc) : zero;
+    out[ext_off<S, K>() + e] = unsigned(a) | (unsigned(b) << 16);
   }
 }
 
 // Merge table of the forward sweep: entry e = t * U + i of level K adds the
-// sons' condensed loads, x = a, y = b as offsets from the start of the
+// sons' condensed loads, a | b << 16 as offsets from the start of the
 // kernel's two LDS value buffers (max_bnd_nodes each; level K's values live
 // in buffer (Lm - K) & 1), the zero slot 2 * max_bnd_nodes where row i is not
 // in that son.  Stored after the build's table.
@@ -112,7 +112,7 @@ template <int S, int K> constexpr int fext_off() {
 template <int S> constexpr int fext_total() { return fext_off<S, Lv<S, 0>::Lm>(); }
 
 template <int S, int K>
-__device__ __forceinline__ void fext_entry(const DevBlocks& B, int e, uint2* out) {
+__device__ __forceinline__ void fext_entry(const DevBlocks& B, int e, unsigned* out) {
   using L = Lv<S, K>;
   if constexpr (K < L::Lm) {
     if (e >= fext_count<S, K>()) {
@@ -127,11 +127,11 @@ __device__ __forceinline__ void fext_entry(const DevBlocks& B, int e, uint2* out
     const int* mB = mA + L::ld;
     const int a = mA[i] >= 0 ? prev + (2 * t) * C::U + C::gam + mA[i] : zero;
     const int b = mB[i] >= 0 ? prev + (2 * t + 1) * C::U + C::gam + mB[i] : zero;
-    out[ext_total<S>() + fext_off<S, K>() + e] = make_uint2(unsigned(a), unsigned(b));
+    out[ext_total<S>() + fext_off<S, K>() + e] = unsigned(a) | (unsigned(b) << 16);
   }
 }
 
-template <int S> __global__ void k_block_ext(DevBlocks B, uint2* __restrict__ ext) {
+template <int S> __global__ void k_block_ext(DevBlocks B, unsigned* __restrict__ ext) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e < ext_total<S>()) ext_entry<S, 0>(B, e, ext);
   else if (e < ext_total<S>() + fext_total<S>()) fext_entry<S, 0>(B, e - ext_total<S>(), ext);
@@ -142,12 +142,12 @@ template <typename T> __device__ __forceinline__ T* cst_block(const DevBlocks& B
   return reinterpret_cast<T*>(B.cst) + (long long)s * B.cst_stride + (long long)q * B.cst_size;
 }
 
-// Largest n * gam over the levels of a block (pivots recorded per column).
-template <int S, int K> constexpr int gam_nodes_from() {
+// Largest n * gam^2 over the levels of a block (the X = L_gg^-1 blocks).
+template <int S, int K> constexpr int inv_size_from() {
   using L = Lv<S, K>;
-  constexpr int m = L::n * L::gam;
+  constexpr int m = L::n * L::gam * L::gam;
   if constexpr (K < L::Lm) {
-    constexpr int rest = gam_nodes_from<S, K + 1>();
+    constexpr int rest = inv_size_from<S, K + 1>();
     return m > rest ? m : rest;
   } else {
     return m;
@@ -160,17 +160,20 @@ constexpr int NTB = 512;  // threads of the build kernel
 // ---------------------------------------------------------------------------
 // Partial Cholesky of the first gam columns of every frame of a level in
 // registers (Section 2.4, eq. SchurC1 with the pivots of eq. Phi): a group
-// of GS lanes per node, lane j holding rows j, j + GS, ... (first gam
-// entries).  Right-looking: column J is scaled by 1 / L_JJ, then the later
-// columns k of every row take A_rk -= L_rJ L_kJ, with L_JJ and L_kJ sent to
-// the group by cross-lane reads (rows J, k < gam sit in the group's first
-// lanes).  No barriers; the frames are read from and written back to LDS.
-// The pivots go to dg, their reciprocals to rdg.
+// of GS lanes per node, lane j holding row j (first gam entries).
+// Right-looking: column J is scaled by 1 / L_JJ, then the later columns k of
+// every row take A_rk -= L_rJ L_kJ, with L_JJ and L_kJ sent to the group by
+// cross-lane reads (rows J, k < gam sit in the group's first lanes).  The
+// same lanes then form X = L_gg^-1 row by row (X_kk = 1 / L_kk,
+// X_ic = -(sum_k L_ik X_kc) / L_ii) and leave it in xs[node][gam][gam].
+// No barriers inside; frames are read from and written back to LDS.  A
+// frame of more than 64 rows (the block root) has its remaining rows done
+// by chol_tail.
 template <typename L> struct CholCfg {
   static constexpr int R = L::U + 1;  // rows: gamma, Gamma, load
-  static constexpr int GS = R >= 64 ? 64 : (R > 32 ? 64 : (R > 16 ? 32 : (R > 8 ? 16 : (R > 4 ? 8 : 4))));
-  static constexpr int RPL = (R + GS - 1) / GS;  // rows per lane
-  static constexpr int NPW = 64 / GS;            // nodes per wave
+  static constexpr int GS = R > 32 ? 64 : (R > 16 ? 32 : (R > 8 ? 16 : (R > 4 ? 8 : 4)));
+  static constexpr int RR = R < 64 ? R : 64;  // rows held in registers (one per lane)
+  static constexpr int NPW = 64 / GS;         // nodes per wave
   static constexpr int WAVES = (L::n + NPW - 1) / NPW;
 };
 
@@ -191,9 +194,9 @@ __device__ __forceinline__ T group_read(T v, int src_lane) {
 }
 
 template <typename T, typename L>
-__device__ __forceinline__ void chol_regs(T* cur, T* dg, T* rdg, int& bad_pivot) {
+__device__ __forceinline__ void chol_regs(T* cur, T* xs, int& bad_pivot) {
   using C = CholCfg<L>;
-  constexpr int g = L::gam, ld = L::ldp, R = C::R, GS = C::GS, RPL = C::RPL;
+  constexpr int g = L::gam, GS = C::GS;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int j = lane % GS;
   const int gbase = lane - j;
@@ -202,50 +205,76 @@ __device__ __forceinline__ void chol_regs(T* cur, T* dg, T* rdg, int& bad_pivot)
     if (w0 + wv >= C::WAVES) break;  // wave-uniform
     const bool act = t < L::n;
     T* F = cur + (act ? t : 0) * L::fsz;
-    T a[RPL][g];
+    const int r = min(j, C::RR - 1);
+    T a[g];
 #pragma unroll
-    for (int q = 0; q < RPL; ++q) {
-      const int r = min(j + GS * q, R - 1);
-#pragma unroll
-      for (int c = 0; c < g; ++c) a[q][c] = F[r * ld + c];
-    }
+    for (int c = 0; c < g; ++c) a[c] = F[L::row(r) + c];  // c > r: unused
+    T rdj = T(1);  // 1 / L_jj in lane j < g
 #pragma unroll
     for (int J = 0; J < g; ++J) {
-      T d = group_read<T, GS>(a[0][J], GS == 64 ? J : gbase + J);
+      T d = group_read<T, GS>(a[J], GS == 64 ? J : gbase + J);
       const bool ok = (d > T(0)) && (d < T(1e300));
       if (!ok && act) bad_pivot = 1;
       d = ok ? T(sqrt(d)) : T(1);
       const T rd = T(1) / d;
-#pragma unroll
-      for (int q = 0; q < RPL; ++q) {
-        const int r = j + GS * q;
-        a[q][J] = r == J ? d : (r > J ? a[q][J] * rd : a[q][J]);
-      }
-      if (j == J && act) {
-        dg[t * g + J] = d;
-        rdg[t * g + J] = rd;
-      }
+      if (j == J) rdj = rd;
+      a[J] = j == J ? d : (j > J ? a[J] * rd : a[J]);
 #pragma unroll
       for (int k = J + 1; k < g; ++k) {
-        const T lk = group_read<T, GS>(a[0][J], GS == 64 ? k : gbase + k);  // L_kJ
-#pragma unroll
-        for (int q = 0; q < RPL; ++q)
-          if (j + GS * q >= k) a[q][k] -= a[q][J] * lk;
+        const T lk = group_read<T, GS>(a[J], GS == 64 ? k : gbase + k);  // L_kJ
+        if (j >= k) a[k] -= a[J] * lk;
       }
     }
-    if (act) {
+    if (act && j < C::RR) {
 #pragma unroll
-      for (int q = 0; q < RPL; ++q) {
-        const int r = j + GS * q;
-        if (r < R) {
+      for (int c = 0; c < g; ++c)
+        if (c <= j) F[L::row(j) + c] = a[c];
+    }
+    // X = L_gg^-1: lane i accumulates v_c = -sum_{k<i} L_ik X_kc and
+    // finishes its row at step k = i
+    T v[g];
 #pragma unroll
-          for (int c = 0; c < g; ++c)
-            if (c <= r) F[r * ld + c] = a[q][c];
-        }
+    for (int c = 0; c < g; ++c) v[c] = T(0);
+#pragma unroll
+    for (int k = 0; k < g; ++k) {
+      if (j == k) {
+#pragma unroll
+        for (int c = 0; c <= k; ++c) v[c] = (c == k ? T(1) + v[c] : v[c]) * rdj;
       }
+#pragma unroll
+      for (int c = 0; c <= k; ++c) {
+        const T xk = group_read<T, GS>(v[c], GS == 64 ? k : gbase + k);  // X_kc
+        if (j > k) v[c] -= a[k] * xk;
+      }
+    }
+    if (act && j < g) {
+      T* X = xs + t * g * g + j * g;
+#pragma unroll
+      for (int c = 0; c < g; ++c) X[c] = c <= j ? v[c] : T(0);
     }
   }
   __syncthreads();
+}
+
+// Rows 64 .. U of a frame with more than 64 rows: L_rJ = sum_{l<=J} A_rl X_Jl
+// (one output per thread, written after a barrier since the row is read).
+template <typename T, typename L>
+__device__ __forceinline__ void chol_tail(T* cur, const T* xs) {
+  constexpr int g = L::gam, R = L::U + 1;
+  if constexpr (R > 64) {
+    static_assert(L::n == 1, "frames of more than 64 rows: one node per level");
+    constexpr int NO = (R - 64) * g;
+    static_assert(NO <= NTB, "tail rows fit the workgroup");
+    const int e = threadIdx.x;
+    T val = T(0);
+    const int r = 64 + min(e, NO - 1) / g, J = min(e, NO - 1) % g;
+    if (e < NO) {
+      for (int l = 0; l <= J; ++l) val += cur[L::row(r) + l] * xs[J * g + l];
+    }
+    __syncthreads();
+    if (e < NO) cur[L::row(r) + J] = val;
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -258,8 +287,8 @@ template <typename T, int S, int K> constexpr int ext_regs() {
 // `tab` holds this thread's entries of the level's gather table, loaded into
 // registers while the level below was being eliminated.
 template <typename T, int S, int K>
-__device__ __forceinline__ void build_level(T* base, T* cur, T* cst, const DevBlocks& B, T* dg, int& bad_pivot,
-                                            const uint2 (&tab)[ext_regs<T, S, K>()]) {
+__device__ __forceinline__ void build_level(T* base, T* cur, T* cst, const DevBlocks& B, T* xs, int& bad_pivot,
+                                            const unsigned (&tab)[ext_regs<T, S, K>()]) {
   using L = Lv<S, K>;
   const int tid = threadIdx.x;
   constexpr int NB = NTB;
@@ -269,17 +298,17 @@ __device__ __forceinline__ void build_level(T* base, T* cur, T* cst, const DevBl
     constexpr int E = ext_count<S, K>(), NP = ext_regs<T, S, K>();
     T v[NP];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) v[j] = base[tab[j].x >> 16] + base[tab[j].y];
+    for (int j = 0; j < NP; ++j) v[j] = base[tab[j] & 0xffffu] + base[tab[j] >> 16];
 #pragma unroll
     for (int j = 0; j < NP; ++j)
-      if (j + 1 < NP || tid + NB * j < E) base[tab[j].x & 0xffffu] = v[j];
+      if (j + 1 < NP || tid + NB * j < E) cur[tid + NB * j] = v[j];
     __syncthreads();
   }
   // Partial Cholesky of the first gam columns: L (interface rows), P
   // (boundary rows) and z (load row) of every node.
-  constexpr int g = L::gam, ld = L::ldp;
-  T* rdg = dg + gam_nodes_from<S, 0>();
-  chol_regs<T, L>(cur, dg, rdg, bad_pivot);
+  constexpr int g = L::gam;
+  chol_regs<T, L>(cur, xs, bad_pivot);
+  chol_tail<T, L>(cur, xs);
   // Schur update of the boundary block and the load row (rank-g, eq.
   // SchurC1): S[i][l] -= sum_k P[i][k] P[l][k], g <= l <= i <= U.
   if constexpr (std::is_same<T, float>::value && g >= 7) {
@@ -294,8 +323,8 @@ __device__ __forceinline__ void build_level(T* base, T* cur, T* cst, const DevBl
       const int ti = tri_row(tq), tj = tq - ti * (ti + 1) / 2;
       T* F = cur + t * L::fsz;
       const int ra = g + ti * 32 + (lane & 31), rb = g + tj * 32 + (lane & 31);
-      const T* pa = F + min(ra, L::U) * ld;
-      const T* pb = F + min(rb, L::U) * ld;
+      const T* pa = F + L::row(min(ra, L::U));
+      const T* pb = F + L::row(min(rb, L::U));
       floatx16 acc;
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[v] = 0.f;
@@ -310,7 +339,7 @@ __device__ __forceinline__ void build_level(T* base, T* cur, T* cst, const DevBl
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int i = g + ti * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-        if (i <= L::U && l <= i) F[i * ld + l] -= acc[v];
+        if (i <= L::U && l <= i) F[L::row(i) + l] -= acc[v];
       }
     }
   } else {
@@ -322,71 +351,57 @@ __device__ __forceinline__ void build_level(T* base, T* cur, T* cst, const DevBl
       T* F = cur + t * L::fsz;
       T acc = T(0);
 #pragma unroll
-      for (int k = 0; k < g; ++k) acc += F[i * ld + k] * F[l * ld + k];
-      F[i * ld + l] -= acc;
+      for (int k = 0; k < g; ++k) acc += F[L::row(i) + k] * F[L::row(l) + k];
+      F[L::row(i) + l] -= acc;
     }
   }
   __syncthreads();
   // Local operators of every node -> compact store, g values per row
   // (Section 3.4: the interface values of a node follow from its boundary
-  // values and its load as u_gamma = A_gg^-1 (b_gamma - A_gG u_Gamma)):
-  //   rows 0 .. g-1   M = A_gg^-1, row c = L^-T L^-1 e_c
-  //   rows g .. U-1   W^T with W = A_gg^-1 A_gG, row j = L^-T p_j (p_j row j of P)
-  //   row  U          y = A_gg^-1 b_gamma = L^-T z
-  // One row per thread, both substitutions in registers.
+  // values and its load as u_gamma = A_gg^-1 (b_gamma - A_gG u_Gamma)).  With
+  // X = L_gg^-1 (lower):
+  //   rows 0 .. g-1   M = A_gg^-1 = X^T X
+  //   rows g .. U-1   W^T with W = A_gg^-1 A_gG = X^T P^T (row j: X^T p_j)
+  //   row  U          y = A_gg^-1 b_gamma = X^T z
+  // every entry a dot product over k >= i, one entry per thread.
   T* out = cst + B.lv[K].cst_off;
-  for (int e = tid; e < L::n * L::ld; e += NB) {
-    const int t = e / L::ld, r = e % L::ld;
+  for (int e = tid; e < L::n * L::per; e += NB) {
+    const int t = e / L::per, rc = e % L::per;
+    const int r = rc / g, i = rc % g;
+    const T* X = xs + t * g * g;
     const T* F = cur + t * L::fsz;
-    const T* rd = rdg + t * g;
-    T w[g];
+    T val = T(0);
     if (r < g) {
-#pragma unroll
-      for (int i = 0; i < g; ++i) {
-        T v = (i == r) ? T(1) : T(0);
-#pragma unroll
-        for (int l = 0; l < i; ++l) v -= F[i * ld + l] * w[l];
-        w[i] = v * rd[i];
-      }
+      for (int k = max(r, i); k < g; ++k) val += X[k * g + r] * X[k * g + i];
     } else {
-#pragma unroll
-      for (int i = 0; i < g; ++i) w[i] = F[r * ld + i];
+      for (int k = i; k < g; ++k) val += X[k * g + i] * F[L::row(r) + k];
     }
-#pragma unroll
-    for (int i = g - 1; i >= 0; --i) {
-      T v = w[i];
-#pragma unroll
-      for (int l = i + 1; l < g; ++l) v -= F[l * ld + i] * w[l];
-      w[i] = v * rd[i];
-    }
-    T* o = out + t * L::per + r * g;
-#pragma unroll
-    for (int i = 0; i < g; ++i) o[i] = w[i];
+    out[e] = val;
   }
   __syncthreads();
 }
 
 // Loads this thread's entries of level K's gather table.
 template <typename T, int S, int K>
-__device__ __forceinline__ void load_ext(const DevBlocks& B, uint2 (&tab)[ext_regs<T, S, K>()]) {
+__device__ __forceinline__ void load_ext(const DevBlocks& B, unsigned (&tab)[ext_regs<T, S, K>()]) {
   constexpr int E = ext_count<S, K>();
   if constexpr (E > 0) {
-    const uint2* src = B.ext + ext_off<S, K>();
+    const unsigned* src = B.ext + ext_off<S, K>();
 #pragma unroll
     for (int j = 0; j < ext_regs<T, S, K>(); ++j) tab[j] = src[min(int(threadIdx.x) + NTB * j, E - 1)];
   }
 }
 
 template <typename T, int S, int K>
-__device__ __forceinline__ void build_levels(T* base, T* cur, T* prev, T* cst, const DevBlocks& B, T* dg,
-                                             int& bad_pivot, const uint2 (&tab)[ext_regs<T, S, K>()]) {
+__device__ __forceinline__ void build_levels(T* base, T* cur, T* prev, T* cst, const DevBlocks& B, T* xs,
+                                             int& bad_pivot, const unsigned (&tab)[ext_regs<T, S, K>()]) {
   if constexpr (K > 0) {
-    uint2 nxt[ext_regs<T, S, K - 1>()];
+    unsigned nxt[ext_regs<T, S, K - 1>()];
     load_ext<T, S, K - 1>(B, nxt);
-    build_level<T, S, K>(base, cur, cst, B, dg, bad_pivot, tab);
-    build_levels<T, S, K - 1>(base, prev, cur, cst, B, dg, bad_pivot, nxt);
+    build_level<T, S, K>(base, cur, cst, B, xs, bad_pivot, tab);
+    build_levels<T, S, K - 1>(base, prev, cur, cst, B, xs, bad_pivot, nxt);
   } else {
-    build_level<T, S, K>(base, cur, cst, B, dg, bad_pivot, tab);
+    build_level<T, S, K>(base, cur, cst, B, xs, bad_pivot, tab);
   }
 }
 
@@ -400,13 +415,13 @@ __global__ void __launch_bounds__(NTB) k_block_build(DevBlocks B, int n_samples,
   T* buf0 = reinterpret_cast<T*>(smem);
   T* buf1 = buf0 + B.max_buf;
   __shared__ int bad_pivot;
-  __shared__ T dg[2 * gam_nodes_from<S, 0>()];  // pivots, then their reciprocals
+  __shared__ T xs[inv_size_from<S, 0>()];  // X = L_gg^-1 of every node of the current level
   const int q = blockIdx.x / n_samples;
   const int s = blockIdx.x % n_samples;
   const int X0 = B.origin[2 * q], Y0 = B.origin[2 * q + 1];
   const int tid = threadIdx.x;
   // the first extend-add's gather entries are in flight during the assembly
-  uint2 first[ext_regs<T, S, (Lm > 0 ? Lm - 1 : 0)>()];
+  unsigned first[ext_regs<T, S, (Lm > 0 ? Lm - 1 : 0)>()];
   if constexpr (Lm > 0) load_ext<T, S, Lm - 1>(B, first);
   if (tid == 0) {
     bad_pivot = 0;
@@ -456,10 +471,10 @@ __global__ void __launch_bounds__(NTB) k_block_build(DevBlocks B, int n_samples,
 #pragma unroll
               for (int b = 0; b < 3; ++b) {
                 const int ib = c_mb_local[vy[b]][vx[b]];
-                if (ib <= ia) F[ia * M::ldp + ib] += T(scale * (gx[a] * gx[b] + gy[a] * gy[b]));
+                if (ib <= ia) F[M::row(ia) + ib] += T(scale * (gx[a] * gx[b] + gy[a] * gy[b]));
               }
               const double fv = fL[(b0 + vy[a]) * S1 + (a0 + vx[a])];
-              F[9 * M::ldp + ia] += T(area * fv / 3.0);
+              F[M::row(9) + ia] += T(area * fv / 3.0);
             }
           }
       if (!ok && bad) atomicCAS(bad + s, 0, 1);
@@ -469,9 +484,9 @@ __global__ void __launch_bounds__(NTB) k_block_build(DevBlocks B, int n_samples,
   T* cst = cst_block<T>(B, q, s);
   int bp = 0;
   {
-    const uint2 none[1] = {make_uint2(0u, 0u)};
-    build_level<T, S, Lm>(buf0, buf0, cst, B, dg, bp, none);
-    if constexpr (Lm > 0) build_levels<T, S, Lm - 1>(buf0, buf1, buf0, cst, B, dg, bp, first);
+    const unsigned none[1] = {0u};
+    build_level<T, S, Lm>(buf0, buf0, cst, B, xs, bp, none);
+    if constexpr (Lm > 0) build_levels<T, S, Lm - 1>(buf0, buf1, buf0, cst, B, xs, bp, first);
   }
   if (bp) bad_pivot = 1;
   __syncthreads();
@@ -483,7 +498,7 @@ __global__ void __launch_bounds__(NTB) k_block_build(DevBlocks B, int n_samples,
     T* G = reinterpret_cast<T*>(B.top.frames) + (long long)s * B.top.stride + nd.frame_off;
     for (int e = tid; e < R::ld * R::ld; e += NTB) {
       const int r = e / R::ld, c = e % R::ld;
-      if (c <= r) G[(long long)r * nd.ld + c] = root[r * R::ldp + c];
+      if (c <= r) G[(long long)r * nd.ld + c] = root[R::row(r) + c];
     }
   }
   if (tid == 0 && bad_pivot && info) atomicCAS(info + s, 0, B.top.node_base + q + 1);
@@ -642,7 +657,7 @@ template <typename T, int S, int K> struct FwLevel {
 template <typename T, int S, int K> struct FwRegs {
   using C = FwLevel<T, S, K>;
   T w[C::R][C::NI];
-  uint2 e[C::NE];
+  unsigned e[C::NE];
 };
 
 template <typename T, int S, int K, bool First = (K == 0)> struct FwAll;
@@ -672,7 +687,7 @@ __device__ __forceinline__ void fw_load(const DevBlocks& B, const T* cst, FwAll<
     for (int ii = 0; ii < C::NI; ++ii) a.r.w[rr][ii] = row[min(p + P * ii, g - 1)];  // masked at use
   }
   if constexpr (K < L::Lm) {
-    const uint2* src = B.ext + ext_total<S>() + fext_off<S, K>();
+    const unsigned* src = B.ext + ext_total<S>() + fext_off<S, K>();
 #pragma unroll
     for (int k = 0; k < C::NE; ++k) a.r.e[k] = src[min(tid + NT * k, fext_count<S, K>() - 1)];
   }
@@ -689,7 +704,7 @@ __device__ __forceinline__ void fw_level(const FwAll<T, S, K>& a, const DevBlock
   if constexpr (K < L::Lm) {
     double v[C::NE];
 #pragma unroll
-    for (int k = 0; k < C::NE; ++k) v[k] = gb[a.r.e[k].x] + gb[a.r.e[k].y];
+    for (int k = 0; k < C::NE; ++k) v[k] = gb[a.r.e[k] & 0xffffu] + gb[a.r.e[k] >> 16];
 #pragma unroll
     for (int k = 0; k < C::NE; ++k)
       if (k + 1 < C::NE || tid + NT * k < L::n * U) cur[tid + NT * k] = v[k];
@@ -785,14 +800,14 @@ size_t block_ext_entries(int s) {
   }
 }
 
-template <int S> static void launch_ext_t(const DevBlocks& B, uint2* ext, hipStream_t st) {
+template <int S> static void launch_ext_t(const DevBlocks& B, unsigned* ext, hipStream_t st) {
   constexpr int n = ext_total<S>() + fext_total<S>();
   if (n > 0) hipLaunchKernelGGL((k_block_ext<S>), dim3((n + 255) / 256), dim3(256), 0, st, B, ext);
 }
 
-hipError_t launch_block_ext(const DevBlocks& B, uint2* ext, hipStream_t st) {
-  // every offset (and the zero slot) must fit the build table's 16-bit fields
-  if (2 * B.max_buf >= 65536) return hipErrorInvalidValue;
+hipError_t launch_block_ext(const DevBlocks& B, unsigned* ext, hipStream_t st) {
+  // every offset (and the zero slots) must fit the tables' 16-bit fields
+  if (2 * B.max_buf >= 65536 || 2 * B.max_bnd_nodes >= 65536) return hipErrorInvalidValue;
   switch (B.s) {
     case 2: launch_ext_t<2>(B, ext, st); break;
     case 4: launch_ext_t<4>(B, ext, st); break;

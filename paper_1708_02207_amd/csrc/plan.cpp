@@ -114,7 +114,7 @@ bool build_template(int s, SubTemplate& T, std::string& err) {
     L.gam = int(nodes[0].gam.size());
     L.bnd = int(nodes[0].bnd.size());
     L.U = L.gam + L.bnd;
-    L.fsz = (L.U + 1) * ((L.U + 1) | 1);  // LDS frame: U+1 rows, odd row stride
+    L.fsz = (L.U + 1) * (L.U + 2) / 2;  // LDS frame: U+1 rows, packed lower triangle
     L.cst_off = cst;
     L.vec_off = vec;
     L.lid_off = int(T.lids.size());

@@ -66,7 +66,7 @@ struct SubLevel {
   int n;          // nodes on this level
   int gam, bnd;   // |gamma|, |Gamma| (uniform on the level, Dirichlet kept)
   int U;          // gam + bnd
-  int fsz;        // frame elements in LDS: U+1 rows with the odd row stride (U+1)|1
+  int fsz;        // frame elements in LDS: U+1 rows, packed lower triangle
   int cst_off;    // offset of the level's retained blocks in a block's compact store
   int vec_off;    // offset of the level's z values in a block's vector store
   int map_off;    // into maps: node t uses maps[map_off + t*2*(U+1) ...] (levels above micro)
