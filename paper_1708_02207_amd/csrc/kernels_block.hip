@@ -343,16 +343,26 @@ __device__ __forceinline__ void build_level(T* base, T* cur, T* cst, const DevBl
       }
     }
   } else {
+    // one thread per row i >= g: its P entries in registers, the columns
+    // l = g .. i unrolled (compile-time offsets; P rows l read by every
+    // thread of the node at once)
     constexpr int nr = L::U + 1 - g;
-    for (int e = tid; e < L::n * nr * nr; e += NB) {
-      const int t = e / (nr * nr), p = e % (nr * nr);
-      const int i = g + p / nr, l = g + p % nr;
-      if (l > i) continue;
+    for (int e = tid; e < L::n * nr; e += NB) {
+      const int t = e / nr, i = g + e % nr;
       T* F = cur + t * L::fsz;
-      T acc = T(0);
+      T* Fi = F + L::row(i);
+      T pi[g];
 #pragma unroll
-      for (int k = 0; k < g; ++k) acc += F[L::row(i) + k] * F[L::row(l) + k];
-      F[L::row(i) + l] -= acc;
+      for (int k = 0; k < g; ++k) pi[k] = Fi[k];
+#pragma unroll
+      for (int l = g; l <= L::U; ++l) {
+        if (l <= i) {
+          T acc = T(0);
+#pragma unroll
+          for (int k = 0; k < g; ++k) acc += pi[k] * F[L::row(l) + k];
+          Fi[l] -= acc;
+        }
+      }
     }
   }
   __syncthreads();
@@ -363,18 +373,22 @@ __device__ __forceinline__ void build_level(T* base, T* cur, T* cst, const DevBl
   //   rows 0 .. g-1   M = A_gg^-1 = X^T X
   //   rows g .. U-1   W^T with W = A_gg^-1 A_gG = X^T P^T (row j: X^T p_j)
   //   row  U          y = A_gg^-1 b_gamma = X^T z
-  // every entry a dot product over k >= i, one entry per thread.
+  // every entry a dot product over k (X is stored with zeros above its
+  // diagonal, so the full-length sums are exact), one entry per thread.
   T* out = cst + B.lv[K].cst_off;
   for (int e = tid; e < L::n * L::per; e += NB) {
     const int t = e / L::per, rc = e % L::per;
     const int r = rc / g, i = rc % g;
-    const T* X = xs + t * g * g;
-    const T* F = cur + t * L::fsz;
+    const T* Xi = xs + t * g * g + i;
+    const T* V = r < g ? xs + t * g * g + r : nullptr;  // column r of X, or row r of the frame
+    const T* Fr = cur + t * L::fsz + L::row(r);
     T val = T(0);
     if (r < g) {
-      for (int k = max(r, i); k < g; ++k) val += X[k * g + r] * X[k * g + i];
+#pragma unroll
+      for (int k = 0; k < g; ++k) val += V[k * g] * Xi[k * g];
     } else {
-      for (int k = i; k < g; ++k) val += X[k * g + i] * F[L::row(r) + k];
+#pragma unroll
+      for (int k = 0; k < g; ++k) val += Fr[k] * Xi[k * g];
     }
     out[e] = val;
   }
@@ -496,10 +510,9 @@ __global__ void __launch_bounds__(NTB) k_block_build(DevBlocks B, int n_samples,
     const T* root = (Lm % 2 == 0) ? buf0 : buf1;
     const DevNode nd = B.top.nodes[q];
     T* G = reinterpret_cast<T*>(B.top.frames) + (long long)s * B.top.stride + nd.frame_off;
-    for (int e = tid; e < R::ld * R::ld; e += NTB) {
-      const int r = e / R::ld, c = e % R::ld;
-      if (c <= r) G[(long long)r * nd.ld + c] = root[R::row(r) + c];
-    }
+    const int lane = tid & 63;
+    for (int r = tid >> 6; r < R::ld; r += NTB / 64)  // one row per wave
+      for (int c = lane; c <= r; c += 64) G[(long long)r * nd.ld + c] = root[R::row(r) + c];
   }
   if (tid == 0 && bad_pivot && info) atomicCAS(info + s, 0, B.top.node_base + q + 1);
 }
