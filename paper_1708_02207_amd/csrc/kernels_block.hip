@@ -31,10 +31,92 @@ namespace hdd {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-__constant__ int c_mb_local[3][3] = {  // micro-block local node (a, b) -> frame index
-    {1, 2, 3},
-    {8, 0, 4},
-    {7, 6, 5}};
+constexpr int NT = 256;   // threads of the top-down / forward kernels
+constexpr int NTB = 512;  // threads of the build kernel
+
+// ---------------------------------------------------------------------------
+// Local systems of the micro-blocks (Section 3.1): 2 x 2 cells, 8 triangles,
+// 9 nodes numbered in the frame as
+//      y=2:  7 6 5
+//      y=1:  8 0 4        (0 = the micro-block's interface node)
+//      y=0:  1 2 3
+// Every entry of the packed 10-row frame (rows 0..8 the nodes, row 9 the
+// load) is a fixed combination of the 8 triangle coefficients (eq. coefA:
+// kappa_T (grad phi_a . grad phi_b) |T|, in cell units) or of the nodal load
+// (eq. coefc, vertex rule: |T| / 3 per triangle at the node).  The
+// combinations are tabulated at compile time; triangle tr = (cb*2 + ca)*2 + tri
+// of cell (ca, cb) has the vertices (0,0),(1,0),(1,1) (tri 0) or
+// (0,0),(1,1),(0,1) (tri 1) relative to the cell corner.
+struct MicroTable {
+  int nt[45];         // nonzero terms of stiffness entry e (packed (r, c), c <= r < 9)
+  int tr[45][6];      // their triangles
+  double co[45][6];   // and coefficients
+  int cnt[9];         // triangles at node c
+  int nx[9], ny[9];   // local coordinates of node c
+};
+
+constexpr MicroTable make_micro_table() {
+  MicroTable m{};
+  const int fidx[3][3] = {{1, 2, 3}, {8, 0, 4}, {7, 6, 5}};  // [y][x]
+  for (int y = 0; y < 3; ++y)
+    for (int x = 0; x < 3; ++x) {
+      m.nx[fidx[y][x]] = x;
+      m.ny[fidx[y][x]] = y;
+    }
+  for (int cb = 0; cb < 2; ++cb)
+    for (int ca = 0; ca < 2; ++ca)
+      for (int tri = 0; tri < 2; ++tri) {
+        const int tr = (cb * 2 + ca) * 2 + tri;
+        const int vx[3] = {ca, ca + 1, tri == 0 ? ca + 1 : ca};
+        const int vy[3] = {cb, tri == 0 ? cb : cb + 1, cb + 1};
+        const int det = (vx[1] - vx[0]) * (vy[2] - vy[0]) - (vx[2] - vx[0]) * (vy[1] - vy[0]);
+        const int gx[3] = {vy[1] - vy[2], vy[2] - vy[0], vy[0] - vy[1]};
+        const int gy[3] = {vx[2] - vx[1], vx[0] - vx[2], vx[1] - vx[0]};
+        for (int a = 0; a < 3; ++a) {
+          const int ia = fidx[vy[a]][vx[a]];
+          m.cnt[ia] += 1;
+          for (int b = 0; b < 3; ++b) {
+            const int ib = fidx[vy[b]][vx[b]];
+            const int num = gx[a] * gx[b] + gy[a] * gy[b];
+            if (ib <= ia && num != 0) {
+              const int e = ia * (ia + 1) / 2 + ib;
+              m.tr[e][m.nt[e]] = tr;
+              m.co[e][m.nt[e]] = double(num) / (2.0 * double(det < 0 ? -det : det));
+              m.nt[e] += 1;
+            }
+          }
+        }
+      }
+  return m;
+}
+constexpr MicroTable kMicro = make_micro_table();
+
+template <int E, int Q> __device__ __forceinline__ double micro_sum(const double (&kap)[8]) {
+  constexpr double c = kMicro.co[E][Q];
+  constexpr int tr = kMicro.tr[E][Q];
+  if constexpr (Q + 1 < kMicro.nt[E]) return c * kap[tr] + micro_sum<E, Q + 1>(kap);
+  else return c * kap[tr];
+}
+
+// Entries E, E + NW, ... of the frame of micro-block t (wave wv takes the
+// entries with E % NW == wv, one micro-block per lane).
+template <typename T, int S, int E>
+__device__ __forceinline__ void micro_entries(T* F, const double (&kap)[8], const double* fL, int a0, int b0,
+                                              double area3, bool act, int wv) {
+  if constexpr (E < 55) {
+    if (E % (NTB / 64) == wv) {
+      double v = 0.0;
+      if constexpr (E < 45) {
+        if constexpr (kMicro.nt[E] > 0) v = micro_sum<E, 0>(kap);
+      } else if constexpr (E < 54) {
+        constexpr int c = E - 45;
+        v = double(kMicro.cnt[c]) * area3 * fL[(b0 + kMicro.ny[c]) * (S + 1) + a0 + kMicro.nx[c]];
+      }
+      if (act) F[E] = T(v);
+    }
+    micro_entries<T, S, E + 1>(F, kap, fL, a0, b0, area3, act, wv);
+  }
+}
 
 constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
 
@@ -154,8 +236,6 @@ template <int S, int K> constexpr int inv_size_from() {
   }
 }
 
-constexpr int NT = 256;   // threads of the top-down / forward kernels
-constexpr int NTB = 512;  // threads of the build kernel
 
 // ---------------------------------------------------------------------------
 // Partial Cholesky of the first gam columns of every frame of a level in
@@ -454,45 +534,27 @@ __global__ void __launch_bounds__(NTB) k_block_build(DevBlocks B, int n_samples,
     }
     for (int e = tid; e < S1 * S1; e += NTB) fL[e] = f[(long long)(Y0 + e / S1) * (nc + 1) + X0 + e % S1];
   }
-  // micro-blocks: assemble the 9 x 9 local systems (lower triangle + load row)
-  for (int e = tid; e < M::n * M::fsz; e += NTB) buf0[e] = T(0);
   __syncthreads();
+  // micro-blocks: every entry of the packed 10-row frames (lower triangle and
+  // load row) written once, one micro-block per lane
   {
+    static_assert(M::n <= 64 && M::fsz == 55, "micro-block frames");
     const double h = 1.0 / nc;
-    const double area = 0.5 * h * h;
-    for (int t = tid; t < M::n; t += NTB) {
-      T* F = buf0 + t * M::fsz;
-      const int a0 = B.micro_xy[2 * t], b0 = B.micro_xy[2 * t + 1];  // local corner
-      bool ok = true;
+    const double area3 = 0.5 * h * h / 3.0;
+    const int lane = tid & 63, wv = tid >> 6;
+    const bool act = lane < M::n;
+    const int t = act ? lane : 0;
+    const int a0 = B.micro_xy[2 * t], b0 = B.micro_xy[2 * t + 1];  // local corner
+    double kap[8];
+    bool ok = true;
 #pragma unroll
-      for (int cb = 0; cb < 2; ++cb)
-#pragma unroll
-        for (int ca = 0; ca < 2; ++ca)
-#pragma unroll
-          for (int tri = 0; tri < 2; ++tri) {
-            // T-: (0,0),(1,0),(1,1); T+: (0,0),(1,1),(0,1) relative to the cell corner
-            const int vx[3] = {ca, ca + 1, tri == 0 ? ca + 1 : ca};
-            const int vy[3] = {cb, tri == 0 ? cb : cb + 1, cb + 1};
-            const double kap = kL[(b0 + cb) * 2 * S + (a0 + ca) * 2 + tri];
-            ok = ok && (kap > 0.0) && (kap < 1.0e300);
-            const double det = double((vx[1] - vx[0]) * (vy[2] - vy[0]) - (vx[2] - vx[0]) * (vy[1] - vy[0]));
-            const double gx[3] = {double(vy[1] - vy[2]), double(vy[2] - vy[0]), double(vy[0] - vy[1])};
-            const double gy[3] = {double(vx[2] - vx[1]), double(vx[0] - vx[2]), double(vx[1] - vx[0])};
-            const double scale = kap / (2.0 * fabs(det));
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              const int ia = c_mb_local[vy[a]][vx[a]];
-#pragma unroll
-              for (int b = 0; b < 3; ++b) {
-                const int ib = c_mb_local[vy[b]][vx[b]];
-                if (ib <= ia) F[M::row(ia) + ib] += T(scale * (gx[a] * gx[b] + gy[a] * gy[b]));
-              }
-              const double fv = fL[(b0 + vy[a]) * S1 + (a0 + vx[a])];
-              F[M::row(9) + ia] += T(area * fv / 3.0);
-            }
-          }
-      if (!ok && bad) atomicCAS(bad + s, 0, 1);
+    for (int tr = 0; tr < 8; ++tr) {
+      const int cb = tr >> 2, ca = (tr >> 1) & 1, tri = tr & 1;
+      kap[tr] = kL[(b0 + cb) * 2 * S + (a0 + ca) * 2 + tri];
+      ok = ok && (kap[tr] > 0.0) && (kap[tr] < 1.0e300);
     }
+    micro_entries<T, S, 0>(buf0 + t * M::fsz, kap, fL, a0, b0, area3, act, wv);
+    if (wv == 0 && act && !ok && bad) atomicCAS(bad + s, 0, 1);
   }
   __syncthreads();
   T* cst = cst_block<T>(B, q, s);
