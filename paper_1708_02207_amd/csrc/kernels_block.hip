@@ -289,20 +289,22 @@ __device__ __forceinline__ void chol_regs(T* cur, T* xs, int& bad_pivot) {
     T a[g];
 #pragma unroll
     for (int c = 0; c < g; ++c) a[c] = F[L::row(r) + c];  // c > r: unused
+    // Entries above the diagonal (a[c], c > j) are updated like the others
+    // but never read back or written out, so no masks are needed.
     T rdj = T(1);  // 1 / L_jj in lane j < g
 #pragma unroll
     for (int J = 0; J < g; ++J) {
-      T d = group_read<T, GS>(a[J], GS == 64 ? J : gbase + J);
-      const bool ok = (d > T(0)) && (d < T(1e300));
+      const T p = group_read<T, GS>(a[J], GS == 64 ? J : gbase + J);
+      const bool ok = (p > T(0)) && (p < T(1e300));
       if (!ok && act) bad_pivot = 1;
-      d = ok ? T(sqrt(d)) : T(1);
-      const T rd = T(1) / d;
+      const T d = ok ? T(sqrt(p)) : T(1);  // correctly rounded: the refinement's
+      const T rd = T(1) / d;               // contraction depends on these pivots
       if (j == J) rdj = rd;
-      a[J] = j == J ? d : (j > J ? a[J] * rd : a[J]);
+      a[J] = j == J ? d : a[J] * rd;
 #pragma unroll
       for (int k = J + 1; k < g; ++k) {
         const T lk = group_read<T, GS>(a[J], GS == 64 ? k : gbase + k);  // L_kJ
-        if (j >= k) a[k] -= a[J] * lk;
+        a[k] -= a[J] * lk;
       }
     }
     if (act && j < C::RR) {
@@ -310,27 +312,29 @@ __device__ __forceinline__ void chol_regs(T* cur, T* xs, int& bad_pivot) {
       for (int c = 0; c < g; ++c)
         if (c <= j) F[L::row(j) + c] = a[c];
     }
-    // X = L_gg^-1: lane i accumulates v_c = -sum_{k<i} L_ik X_kc and
-    // finishes its row at step k = i
+    // X = L_gg^-1: lane i accumulates v_c = -sum_{k<i} L_ik X_kc, finishes
+    // its row at step k = i and stores it then (later updates of a finished
+    // row are harmless)
     T v[g];
 #pragma unroll
     for (int c = 0; c < g; ++c) v[c] = T(0);
+    T* X = xs + (act ? t : 0) * g * g + min(j, g - 1) * g;
 #pragma unroll
     for (int k = 0; k < g; ++k) {
       if (j == k) {
+        v[k] += T(1);
 #pragma unroll
-        for (int c = 0; c <= k; ++c) v[c] = (c == k ? T(1) + v[c] : v[c]) * rdj;
+        for (int c = 0; c <= k; ++c) v[c] *= rdj;
+        if (act) {
+#pragma unroll
+          for (int c = 0; c < g; ++c) X[c] = c <= k ? v[c] : T(0);
+        }
       }
 #pragma unroll
       for (int c = 0; c <= k; ++c) {
         const T xk = group_read<T, GS>(v[c], GS == 64 ? k : gbase + k);  // X_kc
-        if (j > k) v[c] -= a[k] * xk;
+        v[c] -= a[k] * xk;
       }
-    }
-    if (act && j < g) {
-      T* X = xs + t * g * g + j * g;
-#pragma unroll
-      for (int c = 0; c < g; ++c) X[c] = c <= j ? v[c] : T(0);
     }
   }
   __syncthreads();
@@ -402,24 +406,31 @@ __device__ __forceinline__ void build_level(T* base, T* cur, T* cst, const DevBl
       const int t = q / (nt * (nt + 1) / 2), tq = q % (nt * (nt + 1) / 2);
       const int ti = tri_row(tq), tj = tq - ti * (ti + 1) / 2;
       T* F = cur + t * L::fsz;
+      // rows beyond U are clamped: they only feed accumulator rows and
+      // columns that are not written back
       const int ra = g + ti * 32 + (lane & 31), rb = g + tj * 32 + (lane & 31);
-      const T* pa = F + L::row(min(ra, L::U));
-      const T* pb = F + L::row(min(rb, L::U));
+      const T* pa = F + L::row(min(ra, L::U)) + (lane >> 5);
+      const T* pb = F + L::row(min(rb, L::U)) + (lane >> 5);
       floatx16 acc;
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[v] = 0.f;
 #pragma unroll
       for (int kk = 0; kk < g; kk += 2) {
-        const int k = kk + (lane >> 5);
-        const float av = (k < g && ra <= L::U) ? pa[k] : 0.f;
-        const float bv = (k < g && rb <= L::U) ? pb[k] : 0.f;
+        float av = pa[kk], bv = pb[kk];
+        if (kk + 1 == g) av = (lane >> 5) ? 0.f : av;  // odd g: column g is not in P
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
       }
+      // accumulator v of this lane: row i0 + d(v), column l
       const int l = g + tj * 32 + (lane & 31);
+      const int i0 = g + ti * 32 + (lane >> 5) * 4;
+      T* Fl = F + L::row(i0) + l;
+      const bool edge = ti == tj || g + ti * 32 + 31 > L::U;  // wave-uniform
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int i = g + ti * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-        if (i <= L::U && l <= i) F[L::row(i) + l] -= acc[v];
+        const int d = (v >> 2) * 8 + (v & 3);
+        // row(i0 + d) = row(i0) + d * i0 + d (d + 1) / 2
+        T* p = Fl + d * i0 + d * (d + 1) / 2;
+        if (!edge || (i0 + d <= L::U && l <= i0 + d)) *p -= acc[v];
       }
     }
   } else {
