@@ -219,7 +219,9 @@ int hdd_debug_node_schur(hdd_handle h, int32_t sample, int32_t depth, int32_t in
 
 /* Raw frame of one built node (lower triangle, [gamma ; Gamma ; rhs] order,
  * upper triangle returned as zeros): out host float64 [(U+1)^2] with room for
- * the largest frame of the level; *U_out = U.  Synchronizes. */
+ * the largest frame of the level; *U_out = U.  The first gamma columns are the
+ * retained [L ; P ; z] (read from the level's panel store where it has one).
+ * Synchronizes. */
 int hdd_debug_frame(hdd_handle h, int32_t sample, int32_t depth, int32_t index, double* out, int32_t* U_out);
 
 /* Timing of kernel classes with HIP events around every launch of the class

@@ -45,6 +45,25 @@ int validate_opts(const hdd_opts* o) {
   return HDD_OK;
 }
 
+// Levels above the blocks that the fused merge builds (float32 with float32
+// sons, gamma <= 31, the node's panel in LDS); they keep their retained
+// columns in a dense panel store.
+bool merge_level(const Plan& p, const hdd_opts& o, int d) {
+  const int D = int(p.levels.size()) - 1;  // the block level
+  if (d < 0 || d >= D || (o.flags & HDD_FLAG_NO_MFMA)) return false;
+  hdd::DevLevel t{};
+  t.gam = p.levels[d].gam;
+  t.max_U = p.levels[d].max_U;
+  t.is_double = level_double(o, d) ? 1 : 0;
+  return hdd::merge_small_ok(t, true) && !level_double(o, d + 1);
+}
+
+int64_t panel_elems(const Plan& p, int d) {
+  int64_t e = 0;
+  for (const auto& nd : p.levels[d].nodes) e += int64_t(nd.U() + 1) * p.levels[d].gam;
+  return e;
+}
+
 bool make_plan(const hdd_opts& o, Plan& p) {
   hdd::PlanOptions po;
   po.n = o.n;
@@ -56,7 +75,7 @@ bool make_plan(const hdd_opts& o, Plan& p) {
 
 // Byte offsets of everything the handle keeps in its device workspace.
 struct Layout {
-  std::vector<int64_t> frames, nodes, maps, ids, vec;
+  std::vector<int64_t> frames, nodes, maps, ids, vec, panel;
   int64_t kappa, f, u, d, r, info, bad, maxbits, qout, qxy, qy, qsmp, qoff, qsig, lists, iota;
   int64_t cst, bvec, tmaps, tlids, tmicro, origin, text;
   int64_t max_q;
@@ -72,7 +91,7 @@ Layout make_layout(const Plan& p, const hdd_opts& o, int ms) {
     return at;
   };
   const int nd = int(p.levels.size());
-  L.frames.resize(nd); L.nodes.resize(nd); L.maps.resize(nd); L.ids.resize(nd); L.vec.resize(nd);
+  L.frames.resize(nd); L.nodes.resize(nd); L.maps.resize(nd); L.ids.resize(nd); L.vec.resize(nd); L.panel.resize(nd);
   const bool refine = refinement_possible(o);
   int64_t total_nodes = 0, max_nodes = 0;
   for (int d = 0; d < nd; ++d) {
@@ -83,6 +102,7 @@ Layout make_layout(const Plan& p, const hdd_opts& o, int ms) {
     L.maps[d] = take(int64_t(lv.maps.size()) * 4);
     L.ids[d] = take(int64_t(lv.ids.size()) * 4);
     L.vec[d] = refine ? take(int64_t(lv.ids.size()) * 8 * ms) : -1;
+    L.panel[d] = merge_level(p, o, d) ? take(panel_elems(p, d) * 4 * ms) : -1;
     total_nodes += int64_t(lv.nodes.size());
     max_nodes = std::max<int64_t>(max_nodes, int64_t(lv.nodes.size()));
   }
@@ -457,8 +477,11 @@ int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* works
   for (int d = 0; d < nd; ++d) {
     const auto& pl = h->plan.levels[d];
     std::vector<DevNode> dn(pl.nodes.size());
+    int64_t poff = 0;
     for (size_t k = 0; k < pl.nodes.size(); ++k) {
       const auto& p = pl.nodes[k];
+      dn[k].panel_off = poff;
+      poff += int64_t(p.U() + 1) * pl.gam;
       dn[k].frame_off = p.frame_off;
       dn[k].map_off = p.map_off;
       dn[k].U = p.U();
@@ -471,6 +494,8 @@ int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* works
     DevLevel& lv = h->lev[d];
     lv.frames = h->ws + L.frames[d];
     lv.stride = pl.frame_elems;
+    lv.panel = L.panel[d] >= 0 ? h->ws + L.panel[d] : nullptr;
+    lv.panel_stride = L.panel[d] >= 0 ? panel_elems(h->plan, d) : 0;
     lv.nodes = reinterpret_cast<const DevNode*>(h->ws + L.nodes[d]);
     lv.maps = reinterpret_cast<const int*>(h->ws + L.maps[d]);
     lv.ids = reinterpret_cast<const int*>(h->ws + L.ids[d]);
@@ -646,7 +671,7 @@ int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double
   }));
   for (int d = D - 1; d >= 0; --d) {
     h->cur_level = d;
-    if (hdd::merge_small_ok(h->lev[d], mfma) && !h->lev[d + 1].is_double) {
+    if (merge_level(h->plan, h->opt, d)) {
       HDD_TRY(timed(h, K_MERGE, 0.0, [&] {
         return hdd::launch_merge_small(h->lev[d], h->lev[d + 1], n_samples, h->info, h->st);
       }));
@@ -942,6 +967,17 @@ int hdd_debug_frame(hdd_handle h, int32_t sample, int32_t depth, int32_t index, 
                                                   : double(reinterpret_cast<const float*>(buf.data())[k]))
                                           : 0.0;
     }
+  if (h->lev[depth].panel) {  // retained columns kept in the level's panel store (float32)
+    const int g = pl.gam;
+    int64_t poff = 0;
+    for (int k = 0; k < index; ++k) poff += int64_t(pl.nodes[k].U() + 1) * g;
+    std::vector<float> pan(size_t(n) * g);
+    const float* psrc = static_cast<const float*>(h->lev[depth].panel) +
+                        size_t(sample) * h->lev[depth].panel_stride + size_t(poff);
+    HIP_TRY(hipMemcpy(pan.data(), psrc, pan.size() * sizeof(float), hipMemcpyDeviceToHost));
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < g && c <= r; ++c) out[size_t(r) * n + c] = double(pan[size_t(r) * g + c]);
+  }
   *U_out = n - 1;
   return HDD_OK;
 }

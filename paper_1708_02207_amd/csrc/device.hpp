@@ -26,11 +26,18 @@ struct DevNode {
   int ld;               // frame leading dimension
   int ids_off;          // into the level's id array ([gamma ; Gamma] global node ids)
   int x0, y0;           // lower-left cell of the node's rectangle
+  long long panel_off;  // elements within the level's per-sample panel block (levels with a panel store)
 };
 
 struct DevLevel {
   void* frames;          // float* or double*
   long long stride;      // per-sample elements of this level
+  // Levels built by the fused merge keep the retained columns [L ; P ; z] of
+  // every node in a dense panel store, (U+1) x gamma per node with row stride
+  // gamma, instead of in the frame's first gamma columns (the sweeps then
+  // read contiguous rows).  nullptr elsewhere.
+  void* panel;
+  long long panel_stride;  // per-sample elements of the panel store
   const DevNode* nodes;
   const int* maps;
   const int* ids;
@@ -76,6 +83,17 @@ struct DevBlocks {
 
 template <typename T> __device__ __forceinline__ T* frame_ptr(const DevLevel& L, int node, int s) {
   return reinterpret_cast<T*>(L.frames) + (long long)s * L.stride + L.nodes[node].frame_off;
+}
+
+// Retained columns [L ; P ; z] of a node and their row stride: the panel
+// store when the level has one, else the frame's first gamma columns.
+template <typename T> __device__ __forceinline__ T* retained_ptr(const DevLevel& L, int node, int s, int& ld) {
+  if (L.panel) {
+    ld = L.gam;
+    return reinterpret_cast<T*>(L.panel) + (long long)s * L.panel_stride + L.nodes[node].panel_off;
+  }
+  ld = L.nodes[node].ld;
+  return frame_ptr<T>(L, node, s);
 }
 
 __device__ __forceinline__ int tri_row(long long e) {

@@ -653,10 +653,16 @@ __global__ void __launch_bounds__(NT) k_merge_small(DevLevel F, DevLevel S, int 
     for (int k = 0; k < GP; ++k) P[r * KP + k] = x[k];
   }
   __syncthreads();
-  // 3. panel -> frame (lower part of the interface rows, all columns below)
-  for (int e = tid; e < n * GP; e += NT) {
-    const int r = e / GP, c = e % GP;
-    if (c < g && c <= r) Fo[(long long)r * ld + c] = P[r * KP + c];
+  // 3. panel -> the level's panel store, (U+1) x gamma dense (zeros above the
+  // diagonal of L), or the frame's first gamma columns
+  if (F.panel) {
+    float* Po = reinterpret_cast<float*>(F.panel) + (long long)s * F.panel_stride + nd.panel_off;
+    for (int e = tid; e < n * g; e += NT) Po[e] = P[(e / g) * KP + e % g];
+  } else {
+    for (int e = tid; e < n * GP; e += NT) {
+      const int r = e / GP, c = e % GP;
+      if (c < g && c <= r) Fo[(long long)r * ld + c] = P[r * KP + c];
+    }
   }
   // 4. Schur update tiles over rows / columns g..U (lower tiles only)
   const int nt = (n - g + 31) / 32;

@@ -221,12 +221,13 @@ __global__ void __launch_bounds__(BS) k_topdown(DevLevel L, const int* __restric
   const int node = list[e / n_samples];
   const int s = e % n_samples;
   const DevNode nd = L.nodes[node];
-  const int g = L.gam, G = nd.bnd, U = nd.U, ld = nd.ld;
+  const int g = L.gam, G = nd.bnd, U = nd.U;
   const int nbm = solve_nb(g);
   double* r = dyn;                 // [g]
   double* ub = dyn + g;            // [G]
   double* part = dyn + (L.max_U + 1);
-  const T* F = frame_ptr<T>(L, node, s);
+  int ld;
+  const T* F = retained_ptr<T>(L, node, s, ld);
   const int* ids = L.ids + nd.ids_off;
   double* us = u + (long long)s * ustride;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -297,12 +298,13 @@ __global__ void __launch_bounds__(256) k_topdown_gemv(DevLevel L, const int* __r
   const int node = list[e / n_samples];
   const int s = e % n_samples;
   const DevNode nd = L.nodes[node];
-  const int g = L.gam, G = nd.bnd, U = nd.U, ld = nd.ld;
+  const int g = L.gam, G = nd.bnd, U = nd.U;
   const int i0 = blockIdx.y * 64;
   if (i0 >= g) return;  // uniform
   double* ub = dyn;                  // [G]
   double* part = dyn + (L.max_U - L.gam);    // [4][64]
-  const T* F = frame_ptr<T>(L, node, s);
+  int ld;
+  const T* F = retained_ptr<T>(L, node, s, ld);
   const int* ids = L.ids + nd.ids_off;
   double* us = u + (long long)s * ustride;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -334,10 +336,11 @@ __global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int n_sa
   const int node = e / n_samples;
   const int s = e % n_samples;
   const DevNode nd = L.nodes[node];
-  const int g = L.gam, G = nd.bnd, U = nd.U, ld = nd.ld;
+  const int g = L.gam, G = nd.bnd, U = nd.U;
   const int nbm = solve_nb(g);
   double* gt = dyn;  // [U]
-  const T* F = frame_ptr<T>(L, node, s);
+  int ld;
+  const T* F = retained_ptr<T>(L, node, s, ld);
   const int tid = threadIdx.x;
   {
     const int* mA = L.maps + nd.map_off;
@@ -391,10 +394,11 @@ __global__ void __launch_bounds__(256) k_forward_gemv(DevLevel L, int n_samples)
   const int node = e / n_samples;
   const int s = e % n_samples;
   const DevNode nd = L.nodes[node];
-  const int g = L.gam, G = nd.bnd, ld = nd.ld;
+  const int g = L.gam, G = nd.bnd;
   const int j0 = blockIdx.y * 128;
   if (j0 >= G) return;  // uniform
-  const T* F = frame_ptr<T>(L, node, s);
+  int ld;
+  const T* F = retained_ptr<T>(L, node, s, ld);
   double* out = L.vec + (long long)s * L.vec_stride + nd.ids_off;
   double* z = dyn;
   T* tile = reinterpret_cast<T*>(dyn + g) + (threadIdx.x >> 6) * 32 * 65;  // per wave 32 x 65
