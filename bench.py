@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-steps", type=int, default=1, help="extra steps with per-kernel event timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-mix measurement")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the float64 batched full / partial top-down steps reported beside the headline")
     ap.add_argument("--serve-requests", type=int, default=96, help="requests per arrival rate in the serving mix")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run 3 device-to-device copies of BYTES (calibrates HBM byte counters) and exit")
@@ -271,6 +273,40 @@ def main():
                       "value": cs / cdt, "unit": "likelihood evals/s", "ms_per_eval": 1e3 * cdt / cs}
         c.close()
 
+    # Ablation at the same batch and outputs: float64 factors with a full
+    # Root to Leaves, float64 with the partial one, and the headline step
+    ablation = None
+    if not a.no_ablation and prec == H.HDD_FP32_REFINE:
+        ablation = []
+        o64 = H.hdd_default_opts(w.n, H.HDD_FP64, leaf=w.leaf)
+        for name, full in (("fp64 batched, full Root to Leaves", True), ("fp64 batched, partial Root to Leaves", False)):
+            c = H.HDD(o64, B, stream=stream)
+
+            def astep():
+                c.build(kd, fd)
+                if full:
+                    c.solve_full()
+                c.loglik(w.points, yd, w.sigma_y, False, out=ll)
+                c.query_points(w.points, out=pts)
+                H._check(H._lib.hdd_query_interface(c.h, H.ctypes.c_void_p(iface.data_ptr()), None,
+                                                    H.HDD_MEM_DEVICE), "hdd_query_interface")
+                H._check(H._lib.hdd_query_mean(c.h, H._np_ptr(rect), H.ctypes.c_void_p(mean.data_ptr()),
+                                               H.HDD_MEM_DEVICE), "hdd_query_mean")
+
+            astep()
+            torch.cuda.synchronize()
+            ns = max(2, a.steps // 2)
+            a0 = time.perf_counter()
+            for _ in range(ns):
+                astep()
+            torch.cuda.synchronize()
+            adt = time.perf_counter() - a0
+            ablation.append({"name": name, "value": B * ns / adt, "unit": "likelihood evals/s",
+                             "ms_per_step": 1e3 * adt / ns})
+            c.close()
+        ablation.append({"name": "fp32 + float64 refinement batched (headline)", "value": B * a.steps / dt,
+                         "unit": "likelihood evals/s", "ms_per_step": 1e3 * dt / a.steps})
+
     serving = None if a.no_serve else serving_mix(H, a.serve_requests)
     cpu = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
 
@@ -297,6 +333,7 @@ def main():
         "accuracy": {"max_rel_err_vs_oracle": err, "refine_sweeps": sweeps,
                      "max_refine_estimate": float(np.max(est)) if len(est) else None, "status": H.strerror(code)},
         "roofline": roofline,
+        "ablation": ablation,
         "kernels_ms_per_step": {k: v["ms"] for k, v in kern.items()},
         "kernels_tflops": {k: v["tflops"] for k, v in kern.items() if v["tflops"]},
         "comparator": comparator,
