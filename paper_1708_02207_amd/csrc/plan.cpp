@@ -195,6 +195,33 @@ bool build_plan(const PlanOptions& opt, Plan& plan) {
     return false;
   }
   plan.levels.resize(raw.size());
+  // Boundary order: above the block level a son lists its boundary nodes in
+  // the order of its father's frame [gamma ; Gamma], so the father-to-son map
+  // is increasing and a lower-triangle element of the father always reads a
+  // lower-triangle element of the son along a son row (contiguous).  Blocks
+  // keep the order of the compiled block template.
+  std::vector<std::vector<std::vector<int32_t>>> bnd_of(raw.size());
+  for (size_t d = 0; d < raw.size(); ++d) {
+    bnd_of[d].resize(raw[d].size());
+    for (size_t k = 0; k < raw[d].size(); ++k)
+      for (const auto& c : raw[d][k].bnd) bnd_of[d][k].push_back(gid(c));
+  }
+  for (size_t d = 0; d + 2 < raw.size(); ++d)
+    for (size_t k = 0; k < raw[d].size(); ++k) {
+      std::unordered_map<int32_t, int> pos;
+      int q = 0;
+      for (const auto& c : raw[d][k].gam) pos[gid(c)] = q++;
+      for (const int32_t g : bnd_of[d][k]) pos[g] = q++;
+      for (int sidx = 0; sidx < 2; ++sidx) {
+        auto& sb = bnd_of[d + 1][2 * k + sidx];
+        for (const int32_t g : sb)
+          if (!pos.count(g)) {
+            plan.error = "internal: son boundary node missing from father frame";
+            return false;
+          }
+        std::stable_sort(sb.begin(), sb.end(), [&](int32_t a, int32_t b) { return pos[a] < pos[b]; });
+      }
+    }
   for (size_t d = 0; d < raw.size(); ++d) {
     PlanLevel& L = plan.levels[d];
     L.depth = int(d);
@@ -210,7 +237,7 @@ bool build_plan(const PlanOptions& opt, Plan& plan) {
       nd.block = d + 1 == raw.size();
       nd.vertical = r.vertical;
       for (const auto& c : r.gam) nd.gam.push_back(gid(c));
-      for (const auto& c : r.bnd) nd.bnd.push_back(gid(c));
+      nd.bnd = bnd_of[d][k];
       const int U = nd.U();
       if (k == 0) L.gam = int(nd.gam.size());
       if (int(nd.gam.size()) != L.gam) {
