@@ -545,7 +545,6 @@ __global__ void __launch_bounds__(NT) k_merge_small(DevLevel F, DevLevel S, int 
   constexpr int KP = GP + 1;
   constexpr int NW = NT / 64;
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ float col[64];
   __shared__ int bad_pivot;
   const int pair = blockIdx.x;
   const int node = pair / n_samples;
@@ -618,10 +617,9 @@ __global__ void __launch_bounds__(NT) k_merge_small(DevLevel F, DevLevel S, int 
         }
         d = sqrtf(d);
         a[j] = lane == j ? d : (lane > j ? a[j] / d : a[j]);
-        col[lane] = a[j];
 #pragma unroll
         for (int k = j + 1; k < GP; ++k) {
-          const float ck = col[k];
+          const float ck = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[j]), k));  // L_kj
           if (k <= lane) a[k] -= a[j] * ck;
         }
       }
