@@ -9,6 +9,8 @@
 // what the iterative refinement of the FP32 path needs.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -140,6 +142,34 @@ __device__ __forceinline__ void rows_dot(const T* F, int ld, int r0, int r1, int
       const int r = rb + q * step + sub;
       if (c == 0 && r < r1) fn(r, v);
     }
+  }
+}
+
+// Same product with one thread per row: the row's nc values are read as
+// 16-byte vectors where the row is aligned (scalar tail), x from LDS, no
+// cross-lane reduction.  For workgroups of 256 or more threads, where the
+// shuffle reductions of rows_dot saturate the cross-lane network.
+template <typename T, int BS, typename Fn>
+__device__ __forceinline__ void rows_dot_thread(const T* F, int ld, int r0, int r1, int c0, int nc, const double* x,
+                                                Fn&& fn) {
+  constexpr int V = 16 / sizeof(T);  // elements per 16-byte vector
+  using Vec = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+  for (int r = r0 + int(threadIdx.x); r < r1; r += BS) {
+    const T* row = F + (long long)r * ld + c0;
+    double acc = 0.0;
+    int k = 0;
+    if ((reinterpret_cast<uintptr_t>(row) & 15) == 0) {
+      const Vec* rv = reinterpret_cast<const Vec*>(row);
+#pragma unroll 4
+      for (; k + V <= nc; k += V) {
+        const Vec v = rv[k / V];
+        const T* ve = reinterpret_cast<const T*>(&v);
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc += double(ve[e]) * x[k + e];
+      }
+    }
+    for (; k < nc; ++k) acc += double(row[k]) * x[k];
+    fn(r, acc);
   }
 }
 
@@ -367,7 +397,10 @@ __global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int n_sa
     }
     __syncthreads();
     if (b1 < g) {  // rows below the block: gt[i] -= L[i][b0:b1] z[b0:b1]
-      rows_dot<T, BS>(F, ld, b1, g, b0, nb, gt + b0, [&](int i, double y) { gt[i] -= y; });
+      if constexpr (BS >= 256)
+        rows_dot_thread<T, BS>(F, ld, b1, g, b0, nb, gt + b0, [&](int i, double y) { gt[i] -= y; });
+      else
+        rows_dot<T, BS>(F, ld, b1, g, b0, nb, gt + b0, [&](int i, double y) { gt[i] -= y; });
       __syncthreads();
     }
   }
@@ -380,7 +413,7 @@ __global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int n_sa
     T* tile = reinterpret_cast<T*>(dyn + (L.max_U + 1));  // 64 x 65
     if (G > 0) rows_dot_wave64<T>(F, ld, g, g + G, 0, g, gt, tile, [&](int r, double y) { out[r] = gt[r] - y; });
   } else {
-    rows_dot<T, BS>(F, ld, g, g + G, 0, g, gt, [&](int r, double y) { out[r] = gt[r] - y; });
+    rows_dot_thread<T, BS>(F, ld, g, g + G, 0, g, gt, [&](int r, double y) { out[r] = gt[r] - y; });
   }
   for (int i = tid; i < g; i += BS) out[i] = gt[i];
 }
