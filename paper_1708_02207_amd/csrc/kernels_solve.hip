@@ -56,17 +56,22 @@ __device__ __forceinline__ double bcast(double v, int l) {
 // the only serial dependency is the broadcast of each solved entry.
 //   back:    L^T x = v  (lane i holds column i: c[q] = L[j0 + q][i], j >= i)
 //   forward: L z = v    (lane i holds row i:    c[q] = L[i][j0 + q], j <= i)
+// The next chunk's 16 values are loaded while the current chunk is solved
+// (addresses clamped into the block, unused values masked at use).
 template <typename T>
 __device__ __forceinline__ double diag_back(const T* D, int ld, int nb, double v) {
   const int lane = threadIdx.x & 63;
-  const double rinv = 1.0 / double(D[(long long)min(lane, nb - 1) * (ld + 1)]);  // lane j: 1 / L_jj
-  for (int j0 = ((nb - 1) >> 4) << 4; j0 >= 0; j0 -= 16) {
-    T c[16];
+  const int lc = min(lane, nb - 1);
+  const double rinv = 1.0 / double(D[(long long)lc * (ld + 1)]);  // lane j: 1 / L_jj
+  auto load = [&](int j0, T (&c)[16]) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int j = j0 + q;
-      c[q] = (j < nb && lane <= j) ? D[(long long)j * ld + lane] : T(0);
-    }
+    for (int q = 0; q < 16; ++q) c[q] = D[(long long)min(j0 + q, nb - 1) * ld + lc];
+  };
+  int j0 = ((nb - 1) >> 4) << 4;
+  T c[16], cn[16];
+  load(j0, c);
+  for (; j0 >= 0; j0 -= 16) {
+    if (j0 >= 16) load(j0 - 16, cn);
 #pragma unroll
     for (int q = 15; q >= 0; --q) {
       const int j = j0 + q;
@@ -76,6 +81,8 @@ __device__ __forceinline__ double diag_back(const T* D, int ld, int nb, double v
         else if (lane < j) v -= double(c[q]) * xj;
       }
     }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) c[q] = cn[q];
   }
   return v;
 }
@@ -83,14 +90,16 @@ __device__ __forceinline__ double diag_back(const T* D, int ld, int nb, double v
 template <typename T>
 __device__ __forceinline__ double diag_forward(const T* D, int ld, int nb, double v) {
   const int lane = threadIdx.x & 63;
-  const double rinv = 1.0 / double(D[(long long)min(lane, nb - 1) * (ld + 1)]);  // lane j: 1 / L_jj
-  for (int j0 = 0; j0 < nb; j0 += 16) {
-    T c[16];
+  const int lc = min(lane, nb - 1);
+  const double rinv = 1.0 / double(D[(long long)lc * (ld + 1)]);  // lane j: 1 / L_jj
+  auto load = [&](int j0, T (&c)[16]) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int j = j0 + q;
-      c[q] = (lane < nb && j <= lane) ? D[(long long)lane * ld + j] : T(0);
-    }
+    for (int q = 0; q < 16; ++q) c[q] = D[(long long)lc * ld + min(j0 + q, nb - 1)];
+  };
+  T c[16], cn[16];
+  load(0, c);
+  for (int j0 = 0; j0 < nb; j0 += 16) {
+    if (j0 + 16 < nb) load(j0 + 16, cn);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int j = j0 + q;
@@ -100,6 +109,8 @@ __device__ __forceinline__ double diag_forward(const T* D, int ld, int nb, doubl
         else if (lane > j) v -= double(c[q]) * zj;
       }
     }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) c[q] = cn[q];
   }
   return v;
 }
