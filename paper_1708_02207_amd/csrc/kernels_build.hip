@@ -109,7 +109,6 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 
 template <typename T, int NB>
 __global__ void __launch_bounds__(64) k_panel_diag(DevLevel L, int k0, int kb, int n_samples, int* info) {
-  __shared__ T col[64];
   const int pair = blockIdx.x;
   const int node = pair / n_samples;
   const int s = pair % n_samples;
@@ -135,10 +134,9 @@ __global__ void __launch_bounds__(64) k_panel_diag(DevLevel L, int k0, int kb, i
       }
       d = sqrt(d);
       a[j] = lane == j ? d : (lane > j ? a[j] / d : a[j]);
-      col[lane] = a[j];  // zero on lanes >= kb, so columns past kb stay zero
 #pragma unroll
       for (int k = j + 1; k < NB; ++k) {
-        const T ck = col[k];
+        const T ck = lane_value(a[j], k);  // L_kj (zero on lanes >= kb)
         if (k <= lane) a[k] -= a[j] * ck;
       }
     }
@@ -163,25 +161,35 @@ __global__ void __launch_bounds__(PanelCfg<T>::RW) k_panel_rows(DevLevel L, int 
   if (r0 > U) return;  // uniform
   T* F = frame_ptr<T>(L, node, s);
   const int tid = threadIdx.x;
-  for (int e = tid; e < kb * kb; e += RW) {
-    const int i = e / kb, j = e % kb;
-    if (j <= i) D[i][j] = F[(long long)(k0 + i) * ld + k0 + j];
-  }
   const int nrows = min(RW, U + 1 - r0);
   const int total = nrows * kb;
-  constexpr int UNR = 8;
-  for (int base = 0; base < total; base += RW * UNR) {  // consecutive threads read consecutive columns
-    T v[UNR];
+  // every staging load of the thread is issued before any LDS store (one
+  // memory latency): the diagonal block (NB x NB, valid below and on the
+  // diagonal within kb) and the panel rows (nrows x kb), consecutive
+  // threads on consecutive columns; addresses are clamped into the panel
+  constexpr int DPT = (NB * NB + RW - 1) / RW;
+  T dv[DPT], xv[NB];
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const int e = min(base + u * RW + tid, total - 1);
-      v[u] = F[(long long)(r0 + e / kb) * ld + k0 + e % kb];
-    }
+  for (int u = 0; u < DPT; ++u) {
+    const int e = tid + u * RW;
+    const int i = min(e / NB, kb - 1), j = min(e % NB, i);
+    dv[u] = F[(long long)(k0 + i) * ld + k0 + j];
+  }
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) {
-      const int e = base + u * RW + tid;
-      if (e < total) X[e / kb][e % kb] = v[u];
-    }
+  for (int u = 0; u < NB; ++u) {
+    const int e = min(tid + u * RW, total - 1);
+    xv[u] = F[(long long)(r0 + e / kb) * ld + k0 + e % kb];
+  }
+#pragma unroll
+  for (int u = 0; u < DPT; ++u) {
+    const int e = tid + u * RW;
+    const int i = e / NB, j = e % NB;
+    if (i < kb && j <= i) D[i][j] = dv[u];
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const int e = tid + u * RW;
+    if (e < total) X[e / kb][e % kb] = xv[u];
   }
   __syncthreads();
   if (tid < nrows) {
