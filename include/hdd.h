@@ -63,7 +63,8 @@ extern "C" {
 #define HDD_MEM_DEVICE 1
 
 /* option flags */
-#define HDD_FLAG_NO_MFMA 1        /* use the plain FMA Schur update (cross-check) */
+#define HDD_FLAG_NO_MFMA 1        /* Schur updates and fused merges without matrix cores (plain FMA), in
+                                     the blocks too: a cross-check of the matrix-core lane layouts */
 #define HDD_FLAG_KEEP_DIRICHLET 2 /* plan only: keep outer-boundary nodes in every Gamma */
 #define HDD_FLAG_BLOCK8 4         /* eliminate leaf interiors in 8 x 8-cell blocks (default 16 x 16) */
 

@@ -533,6 +533,7 @@ int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* works
     B.max_buf = T.max_buf;
     B.max_gam_nodes = T.max_gam_nodes;
     B.max_bnd_nodes = T.max_bnd_nodes;
+    B.no_mfma = (o->flags & HDD_FLAG_NO_MFMA) ? 1 : 0;
     B.maps = reinterpret_cast<const int*>(h->ws + L.tmaps);
     B.lids = reinterpret_cast<const int*>(h->ws + L.tlids);
     B.micro_xy = reinterpret_cast<const int*>(h->ws + L.tmicro);

@@ -69,6 +69,7 @@ struct DevBlocks {
   int max_buf;        // LDS frame elements per buffer
   int max_gam_nodes;  // max n * gam over levels
   int max_bnd_nodes;  // max n * U over levels
+  int no_mfma;        // in-block Schur updates without matrix cores (cross-check)
   const int* maps;
   const int* lids;
   const int* micro_xy;

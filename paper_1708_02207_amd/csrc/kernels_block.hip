@@ -395,48 +395,10 @@ __device__ __forceinline__ void build_level(T* base, T* cur, T* cst, const DevBl
   chol_tail<T, L>(cur, xs);
   // Schur update of the boundary block and the load row (rank-g, eq.
   // SchurC1): S[i][l] -= sum_k P[i][k] P[l][k], g <= l <= i <= U.
-  if constexpr (std::is_same<T, float>::value && g >= 7) {
-    // matrix cores: 32 x 32 tiles of the lower triangle, one wave per tile,
-    // K = g padded to even with zeros; P read from the frame in LDS
-    constexpr int nr = L::U + 1 - g;
-    constexpr int nt = (nr + 31) / 32;
-    constexpr int tiles = L::n * nt * (nt + 1) / 2;
-    const int lane = tid & 63, wv = tid >> 6;
-    for (int q = wv; q < tiles; q += NB / 64) {
-      const int t = q / (nt * (nt + 1) / 2), tq = q % (nt * (nt + 1) / 2);
-      const int ti = tri_row(tq), tj = tq - ti * (ti + 1) / 2;
-      T* F = cur + t * L::fsz;
-      // rows beyond U are clamped: they only feed accumulator rows and
-      // columns that are not written back
-      const int ra = g + ti * 32 + (lane & 31), rb = g + tj * 32 + (lane & 31);
-      const T* pa = F + L::row(min(ra, L::U)) + (lane >> 5);
-      const T* pb = F + L::row(min(rb, L::U)) + (lane >> 5);
-      floatx16 acc;
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-#pragma unroll
-      for (int kk = 0; kk < g; kk += 2) {
-        float av = pa[kk], bv = pb[kk];
-        if (kk + 1 == g) av = (lane >> 5) ? 0.f : av;  // odd g: column g is not in P
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
-      }
-      // accumulator v of this lane: row i0 + d(v), column l
-      const int l = g + tj * 32 + (lane & 31);
-      const int i0 = g + ti * 32 + (lane >> 5) * 4;
-      T* Fl = F + L::row(i0) + l;
-      const bool edge = ti == tj || g + ti * 32 + 31 > L::U;  // wave-uniform
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int d = (v >> 2) * 8 + (v & 3);
-        // row(i0 + d) = row(i0) + d * i0 + d (d + 1) / 2
-        T* p = Fl + d * i0 + d * (d + 1) / 2;
-        if (!edge || (i0 + d <= L::U && l <= i0 + d)) *p -= acc[v];
-      }
-    }
-  } else {
-    // one thread per row i >= g: its P entries in registers, the columns
-    // l = g .. i unrolled (compile-time offsets; P rows l read by every
-    // thread of the node at once)
+  // One thread per row i >= g: its P entries in registers, the columns
+  // l = g .. i unrolled (compile-time offsets; P rows l read by every thread
+  // of the node at once).
+  auto schur_rows = [&]() {
     constexpr int nr = L::U + 1 - g;
     for (int e = tid; e < L::n * nr; e += NB) {
       const int t = e / nr, i = g + e % nr;
@@ -455,6 +417,51 @@ __device__ __forceinline__ void build_level(T* base, T* cur, T* cst, const DevBl
         }
       }
     }
+  };
+  if constexpr (std::is_same<T, float>::value && g >= 7) {
+    if (!B.no_mfma) {  // uniform
+      // matrix cores: 32 x 32 tiles of the lower triangle, one wave per tile,
+      // K = g padded to even with zeros; P read from the frame in LDS
+      constexpr int nr = L::U + 1 - g;
+      constexpr int nt = (nr + 31) / 32;
+      constexpr int tiles = L::n * nt * (nt + 1) / 2;
+      const int lane = tid & 63, wv = tid >> 6;
+      for (int q = wv; q < tiles; q += NB / 64) {
+        const int t = q / (nt * (nt + 1) / 2), tq = q % (nt * (nt + 1) / 2);
+        const int ti = tri_row(tq), tj = tq - ti * (ti + 1) / 2;
+        T* F = cur + t * L::fsz;
+        // rows beyond U are clamped: they only feed accumulator rows and
+        // columns that are not written back
+        const int ra = g + ti * 32 + (lane & 31), rb = g + tj * 32 + (lane & 31);
+        const T* pa = F + L::row(min(ra, L::U)) + (lane >> 5);
+        const T* pb = F + L::row(min(rb, L::U)) + (lane >> 5);
+        floatx16 acc;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+#pragma unroll
+        for (int kk = 0; kk < g; kk += 2) {
+          float av = pa[kk], bv = pb[kk];
+          if (kk + 1 == g) av = (lane >> 5) ? 0.f : av;  // odd g: column g is not in P
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+        }
+        // accumulator v of this lane: row i0 + d(v), column l
+        const int l = g + tj * 32 + (lane & 31);
+        const int i0 = g + ti * 32 + (lane >> 5) * 4;
+        T* Fl = F + L::row(i0) + l;
+        const bool edge = ti == tj || g + ti * 32 + 31 > L::U;  // wave-uniform
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int d = (v >> 2) * 8 + (v & 3);
+          // row(i0 + d) = row(i0) + d * i0 + d (d + 1) / 2
+          T* p = Fl + d * i0 + d * (d + 1) / 2;
+          if (!edge || (i0 + d <= L::U && l <= i0 + d)) *p -= acc[v];
+        }
+      }
+    } else {
+      schur_rows();
+    }
+  } else {
+    schur_rows();
   }
   __syncthreads();
   // Local operators of every node -> compact store, g values per row

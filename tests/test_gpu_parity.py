@@ -163,10 +163,14 @@ def test_node_schur_fp32(H, oracle_mod, n, leaf):
     t.close()
 
 
-def test_c0_fp32_refine(H, oracle_mod):
+@pytest.mark.parametrize("flags", [0, 1])
+def test_c0_fp32_refine(H, oracle_mod, flags):
+    """float32 frames + float64 refinement against the oracle, with matrix
+    cores and (flags=1) with the plain FMA updates everywhere, blocks
+    included."""
     w = make_workload("c0_63")
-    say("c0_63 fp32+refine")
-    o = H.hdd_default_opts(w.n, H.HDD_FP32_REFINE, leaf=w.leaf)
+    say("c0_63 fp32+refine flags", flags)
+    o = H.hdd_default_opts(w.n, H.HDD_FP32_REFINE, leaf=w.leaf, flags=flags)
     t = H.HDD(o, 1)
     t.build(w.kappa, w.f)
     ref = oracle_values(oracle_mod, w.n, w.kappa[0], w.f, w.points)
