@@ -9,6 +9,7 @@ Contents
                                  precision refinement (oracle.c)
   residual(n, kappa, f, u)       b - A u in extended precision (oracle.c)
   point_values / interface / mean / loglik    the measurement operators
+  tree_rects / node_means        subdomains of the tree and their means
   element_matrix_dense(...)      independent element-loop assembly (dense)
   subdomain_schur(...)           brute-force dense Schur complement of one
                                  subdomain's own matrix (Section 2.4)
@@ -167,6 +168,42 @@ def mean_value(n: int, u_full: np.ndarray, rect: Sequence[float]) -> float:
             total += area_t / 3.0 * (a + b + c)  # T-
             total += area_t / 3.0 * (a + c + d)  # T+
     return total / ((i1 - i0) * (j1 - j0) * h * h)
+
+
+def tree_rects(n: int, block: int) -> list:
+    """Cell rectangles (i0, i1, j0, j1) of every node of the HDD tree (Section
+    2.1) down to block x block cells, root first, then depth by depth, each
+    father's two sons next to each other (left before right for a vertical
+    cut, bottom before top for a horizontal one).  The paper only asks for
+    halves with a small shared interface; the split taken here cuts the longer
+    side at its midpoint and cuts squares vertically, so the root interface is
+    the midline x = 1/2."""
+    nc = n + 1
+    level = [(0, nc, 0, nc)]
+    out = list(level)
+    while level[0][1] - level[0][0] > block or level[0][3] - level[0][2] > block:
+        nxt = []
+        for i0, i1, j0, j1 in level:
+            if i1 - i0 >= j1 - j0:
+                m = (i0 + i1) // 2
+                nxt += [(i0, m, j0, j1), (m, i1, j0, j1)]
+            else:
+                m = (j0 + j1) // 2
+                nxt += [(i0, i1, j0, m), (i0, i1, m, j1)]
+        level = nxt
+        out += level
+    return out
+
+
+def node_means(n: int, u_full: np.ndarray, block: int, nodes=None) -> np.ndarray:
+    """Mean of u_h over every subdomain of the tree (the example after Lemma
+    Func1 in Section 5.1: mean values in all subdomains), each by eq. mean
+    over the node's own triangles, in the order of tree_rects.  nodes: indices
+    into that order to evaluate (default all)."""
+    nc = n + 1
+    rects = tree_rects(n, block)
+    pick = range(len(rects)) if nodes is None else nodes
+    return np.array([mean_value(n, u_full, tuple(c / nc for c in rects[k])) for k in pick])
 
 
 def loglik(y: np.ndarray, hu: np.ndarray, sigma: float, normalized: bool = False) -> float:

@@ -276,3 +276,130 @@ def test_subdomain_schur_quotient(oracle_mod):
     assert ev[0] > -1e-12 * ev[-1] and ev[1] > 1e-6 * ev[-1]
     St, _, _ = O.subdomain_schur(n, k, f, (0, 8, 0, 8))
     assert np.linalg.eigvalsh(St)[0] > 0
+
+
+# Subdomains of the tree and their means (Section 5.1) ----------------------------------
+@pytest.mark.parametrize("n,block,count", [(63, 8, 127), (255, 16, 511), (1023, 16, 8191)])
+def test_tree_rects_tile(oracle_mod, n, block, count):
+    """Every depth tiles the square with 2^d equal halves of the depth above;
+    the root is cut vertically at x = 1/2; the last depth is block x block."""
+    O = oracle_mod
+    nc = n + 1
+    rects = O.tree_rects(n, block)
+    assert len(rects) == count
+    assert rects[0] == (0, nc, 0, nc) and rects[1] == (0, nc // 2, 0, nc) and rects[2] == (nc // 2, nc, 0, nc)
+    start, d = 0, 0
+    while start < len(rects):
+        lev = rects[start:start + 2 ** d]
+        cover = np.zeros((nc, nc), dtype=int)
+        for i0, i1, j0, j1 in lev:
+            cover[j0:j1, i0:i1] += 1
+        assert (cover == 1).all()
+        if d > 0:
+            for k, (i0, i1, j0, j1) in enumerate(lev):
+                fi0, fi1, fj0, fj1 = rects[start - 2 ** (d - 1) + k // 2]
+                assert 2 * (i1 - i0) * (j1 - j0) == (fi1 - fi0) * (fj1 - fj0)
+                assert fi0 <= i0 and i1 <= fi1 and fj0 <= j0 and j1 <= fj1
+        start += 2 ** d
+        d += 1
+    assert all(r[1] - r[0] == block and r[3] - r[2] == block for r in rects[-(nc // block) ** 2:])
+
+
+def test_node_means_root_closed_form(oracle_mod):
+    """kappa = 1, f = 2 pi^2 sin sin: the P1 interpolant of the exact discrete
+    solution U = C sin(pi x) sin(pi y) integrates to h^2 sum_p U_p (every
+    interior node carries 6 triangles of area h^2/2, a third each), and
+    sum_{i=1..N} sin(i pi h) = cot(pi h / 2), so the mean over the square is
+    C h^2 cot^2(pi h / 2)."""
+    O = oracle_mod
+    for n in (15, 63):
+        h = 1.0 / (n + 1)
+        C = math.pi ** 2 * h * h / (4.0 * math.sin(math.pi * h / 2) ** 2)
+        ref = C * h * h / math.tan(math.pi * h / 2) ** 2
+        m = O.node_means(n, O.exact_discrete_sinsin(n), 8, nodes=[0])[0]
+        assert abs(m - ref) < 1e-14 * abs(ref)
+
+
+def test_node_means_sons_average(oracle_mod):
+    """Means of the sons average to the father's mean with weights
+    |omega_i| / |omega| (the constants c_1, c_2 of the example after Lemma
+    Func1), at every node."""
+    O = oracle_mod
+    n = 63
+    k = _rand_tri_kappa(n, 5)
+    u, _ = O.solve(n, k, rhs_nodal(n, "bump"))
+    rects = O.tree_rects(n, 8)
+    m = O.node_means(n, u, 8)
+    area = np.array([(r[1] - r[0]) * (r[3] - r[2]) for r in rects], dtype=float)
+    for p in range((len(rects) - 1) // 2):
+        a, b = 2 * p + 1, 2 * p + 2
+        assert abs(m[p] - (area[a] * m[a] + area[b] * m[b]) / area[p]) < 1e-13 * np.abs(m).max()
+
+
+@pytest.mark.parametrize("father", [(4, 12, 2, 10), (0, 16, 0, 16), (8, 16, 0, 8)])
+def test_functional_lemma_dense(oracle_mod, father):
+    """Lemma Func1 for the integral over a subdomain, brute force on dense
+    matrices.  For a node with interior I and boundary Gamma, the integral of
+    u_h is (l^f, f) + (l^g, u_Gamma) with l^g = w_Gamma - A_GI A_II^-1 w_I and
+    (l^f, f) = w_I . A_II^-1 b_I, where w are the node's own quadrature weights
+    (|t|/3 per triangle vertex, i.e. its load for f = 1).  The lemma builds
+    both from the sons: with the son-union frame [gamma ; Gamma], the sum of
+    the sons' Schur complements S~, loads g~ and functionals l~,
+        l^g = l~_Gamma - S~_Gamma,gamma S~_gamma,gamma^-1 l~_gamma
+        (l^f, f) = (l^f_1, f_1) + (l^f_2, f_2) + l~_gamma . S~_gamma,gamma^-1 g~_gamma
+    (its last term uses l^g on gamma, as the lemma does).  Both must agree,
+    and with u from the oracle give eq. mean times |omega|."""
+    O = oracle_mod
+    n = 15
+    nc = n + 1
+    h = 1.0 / nc
+    k = _rand_tri_kappa(n, 77)
+    f = rhs_nodal(n, "bump")
+    ones = np.ones((n + 2, n + 2))
+    u, _ = O.solve(n, k, f)
+    i0, i1, j0, j1 = father
+    if i1 - i0 >= j1 - j0:
+        m = (i0 + i1) // 2
+        sons = [(i0, m, j0, j1), (m, i1, j0, j1)]
+    else:
+        m = (j0 + j1) // 2
+        sons = [(i0, i1, j0, m), (i0, i1, m, j1)]
+
+    def direct(rect):
+        S, g, bn = O.subdomain_schur(n, k, f, rect)
+        _, lg, _ = O.subdomain_schur(n, k, ones, rect)
+        A, b, nodes = O.assemble_dense(n, k, f, rect)
+        _, w, _ = O.assemble_dense(n, k, ones, rect)
+        a0, a1, b0, b1 = rect
+        inner = [t for t, (i, j) in enumerate(nodes) if a0 < i < a1 and b0 < j < b1]
+        mu = w[inner] @ np.linalg.solve(A[np.ix_(inner, inner)], b[inner]) if inner else 0.0
+        return S, g, lg, mu, bn
+
+    S_f, _, lg_f, mu_f, bn_f = direct(father)
+    frame = {}
+    parts = [direct(r) for r in sons]
+    for _, _, _, _, bn in parts:
+        for nd in bn:
+            frame.setdefault(nd, len(frame))
+    Uf = len(frame)
+    St, gt, lt = np.zeros((Uf, Uf)), np.zeros(Uf), np.zeros(Uf)
+    for S, g, lg, _, bn in parts:
+        ix = [frame[nd] for nd in bn]
+        St[np.ix_(ix, ix)] += S
+        gt[ix] += g
+        lt[ix] += lg
+    G = [frame[nd] for nd in bn_f]
+    gam = [t for nd, t in frame.items() if nd not in set(bn_f)]
+    assert len(gam) > 0
+    Sgg = St[np.ix_(gam, gam)]
+    lam = lt[G] - St[np.ix_(G, gam)] @ np.linalg.solve(Sgg, lt[gam])
+    mu = parts[0][3] + parts[1][3] + lt[gam] @ np.linalg.solve(Sgg, gt[gam])
+    assert len(lam) == len(lg_f)
+    if len(lg_f):
+        assert np.abs(lam - lg_f).max() < 1e-12 * np.abs(lg_f).max()
+    assert abs(mu - mu_f) < 1e-12 * abs(mu_f)
+    ub = np.array([u[j, i] for i, j in bn_f]) if bn_f else np.zeros(0)
+    integral = mu + lam @ ub
+    area = (i1 - i0) * (j1 - j0) * h * h
+    ref = O.mean_value(n, u, (i0 / nc, i1 / nc, j0 / nc, j1 / nc)) * area
+    assert abs(integral - ref) < 1e-12 * abs(ref)
