@@ -142,6 +142,26 @@ int hdd_query_interface(hdd_handle h, double* u_out, int32_t* len, int32_t mem);
 int hdd_query_mean(hdd_handle h, const double rect[4], double* out, int32_t mem);
 
 /*
+ * Mean of u over every subdomain of the tree down to the blocks (the example
+ * after Lemma Func1, Section 5.1: mean values in all subdomains):
+ *   out (mem) float64 [n_samples][n_nodes], n_nodes = hdd_plan_summary()
+ *   out[1]; node order root first, then depth by depth, node k of a depth as
+ *   in hdd_plan_node(depth, k) (the sons of node k are 2k and 2k+1 of the
+ *   next depth).
+ * Without the full field (HDD_FP64 with max_refine = 0, before
+ * hdd_solve_full) the means come from functional propagation (Lemma Func1;
+ * the algorithms of Section 5.2 in factored form): a bottom-up pass builds
+ * every node's functional l^g on its boundary and the scalar (l^f, f) from
+ * the retained factors, Root to Leaves solves the interfaces above the
+ * blocks only, and each mean is (l^f, f) + (l^g, u_Gamma) divided by |omega|;
+ * no block interior is solved.  With the full field (always in
+ * HDD_FP32_REFINE mode, whose refinement needs it) the means are summed from
+ * the field (eq. mean per block, sons into fathers).  Overwrites the
+ * forward-pass vectors of the handle.  Errors: HDD_ESTATE before a build.
+ */
+int hdd_query_node_means(hdd_handle h, double* out, int32_t mem);
+
+/*
  * Log-likelihood of observations y at sites xy for every built sample:
  *   out[s] = -sum_i (y_i - u_s(x_i))^2 / (2 sigma^2)
  *            [- n_y log(sigma sqrt(2 pi)) if normalized]
@@ -232,7 +252,8 @@ int hdd_debug_frame(hdd_handle h, int32_t sample, int32_t depth, int32_t index, 
  * leaf interior), 4 top-down, 5 forward pass, 6 residual, 7 Schur update on
  * float64 levels, 8 the 128 x 128-tile float32 Schur update kernel (launches
  * of kind 8 are not counted in kind 0), 9 fused merge of narrow float32
- * levels (extend-add, factorization and Schur update in one launch).
+ * levels (extend-add, factorization and Schur update in one launch),
+ * 10 the functional and readout kernels of hdd_query_node_means.
  * hdd_timing_enable(h, mask): bit k enables kind k (0 disables and clears).
  * hdd_timing_get: total milliseconds, number of launches and summed
  * algorithmic flops of the timed launches (Schur update: 2 K per lower-

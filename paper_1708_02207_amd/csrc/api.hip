@@ -19,10 +19,10 @@ using hdd::Plan;
 
 namespace {
 
-constexpr int kKinds = 10;
+constexpr int kKinds = 11;
 enum Kind {
   K_SYRK = 0, K_FACTOR = 1, K_EXTEND = 2, K_ASSEMBLE = 3, K_TOPDOWN = 4, K_FORWARD = 5, K_RESIDUAL = 6, K_SYRK64 = 7,
-  K_SYRK128 = 8, K_MERGE = 9
+  K_SYRK128 = 8, K_MERGE = 9, K_FUNCTIONAL = 10
 };
 
 int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
@@ -78,6 +78,7 @@ struct Layout {
   std::vector<int64_t> frames, nodes, maps, ids, vec, panel;
   int64_t kappa, f, u, d, r, info, bad, maxbits, qout, qxy, qy, qsmp, qoff, qsig, lists, iota;
   int64_t cst, bvec, tmaps, tlids, tmicro, origin, text;
+  int64_t wts, mu, nmean;  // node means: weight vector, subtree functionals, output staging
   int64_t max_q;
   int64_t total;
 };
@@ -101,7 +102,8 @@ Layout make_layout(const Plan& p, const hdd_opts& o, int ms) {
     L.nodes[d] = take(int64_t(lv.nodes.size()) * int64_t(sizeof(DevNode)));
     L.maps[d] = take(int64_t(lv.maps.size()) * 4);
     L.ids[d] = take(int64_t(lv.ids.size()) * 4);
-    L.vec[d] = refine ? take(int64_t(lv.ids.size()) * 8 * ms) : -1;
+    // forward-pass vectors: refinement, and the functional propagation of the node means
+    L.vec[d] = take(int64_t(lv.ids.size()) * 8 * ms);
     L.panel[d] = merge_level(p, o, d) ? take(panel_elems(p, d) * 4 * ms) : -1;
     total_nodes += int64_t(lv.nodes.size());
     max_nodes = std::max<int64_t>(max_nodes, int64_t(lv.nodes.size()));
@@ -129,7 +131,10 @@ Layout make_layout(const Plan& p, const hdd_opts& o, int ms) {
   const int64_t nb = int64_t(p.levels.back().nodes.size());
   const int64_t besz = level_double(o, int(p.levels.size()) - 1) ? 8 : 4;
   L.cst = take(int64_t(ms) * nb * T.cst_size * besz);
-  L.bvec = refine ? take(int64_t(ms) * nb * T.vec_size * 8) : -1;
+  L.bvec = take(int64_t(ms) * nb * T.vec_size * 8);
+  L.wts = take(nn * 8);
+  L.mu = take(int64_t(ms) * total_nodes * 8);
+  L.nmean = take(int64_t(ms) * total_nodes * 8);
   L.tmaps = take(int64_t(T.maps.size()) * 4);
   L.tlids = take(int64_t(T.lids.size()) * 4);
   L.tmicro = take(int64_t(T.micro_xy.size()) * 4);
@@ -161,6 +166,9 @@ struct hdd_tree {
   double *qout = nullptr, *qxy = nullptr, *qy = nullptr, *qsig = nullptr;
   int *qsmp = nullptr, *qoff = nullptr;
   int *lists = nullptr, *iota = nullptr;
+  double *wts = nullptr, *mu = nullptr, *nmean = nullptr;
+  long long total_nodes = 0;
+  bool wts_ready = false;
   int* pinned_lists = nullptr;
   hipEvent_t lists_done = nullptr;
   bool built = false, full = false;
@@ -490,6 +498,8 @@ int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* works
       dn[k].ids_off = int(p.ids_off);
       dn[k].x0 = p.x0;
       dn[k].y0 = p.y0;
+      dn[k].cw = p.w;
+      dn[k].ch = p.h;
     }
     DevLevel& lv = h->lev[d];
     lv.frames = h->ws + L.frames[d];
@@ -584,6 +594,11 @@ int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* works
   h->qsig = reinterpret_cast<double*>(h->ws + L.qsig);
   h->lists = reinterpret_cast<int*>(h->ws + L.lists);
   h->iota = reinterpret_cast<int*>(h->ws + L.iota);
+  h->wts = reinterpret_cast<double*>(h->ws + L.wts);
+  h->mu = reinterpret_cast<double*>(h->ws + L.mu);
+  h->nmean = reinterpret_cast<double*>(h->ws + L.nmean);
+  h->total_nodes = 0;
+  for (auto& lv : h->lev) h->total_nodes += lv.n_nodes;
   if (hipHostMalloc(&h->pinned_lists, sizeof(int) * size_t(std::max<int64_t>(list_off, 1))) != hipSuccess) {
     h->pinned_lists = nullptr;
     return fail(HDD_ENOMEM);
@@ -797,6 +812,64 @@ int hdd_query_mean(hdd_handle h, const double rect[4], double* out, int32_t mem)
   HIP_TRY(hdd::launch_mean(nc, h->n_samples, b[0], b[1], b[2], b[3], h->u, dst, h->st));
   if (mem == HDD_MEM_DEVICE) return HDD_OK;
   return copy_out(h, out, h->qout, size_t(h->n_samples), HDD_MEM_HOST);
+}
+
+int hdd_query_node_means(hdd_handle h, double* out, int32_t mem) {
+  if (!h || !out || (mem != HDD_MEM_HOST && mem != HDD_MEM_DEVICE)) return HDD_EINVAL;
+  if (!h->built) return HDD_ESTATE;
+  if (!h->full && h->opt.max_refine > 0) HDD_TRY(ensure_full(h));
+  const int ns = h->n_samples, nc = h->plan.nc;
+  const int D = int(h->lev.size()) - 1;
+  const long long tn = h->total_nodes;
+  double* dst = mem == HDD_MEM_DEVICE ? out : h->nmean;
+  if (h->full) {
+    // the field is known: eq. mean per block, then every father sums its sons
+    h->cur_level = D;
+    HDD_TRY(timed(h, K_FUNCTIONAL, 0.0, [&] {
+      return hdd::launch_block_integral(h->lev[D], ns, nc, h->u, h->nn, h->mu, tn, dst, tn, h->st);
+    }));
+    for (int d = D - 1; d >= 0; --d) {
+      h->cur_level = d;
+      HDD_TRY(timed(h, K_FUNCTIONAL, 0.0, [&] {
+        return hdd::launch_level_sum(h->lev[d], h->lev[d + 1], ns, nc, h->mu, tn, dst, tn, h->st);
+      }));
+    }
+  } else {
+    // Lemma Func1 bottom-up: the functional of every node from the nodal
+    // weight vector h^2 (shared by all samples), then mu of every subtree
+    if (!h->wts_ready) {
+      const double hc = 1.0 / nc;
+      HIP_TRY(hdd::launch_fill(h->wts, h->nn, hc * hc, h->st));
+      h->wts_ready = true;
+    }
+    h->cur_level = D;
+    HDD_TRY(timed(h, K_FORWARD, 0.0, [&] { return hdd::launch_block_forward(h->blk, ns, nc, h->wts, 0, h->st); }));
+    for (int d = D - 1; d >= 0; --d) {
+      h->cur_level = d;
+      HDD_TRY(timed(h, K_FORWARD, 0.0, [&] { return hdd::launch_forward(h->lev[d], h->lev[d + 1], ns, h->st); }));
+    }
+    h->cur_level = D;
+    HDD_TRY(timed(h, K_FUNCTIONAL, 0.0, [&] { return hdd::launch_block_mu(h->blk, ns, h->mu, tn, h->st); }));
+    for (int d = D - 1; d >= 0; --d) {
+      h->cur_level = d;
+      HDD_TRY(timed(h, K_FUNCTIONAL, 0.0, [&] {
+        return hdd::launch_level_mu(h->lev[d], h->lev[d + 1], ns, h->mu, tn, h->st);
+      }));
+    }
+    // Root to Leaves on the interfaces above the blocks only: every node's
+    // boundary is then known, and no block interior is solved
+    auto need = empty_need(h);
+    for (int d = 0; d < D; ++d) std::fill(need[d].begin(), need[d].end(), 1);
+    HDD_TRY(partial_topdown(h, need));
+    for (int d = 0; d <= D; ++d) {
+      h->cur_level = d;
+      HDD_TRY(timed(h, K_FUNCTIONAL, 0.0, [&] {
+        return hdd::launch_node_means(h->lev[d], ns, nc, h->u, h->nn, h->mu, tn, dst, tn, h->st);
+      }));
+    }
+  }
+  if (mem == HDD_MEM_DEVICE) return HDD_OK;
+  return copy_out(h, out, h->nmean, size_t(ns) * size_t(tn), HDD_MEM_HOST);
 }
 
 int hdd_loglik(hdd_handle h, int32_t n_y, const double* xy, const double* y, double sigma, int32_t normalized,

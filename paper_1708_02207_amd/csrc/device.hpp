@@ -27,6 +27,7 @@ struct DevNode {
   int ids_off;          // into the level's id array ([gamma ; Gamma] global node ids)
   int x0, y0;           // lower-left cell of the node's rectangle
   long long panel_off;  // elements within the level's per-sample panel block (levels with a panel store)
+  int cw, ch;           // width and height of the rectangle in cells
 };
 
 struct DevLevel {

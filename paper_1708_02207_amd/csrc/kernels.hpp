@@ -59,4 +59,17 @@ hipError_t launch_loglik(int n_samples, int n_y, const double* hu, const double*
                          double* out, hipStream_t st);
 hipError_t launch_mfma_selftest(int dtype, double* out, hipStream_t st);
 
+// Means over every subdomain of the tree (functional propagation, or the
+// direct sum when the whole field is known).  mu / out: [sample][global node].
+hipError_t launch_block_mu(const DevBlocks& B, int n_samples, double* mu, long long mu_stride, hipStream_t st);
+hipError_t launch_level_mu(const DevLevel& L, const DevLevel& child, int n_samples, double* mu, long long mu_stride,
+                           hipStream_t st);
+hipError_t launch_node_means(const DevLevel& L, int n_samples, int nc, const double* u, long long ustride,
+                             const double* mu, long long mu_stride, double* out, long long out_stride,
+                             hipStream_t st);
+hipError_t launch_block_integral(const DevLevel& L, int n_samples, int nc, const double* u, long long ustride,
+                                 double* mu, long long mu_stride, double* out, long long out_stride, hipStream_t st);
+hipError_t launch_level_sum(const DevLevel& L, const DevLevel& child, int n_samples, int nc, double* mu,
+                            long long mu_stride, double* out, long long out_stride, hipStream_t st);
+
 }  // namespace hdd

@@ -33,7 +33,7 @@ HDD_FLAG_BLOCK8 = 4
 
 EXPORTED = [
     "hdd_default_opts", "hdd_workspace_size", "hdd_create", "hdd_build", "hdd_query_points",
-    "hdd_query_interface", "hdd_query_mean", "hdd_loglik", "hdd_solve_full", "hdd_get_solution",
+    "hdd_query_interface", "hdd_query_mean", "hdd_query_node_means", "hdd_loglik", "hdd_solve_full", "hdd_get_solution",
     "hdd_error_estimate", "hdd_sync", "hdd_last_node", "hdd_destroy", "hdd_strerror",
     "hdd_plan_summary", "hdd_plan_node", "hdd_plan_level", "hdd_debug_node_schur",
     "hdd_timing_enable", "hdd_timing_get", "hdd_mfma_selftest", "hdd_debug_frame",
@@ -85,6 +85,7 @@ def _load() -> ctypes.CDLL:
         "hdd_query_points": [P, i32, P, P, i32],
         "hdd_query_interface": [P, P, ctypes.POINTER(i32), i32],
         "hdd_query_mean": [P, P, P, i32],
+        "hdd_query_node_means": [P, P, i32],
         "hdd_loglik": [P, i32, P, P, dbl, i32, P, i32],
         "hdd_solve_full": [P],
         "hdd_get_solution": [P, i32, P, i32],
@@ -276,6 +277,18 @@ class HDD:
         res = np.zeros(self.n_samples)
         _check(_lib.hdd_query_mean(self.h, _np_ptr(r), _np_ptr(res), HDD_MEM_HOST), "hdd_query_mean")
         return res
+
+    def query_node_means(self, out=None) -> np.ndarray:
+        """Mean of u over every node of the tree down to the blocks,
+        [n_samples][nodes] in plan order (root, then depth by depth)."""
+        if out is None:
+            nodes = hdd_plan_summary(self.opts)["nodes"]
+            res = np.zeros((self.n_samples, nodes))
+            _check(_lib.hdd_query_node_means(self.h, _np_ptr(res), HDD_MEM_HOST), "hdd_query_node_means")
+            return res
+        op, mem = _ptr(out)
+        _check(_lib.hdd_query_node_means(self.h, op, mem), "hdd_query_node_means")
+        return out
 
     def loglik(self, xy, y, sigma: float, normalized: bool = False, out=None):
         xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)

@@ -1,0 +1,193 @@
+"""GPU parity of the means over every subdomain of the tree (Section 5.1).
+
+Two routes of hdd_query_node_means are checked against the oracle's means
+(eq. mean over each node's own triangles, oracle.node_means):
+  - functional propagation (HDD_FP64, max_refine = 0, before the full solve):
+    no block interior is solved, which the launch counters confirm;
+  - the direct sum from the full field (after hdd_solve_full, and always in
+    HDD_FP32_REFINE mode).
+Tolerances as for the other measurements: 1e-10 (float64), 1e-8 (float32 +
+refinement), normwise over each sample's vector of node means.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+try:  # import at collection so a slow first import is not charged to a test
+    import torch
+except Exception:  # pragma: no cover
+    torch = None
+
+from workload import make_workload, rhs_nodal
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = {0: 1e-10, 1: 1e-8}
+K_TOPDOWN = 4
+K_FUNCTIONAL = 10
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def H():
+    if torch is None or not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_02207_amd import hdd
+    return hdd
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _rand_tri_kappa(n, ns, seed, lo=0.1, hi=10.0):
+    return np.random.default_rng(seed).uniform(lo, hi, size=(ns, n + 1, n + 1, 2))
+
+
+@pytest.mark.parametrize("n,leaf,flags,ns,f", [
+    (3, 2, 0, 1, "one"),        # smallest tree: 2 x 2-cell blocks, every block touches the boundary
+    (15, 4, 0, 2, "bump"),
+    (31, 4, 1, 1, "bump"),      # plain-FMA cross-check
+    (63, 8, 0, 2, "bump"),
+    (127, 32, 4, 1, "one"),     # 8 x 8-cell blocks under 32 x 32-cell leaves
+    (255, 16, 0, 1, "bump"),
+])
+def test_node_means_fp64(H, oracle_mod, n, leaf, flags, ns, f):
+    O = oracle_mod
+    say(f"node means fp64 n={n} leaf={leaf} flags={flags} samples={ns} f={f}")
+    kap = _rand_tri_kappa(n, ns, 1000 + n)
+    fn = rhs_nodal(n, f)
+    o = H.hdd_default_opts(n, H.HDD_FP64, leaf=leaf, flags=flags)
+    block = min(16, leaf) if not (flags & 4) else 8
+    t = H.HDD(o, ns)
+    t.build(kap, fn)
+    summ = H.hdd_plan_summary(o)
+    t.timing_enable(1 << K_TOPDOWN)
+    got = t.query_node_means()
+    _, blk_launches, _ = t.timing_get(K_TOPDOWN, summ["depth_block"])
+    assert blk_launches == 0  # functional route: no block interior solved
+    assert got.shape == (ns, summ["nodes"])
+    refs = []
+    for s in range(ns):
+        u, _ = O.solve(n, kap[s], fn)
+        ref = O.node_means(n, u, block)
+        refs.append(ref)
+        e = rel(got[s], ref)
+        say(f"  sample {s}: functional route {e:.2e}")
+        assert e < TOL[0]
+    # the same means from the full field
+    t.solve_full()
+    got2 = t.query_node_means()
+    for s in range(ns):
+        e = rel(got2[s], refs[s])
+        say(f"  sample {s}: direct route {e:.2e}")
+        assert e < TOL[0]
+    t.close()
+
+
+def test_node_means_fp32_refine(H, oracle_mod):
+    O = oracle_mod
+    w = make_workload("c0_63")
+    say("node means fp32+refinement c0_63")
+    o = H.hdd_default_opts(w.n, H.HDD_FP32_REFINE, leaf=w.leaf)
+    t = H.HDD(o, 1)
+    t.build(w.kappa, w.f)
+    got = t.query_node_means()
+    u, _ = O.solve(w.n, w.kappa[0], w.f)
+    e = rel(got[0], O.node_means(w.n, u, 8))
+    say(f"  rel err {e:.2e}")
+    assert e < TOL[1]
+    t.close()
+
+
+def test_node_means_device_output_and_rebuild(H, oracle_mod):
+    """Device output buffer; a second build on the same handle (new kappa)
+    gives the new means (no stale functional or interface values)."""
+    O = oracle_mod
+    n, leaf = 31, 4
+    fn = rhs_nodal(n, "bump")
+    o = H.hdd_default_opts(n, H.HDD_FP64, leaf=leaf)
+    t = H.HDD(o, 2)
+    nodes = H.hdd_plan_summary(o)["nodes"]
+    for seed in (5, 6):
+        kap = _rand_tri_kappa(n, 2, seed)
+        t.build(torch.from_numpy(kap).cuda(), torch.from_numpy(fn).cuda())
+        out = torch.zeros((2, nodes), dtype=torch.float64, device="cuda")
+        t.query_node_means(out=out)
+        t.sync()
+        got = out.cpu().numpy()
+        for s in range(2):
+            u, _ = O.solve(n, kap[s], fn)
+            e = rel(got[s], O.node_means(n, u, 4))
+            say(f"  seed {seed} sample {s}: {e:.2e}")
+            assert e < TOL[0]
+    t.close()
+
+
+def test_node_means_1023_functional(H):
+    """1023^2, 32 x 32-cell leaves, the four samples with stored oracle
+    values: the functional route in float64 (8191 nodes per sample).  The
+    node [0.25, 0.5]^2 (depth 4) matches the oracle's stored mean; every
+    father's mean is the area-weighted average of its sons' (a property at any
+    size); the root and depth-1 means agree with the float32 + refinement path
+    (direct route) to 1e-8."""
+    with open(os.path.join(HERE, "golden", "c2_1023.json")) as fh:
+        g = json.load(fh)
+    w = make_workload("c2_1023")
+    ns = len(g["samples"])
+    say("node means 1023^2 fp64 functional, samples", ns)
+    kd = torch.from_numpy(w.kappa[:ns]).cuda()
+    fd = torch.from_numpy(w.f).cuda()
+    o = H.hdd_default_opts(w.n, H.HDD_FP64, leaf=w.leaf)
+    t = H.HDD(o, ns)
+    t.build(kd, fd)
+    got = t.query_node_means()
+    t.close()
+    nc = w.n + 1
+    # locate the [0.25, 0.5]^2 node: depth 4 splits the square into 4 x 4
+    x0, x1, y0, y1 = (int(round(v * nc)) for v in g["mean_rect"])
+    k, lo, d = 0, [0, nc, 0, nc], 0
+    while (lo[0], lo[1], lo[2], lo[3]) != (x0, x1, y0, y1):
+        vert = lo[1] - lo[0] >= lo[3] - lo[2]
+        if vert:
+            m = (lo[0] + lo[1]) // 2
+            right = x0 >= m
+            lo = [m, lo[1], lo[2], lo[3]] if right else [lo[0], m, lo[2], lo[3]]
+        else:
+            m = (lo[2] + lo[3]) // 2
+            right = y0 >= m
+            lo = [lo[0], lo[1], m, lo[3]] if right else [lo[0], lo[1], lo[2], m]
+        k = 2 * k + (1 if right else 0)
+        d += 1
+    idx = (2 ** d - 1) + k
+    for s in g["samples"]:
+        e = rel([got[s["sample"], idx]], [s["mean"]])
+        say(f"  sample {s['sample']}: node {idx} (depth {d}) vs stored oracle mean {e:.2e}")
+        assert e < TOL[0]
+    # sons average to the father at every node
+    nodes = got.shape[1]
+    area = np.empty(nodes)
+    area[0] = 1.0
+    for p in range((nodes - 1) // 2):
+        area[2 * p + 1] = area[2 * p + 2] = area[p] / 2
+    for p in range((nodes - 1) // 2):
+        fa = got[:, p]
+        av = (got[:, 2 * p + 1] + got[:, 2 * p + 2]) / 2
+        assert np.abs(fa - av).max() < 1e-12 * np.abs(got).max()
+    o32 = H.hdd_default_opts(w.n, H.HDD_FP32_REFINE, leaf=w.leaf)
+    t32 = H.HDD(o32, ns)
+    t32.build(kd, fd)
+    got32 = t32.query_node_means()
+    t32.close()
+    e = rel(got32, got)
+    say(f"  float32 + refinement (direct route) vs float64 functional, all nodes: {e:.2e}")
+    assert e < TOL[1]
