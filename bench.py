@@ -307,6 +307,35 @@ def main():
         ablation.append({"name": "fp32 + float64 refinement batched (headline)", "value": B * a.steps / dt,
                          "unit": "likelihood evals/s", "ms_per_step": 1e3 * dt / a.steps})
 
+    # Means over all 2 nb - 1 subdomains of the tree on the float64 batch:
+    # functional propagation (bottom-up functional pass, interfaces above the
+    # blocks only) against the full Root to Leaves plus the direct sum.
+    node_means = None
+    if not a.no_ablation and prec == H.HDD_FP32_REFINE:
+        o64 = H.hdd_default_opts(w.n, H.HDD_FP64, leaf=w.leaf)
+        summ = H.hdd_plan_summary(o64)
+        c = H.HDD(o64, B, stream=stream)
+        nm = torch.empty((B, summ["nodes"]), dtype=torch.float64, device="cuda")
+        route_ms = {}
+        for route in ("functional", "full_field"):
+            reps, tot = 3, 0.0
+            for r in range(reps + 1):
+                c.build(kd, fd)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if route == "full_field":
+                    c.solve_full()
+                c.query_node_means(out=nm)
+                torch.cuda.synchronize()
+                if r > 0:
+                    tot += time.perf_counter() - t0
+            route_ms[route] = 1e3 * tot / reps
+        c.close()
+        node_means = {"nodes": summ["nodes"], "samples": B, "dtype": "f64",
+                      "functional_ms": route_ms["functional"], "full_field_ms": route_ms["full_field"],
+                      "means_per_s": summ["nodes"] * B / (1e-3 * route_ms["functional"]),
+                      "note": "ms per batch after the build; full_field = full Root to Leaves + direct sums"}
+
     serving = None if a.no_serve else serving_mix(H, a.serve_requests)
     cpu = None if a.no_cpu_baseline else cpu_baseline(w, a.cpu_seconds)
 
@@ -334,6 +363,7 @@ def main():
                      "max_refine_estimate": float(np.max(est)) if len(est) else None, "status": H.strerror(code)},
         "roofline": roofline,
         "ablation": ablation,
+        "node_means": node_means,
         "kernels_ms_per_step": {k: v["ms"] for k, v in kern.items()},
         "kernels_tflops": {k: v["tflops"] for k, v in kern.items() if v["tflops"]},
         "comparator": comparator,
