@@ -62,14 +62,20 @@ __global__ void __launch_bounds__(FT) k_block_mu(DevBlocks B, int n_samples, dou
   const int s = blockIdx.x % n_samples;
   const T* cst = reinterpret_cast<const T*>(B.cst) + (long long)s * B.cst_stride + (long long)q * B.cst_size;
   const double* vz = B.vec + (long long)s * B.vec_stride + (long long)q * B.vec_size;
+  // one entry of the store per thread (the levels' entries are contiguous,
+  // level K at vec_off[K]), every load issued before any is used
   double acc = 0.0;
-  for (int K = 0; K < B.nlev; ++K) {
+  for (int e0 = 0; e0 < B.vec_size; e0 += FT) {
+    const int e = e0 + int(threadIdx.x);
+    int K = 0;
+    for (int k = 1; k < B.nlev; ++k)
+      if (e >= B.lv[k].vec_off) K = k;
     const DevSubLevel l = B.lv[K];
-    const int g = l.gam;
-    for (int e = threadIdx.x; e < l.n * g; e += FT) {
-      const int t = e / g, i = e % g;
-      acc += vz[l.vec_off + e] * double(cst[l.cst_off + (long long)t * (l.U + 1) * g + (long long)l.U * g + i]);
-    }
+    const int r = min(e, B.vec_size - 1) - l.vec_off;
+    const int t = r / l.gam, i = r % l.gam;
+    const double a = vz[l.vec_off + r];
+    const double y = double(cst[l.cst_off + (long long)t * (l.U + 1) * l.gam + (long long)l.U * l.gam + i]);
+    if (e < B.vec_size) acc += a * y;
   }
   const double tot = block_sum(acc, red);
   if (threadIdx.x == 0) mu[(long long)s * mu_stride + B.top.node_base + q] = tot;
