@@ -7,6 +7,7 @@ never imports it.
 Contents
   solve(n, kappa, f)             global P1 solve, banded Cholesky + extended-
                                  precision refinement (oracle.c)
+  solve_dirichlet(n, kappa, f, g)  the same with non-zero Dirichlet data
   residual(n, kappa, f, u)       b - A u in extended precision (oracle.c)
   point_values / interface / mean / loglik    the measurement operators
   tree_rects / node_means        subdomains of the tree and their means
@@ -81,6 +82,39 @@ def solve(n: int, kappa: np.ndarray, f: np.ndarray, sweeps: int = 2) -> Tuple[np
     if info != 0:
         raise RuntimeError(f"oracle_solve failed: info={info}")
     return u, rr.value
+
+
+def solve_dirichlet(n: int, kappa: np.ndarray, f: np.ndarray, g: np.ndarray, sweeps: int = 2) -> np.ndarray:
+    """u_full for the problem with Dirichlet data (the boundary condition u = g
+    of eq. elliptic_det): u = g at the outer boundary nodes and, inside,
+    A_II u_I = b_I - A_ID g_D.  The lifting A_ID g_D is summed triangle by
+    triangle from the element matrices of eq. coefA over the ring of cells
+    that touches the boundary; the interior system is then the zero-Dirichlet
+    solve above with the lifted load (passed as the nodal f it corresponds
+    to, b / h^2)."""
+    nc = n + 1
+    h = 1.0 / nc
+    k = np.asarray(kappa, dtype=np.float64).reshape(nc, nc, 2)
+    gg = np.asarray(g, dtype=np.float64)
+
+    def boundary(v):
+        return v[0] in (0, nc) or v[1] in (0, nc)
+
+    lift = np.zeros((n + 2, n + 2))
+    ring = [(i, j) for j in range(nc) for i in range(nc) if i in (0, nc - 1) or j in (0, nc - 1)]
+    for i, j in ring:
+        for verts, (jj, ii, t) in _triangles(n, i, i + 1, j, j + 1):
+            K, _ = _element(verts, k[jj, ii, t], h)
+            for a in range(3):
+                if boundary(verts[a]):
+                    continue
+                for c in range(3):
+                    if boundary(verts[c]):
+                        lift[verts[a][1], verts[a][0]] += K[a, c] * gg[verts[c][1], verts[c][0]]
+    f_lift = np.asarray(f, dtype=np.float64) - lift / (h * h)
+    u, _ = solve(n, kappa, f_lift, sweeps)
+    u[0, :], u[-1, :], u[:, 0], u[:, -1] = gg[0, :], gg[-1, :], gg[:, 0], gg[:, -1]
+    return u
 
 
 def residual(n: int, kappa: np.ndarray, f: np.ndarray, u_full: np.ndarray) -> np.ndarray:

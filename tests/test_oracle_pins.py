@@ -403,3 +403,58 @@ def test_functional_lemma_dense(oracle_mod, father):
     area = (i1 - i0) * (j1 - j0) * h * h
     ref = O.mean_value(n, u, (i0 / nc, i1 / nc, j0 / nc, j1 / nc)) * area
     assert abs(integral - ref) < 1e-12 * abs(ref)
+
+
+# Non-zero Dirichlet data ----------------------------------------------------------------
+def test_dirichlet_affine_exact(oracle_mod):
+    """Constant kappa, f = 0, affine boundary data: the P1 space holds the
+    affine function, and it is discrete-harmonic (the gradients of a node's
+    hat function sum to zero over its patch), so u_h equals it at every node."""
+    O = oracle_mod
+    n = 31
+    h = 1.0 / (n + 1)
+    x = np.arange(n + 2) * h
+    X, Y = np.meshgrid(x, x)
+    g = 0.5 + 2.0 * X - 3.0 * Y
+    u = O.solve_dirichlet(n, 2.5 * np.ones((n + 1, n + 1, 2)), np.zeros((n + 2, n + 2)), g)
+    assert np.abs(u - g).max() < 1e-13
+
+
+@pytest.mark.parametrize("n,seed", [(3, 1), (7, 2)])
+def test_dirichlet_bruteforce(oracle_mod, n, seed):
+    """Dense element-loop assembly on every node, boundary values moved to
+    the right-hand side, inverse by LAPACK."""
+    O = oracle_mod
+    rng = np.random.default_rng(seed)
+    k = _rand_tri_kappa(n, seed)
+    f = rng.standard_normal((n + 2, n + 2))
+    g = rng.standard_normal((n + 2, n + 2))
+    A, b, nodes = O.assemble_dense(n, k, f)
+    nc = n + 1
+    inner = [t for t, (i, j) in enumerate(nodes) if 1 <= i <= n and 1 <= j <= n]
+    bnd = [t for t, (i, j) in enumerate(nodes) if not (1 <= i <= n and 1 <= j <= n)]
+    gD = np.array([g[nodes[t][1], nodes[t][0]] for t in bnd])
+    uI = np.linalg.solve(A[np.ix_(inner, inner)], b[inner] - A[np.ix_(inner, bnd)] @ gD)
+    u = O.solve_dirichlet(n, k, f, g)
+    ref = g.copy()
+    for t, val in zip(inner, uI):
+        ref[nodes[t][1], nodes[t][0]] = val
+    assert np.abs(u - ref).max() < 1e-12 * np.abs(ref).max()
+    assert nc == n + 1
+
+
+def test_dirichlet_superposition(oracle_mod):
+    """u(f, g) = u(f, 0) + u(0, g) (the operators F_h and G_h of eq.
+    oper_represent2 are linear), and u(f, 0) is the zero-Dirichlet solve."""
+    O = oracle_mod
+    n = 31
+    rng = np.random.default_rng(4)
+    k = _rand_tri_kappa(n, 9)
+    f = rhs_nodal(n, "bump")
+    g = rng.uniform(-1, 1, (n + 2, n + 2))
+    z = np.zeros((n + 2, n + 2))
+    u = O.solve_dirichlet(n, k, f, g)
+    u0, _ = O.solve(n, k, f)
+    assert np.abs(O.solve_dirichlet(n, k, f, z) - u0).max() < 1e-14 * np.abs(u0).max()
+    ug = O.solve_dirichlet(n, k, z, g)
+    assert np.abs(u - (u0 + ug)).max() < 1e-13 * np.abs(u).max()
