@@ -193,6 +193,28 @@ int hdd_loglik_ragged(hdd_handle h, const int32_t* offsets, const double* xy, co
  * HDD_FP32_REFINE mode.  Errors: HDD_ENOTCONVERGED (values still usable). */
 int hdd_solve_full(hdd_handle h);
 
+/*
+ * The field for another load and Dirichlet data on the built operators: the
+ * maps of every node (Phi^f and Phi^g in factored form) are computed once by
+ * hdd_build and applied here again (u_h = F_h f_h + G_h g_h, eq.
+ * oper_represent2; the advantage for many right-hand sides and Dirichlet data
+ * noted after it).  For every built sample, u_h solves the problem of eq.
+ * elliptic_det with load f and u = g on the outer boundary:
+ *   f  (mem) float64 [N+2][N+2] nodal, shared by all samples (boundary
+ *      entries unused)
+ *   g  (mem) float64 [N+2][N+2] nodal, only the outer-boundary entries are
+ *      read, shared by all samples; NULL: zero Dirichlet data
+ * Starting from u = g on the boundary and 0 inside, the lifted load
+ * b(f) - A u is eliminated bottom-up (the forward pass), then a full Root to
+ * Leaves solves every node; in HDD_FP32_REFINE mode (max_refine > 0) the
+ * refinement sweeps follow with the stopping test of refine_tol.  Later
+ * queries (points, interface, means, likelihood, hdd_get_solution) read this
+ * field until the next hdd_build.  hdd_error_estimate reports the sweeps,
+ * the solve sweep included.  Errors: HDD_ESTATE before a build, HDD_EINVAL
+ * (non-finite host data), HDD_ENOTCONVERGED (values still usable).
+ */
+int hdd_solve_rhs(hdd_handle h, const double* f, const double* g, int32_t mem);
+
 /* The nodal field of one sample, u_out (mem) float64 [N+2][N+2]; requires
  * hdd_solve_full. */
 int hdd_get_solution(hdd_handle h, int32_t sample, double* u_out, int32_t mem);

@@ -8,6 +8,7 @@ Contents
   solve(n, kappa, f)             global P1 solve, banded Cholesky + extended-
                                  precision refinement (oracle.c)
   solve_dirichlet(n, kappa, f, g)  the same with non-zero Dirichlet data
+  lifted_load(n, kappa, f, g)    its interior load, as a nodal f
   residual(n, kappa, f, u)       b - A u in extended precision (oracle.c)
   point_values / interface / mean / loglik    the measurement operators
   tree_rects / node_means        subdomains of the tree and their means
@@ -84,14 +85,12 @@ def solve(n: int, kappa: np.ndarray, f: np.ndarray, sweeps: int = 2) -> Tuple[np
     return u, rr.value
 
 
-def solve_dirichlet(n: int, kappa: np.ndarray, f: np.ndarray, g: np.ndarray, sweeps: int = 2) -> np.ndarray:
-    """u_full for the problem with Dirichlet data (the boundary condition u = g
-    of eq. elliptic_det): u = g at the outer boundary nodes and, inside,
-    A_II u_I = b_I - A_ID g_D.  The lifting A_ID g_D is summed triangle by
-    triangle from the element matrices of eq. coefA over the ring of cells
-    that touches the boundary; the interior system is then the zero-Dirichlet
-    solve above with the lifted load (passed as the nodal f it corresponds
-    to, b / h^2)."""
+def lifted_load(n: int, kappa: np.ndarray, f: np.ndarray, g: np.ndarray) -> np.ndarray:
+    """The nodal load f' whose interior load vector is b_I - A_ID g_D (u = g
+    on the outer boundary, eq. elliptic_det): the lifting A_ID g_D is summed
+    triangle by triangle from the element matrices of eq. coefA over the ring
+    of cells that touches the boundary, and divided by h^2 (the load vector
+    of eq. coefc is h^2 f at an interior node)."""
     nc = n + 1
     h = 1.0 / nc
     k = np.asarray(kappa, dtype=np.float64).reshape(nc, nc, 2)
@@ -111,8 +110,14 @@ def solve_dirichlet(n: int, kappa: np.ndarray, f: np.ndarray, g: np.ndarray, swe
                 for c in range(3):
                     if boundary(verts[c]):
                         lift[verts[a][1], verts[a][0]] += K[a, c] * gg[verts[c][1], verts[c][0]]
-    f_lift = np.asarray(f, dtype=np.float64) - lift / (h * h)
-    u, _ = solve(n, kappa, f_lift, sweeps)
+    return np.asarray(f, dtype=np.float64) - lift / (h * h)
+
+
+def solve_dirichlet(n: int, kappa: np.ndarray, f: np.ndarray, g: np.ndarray, sweeps: int = 2) -> np.ndarray:
+    """u_full for the problem with Dirichlet data: u = g at the outer boundary
+    nodes and, inside, the zero-Dirichlet solve above with the lifted load."""
+    gg = np.asarray(g, dtype=np.float64)
+    u, _ = solve(n, kappa, lifted_load(n, kappa, f, g), sweeps)
     u[0, :], u[-1, :], u[:, 0], u[:, -1] = gg[0, :], gg[-1, :], gg[:, 0], gg[:, -1]
     return u
 

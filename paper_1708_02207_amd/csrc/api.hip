@@ -114,8 +114,9 @@ Layout make_layout(const Plan& p, const hdd_opts& o, int ms) {
   L.kappa = take(int64_t(ms) * nc * nc * 2 * 8);
   L.f = take(nn * 8);
   L.u = take(int64_t(ms) * nn * 8);
-  L.d = refine ? take(int64_t(ms) * nn * 8) : -1;
-  L.r = refine ? take(int64_t(ms) * nn * 8) : -1;
+  // correction and residual fields: refinement, and solves for further loads
+  L.d = take(int64_t(ms) * nn * 8);
+  L.r = take(int64_t(ms) * nn * 8);
   L.info = take(int64_t(ms) * 4);
   L.bad = take(int64_t(ms) * 4);
   L.maxbits = take(int64_t(ms) * 16);
@@ -290,15 +291,13 @@ int full_topdown(hdd_tree* h, double* target, bool from_vec) {
   return run_block_topdown(h, h->iota, h->blk.nb, target, from_vec);
 }
 
-int ensure_full(hdd_tree* h) {
-  if (h->full) return HDD_OK;
-  HDD_TRY(full_topdown(h, h->u, false));
-  for (auto& v : h->solved) std::fill(v.begin(), v.end(), 1);
-  h->full = true;
-  h->sweeps = 0;
-  std::fill(h->est.begin(), h->est.end(), 0.0);
-  const int max_it = h->opt.max_refine;
-  if (max_it <= 0 || h->d == nullptr) return HDD_OK;
+// Up to max_it correction sweeps u += d, with d from the bottom-up
+// elimination of the residual r = b - A u (forward pass) and a full top-down
+// on it, stopped by the predicted-error test below.  With u holding only
+// boundary data the first sweep is the solve itself.  With `test` false the
+// sweeps never report non-convergence (a single solve sweep has nothing to
+// compare with).
+int correction_sweeps(hdd_tree* h, int max_it, bool test) {
   const int D = int(h->lev.size()) - 1;
   const int nc = h->plan.nc;
   const int ns = h->n_samples;
@@ -348,8 +347,19 @@ int ensure_full(hdd_tree* h) {
       break;
     }
   }
-  if (!converged) h->deferred = HDD_ENOTCONVERGED;
+  if (!converged && test) h->deferred = HDD_ENOTCONVERGED;
   return HDD_OK;
+}
+
+int ensure_full(hdd_tree* h) {
+  if (h->full) return HDD_OK;
+  HDD_TRY(full_topdown(h, h->u, false));
+  for (auto& v : h->solved) std::fill(v.begin(), v.end(), 1);
+  h->full = true;
+  h->sweeps = 0;
+  std::fill(h->est.begin(), h->est.end(), 0.0);
+  if (h->opt.max_refine <= 0) return HDD_OK;
+  return correction_sweeps(h, h->opt.max_refine, true);
 }
 
 // Solve, root first, the nodes marked in `need` that are not solved yet.
@@ -892,6 +902,29 @@ int hdd_solve_full(hdd_handle h) {
   if (!h) return HDD_EINVAL;
   if (!h->built) return HDD_ESTATE;
   HDD_TRY(ensure_full(h));
+  return check_deferred(h);
+}
+
+int hdd_solve_rhs(hdd_handle h, const double* f, const double* g, int32_t mem) {
+  if (!h || !f || (mem != HDD_MEM_HOST && mem != HDD_MEM_DEVICE)) return HDD_EINVAL;
+  if (!h->built) return HDD_ESTATE;
+  const size_t fbytes = size_t(h->nn) * 8;
+  const hipMemcpyKind kind = mem == HDD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  if (mem == HDD_MEM_HOST) {
+    for (long long i = 0; i < h->nn; ++i)
+      if (!std::isfinite(f[i]) || (g && !std::isfinite(g[i]))) return HDD_EINVAL;
+  }
+  // the new load replaces the build's (the residual reads it); g is staged in
+  // the residual field, which the first sweep overwrites
+  HIP_TRY(hipMemcpyAsync(h->f, f, fbytes, kind, h->st));
+  if (g) HIP_TRY(hipMemcpyAsync(h->r, g, fbytes, kind, h->st));
+  HIP_TRY(hdd::launch_lift_init(h->plan.nc, h->n_samples, g ? h->r : nullptr, h->u, h->st));
+  for (auto& v : h->solved) std::fill(v.begin(), v.end(), 1);
+  h->full = true;
+  h->sweeps = 0;
+  std::fill(h->est.begin(), h->est.end(), 0.0);
+  const int refine = std::max(0, h->opt.max_refine);
+  HDD_TRY(correction_sweeps(h, 1 + refine, refine > 0));
   return check_deferred(h);
 }
 

@@ -511,6 +511,19 @@ __global__ void k_residual(int nc, int n_samples, const double* __restrict__ kap
   rs[id] = b - au;
 }
 
+// Start of a solve with Dirichlet data: u = g on the outer boundary (g
+// nodal, shared by all samples; nullptr = zero) and 0 inside, so that the
+// residual b - A u is the lifted load b_I - A_ID g_D at the interior nodes.
+__global__ void k_lift_init(int nc, int n_samples, const double* __restrict__ g, double* __restrict__ u) {
+  const long long nn = (long long)(nc + 1) * (nc + 1);
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nn * n_samples) return;
+  const int id = int(t % nn);
+  const int i = id % (nc + 1), j = id / (nc + 1);
+  const bool bnd = i == 0 || j == 0 || i == nc || j == nc;
+  u[t] = (bnd && g) ? g[id] : 0.0;
+}
+
 __device__ __forceinline__ void atomic_max_abs(unsigned long long* p, double v) {
   atomicMax(p, (unsigned long long)__double_as_longlong(fabs(v)));
 }
@@ -803,6 +816,12 @@ hipError_t launch_fill(double* p, long long n, double v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   dim3 grid(std::max(1, std::min(ceil_div(n, 256), 65536))), block(256);
   hipLaunchKernelGGL(k_fill, grid, block, 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_lift_init(int nc, int n_samples, const double* g, double* u, hipStream_t st) {
+  const long long n = (long long)(nc + 1) * (nc + 1) * n_samples;
+  hipLaunchKernelGGL(k_lift_init, dim3(ceil_div(n, 256)), dim3(256), 0, st, nc, n_samples, g, u);
   return hipGetLastError();
 }
 
