@@ -9,6 +9,7 @@ Contents
                                  precision refinement (oracle.c)
   solve_dirichlet(n, kappa, f, g)  the same with non-zero Dirichlet data
   lifted_load(n, kappa, f, g)    its interior load, as a nodal f
+  prolong(n_coarse, v)           P1 values of a coarse-mesh function on the mesh of half the step
   residual(n, kappa, f, u)       b - A u in extended precision (oracle.c)
   point_values / interface / mean / loglik    the measurement operators
   tree_rects / node_means        subdomains of the tree and their means
@@ -111,6 +112,29 @@ def lifted_load(n: int, kappa: np.ndarray, f: np.ndarray, g: np.ndarray) -> np.n
                     if boundary(verts[c]):
                         lift[verts[a][1], verts[a][0]] += K[a, c] * gg[verts[c][1], verts[c][0]]
     return np.asarray(f, dtype=np.float64) - lift / (h * h)
+
+
+def prolong(n_coarse: int, v: np.ndarray) -> np.ndarray:
+    """Nodal values on the mesh of step h = H/2 of the P1 function with nodal
+    values v on the coarse mesh of step H (Section 3.5, multiple scales: a
+    smooth right-hand side given on a coarser mesh).  Both meshes split every
+    cell along its SW-NE diagonal, so a fine node is a coarse node, the
+    midpoint of a horizontal or vertical coarse edge, or the midpoint of a
+    coarse diagonal, and takes the coarse value or the mean of the edge's two
+    ends.  v: [n_coarse+2]^2; returns [2 n_coarse + 3]^2."""
+    v = np.asarray(v, dtype=np.float64)
+    m = n_coarse + 1  # coarse cells per side
+    out = np.zeros((2 * m + 1, 2 * m + 1))
+    for J in range(m + 1):
+        for I in range(m + 1):
+            out[2 * J, 2 * I] = v[J, I]
+            if I < m:
+                out[2 * J, 2 * I + 1] = 0.5 * (v[J, I] + v[J, I + 1])
+            if J < m:
+                out[2 * J + 1, 2 * I] = 0.5 * (v[J, I] + v[J + 1, I])
+            if I < m and J < m:
+                out[2 * J + 1, 2 * I + 1] = 0.5 * (v[J, I] + v[J + 1, I + 1])
+    return out
 
 
 def solve_dirichlet(n: int, kappa: np.ndarray, f: np.ndarray, g: np.ndarray, sweeps: int = 2) -> np.ndarray:

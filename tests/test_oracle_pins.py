@@ -458,3 +458,24 @@ def test_dirichlet_superposition(oracle_mod):
     assert np.abs(O.solve_dirichlet(n, k, f, z) - u0).max() < 1e-14 * np.abs(u0).max()
     ug = O.solve_dirichlet(n, k, z, g)
     assert np.abs(u - (u0 + ug)).max() < 1e-13 * np.abs(u).max()
+
+
+# Coarse-mesh data (Section 3.5) ----------------------------------------------------------
+def test_prolong_affine_and_interpolant(oracle_mod):
+    """The fine-mesh values of a coarse P1 function: affine functions are
+    reproduced exactly, and the fine P1 interpolant of the prolonged values
+    equals the coarse P1 function at arbitrary points (same SW-NE diagonals
+    on both meshes)."""
+    O = oracle_mod
+    nH = 15
+    m = nH + 1
+    X, Y = np.meshgrid(np.arange(m + 1) / m, np.arange(m + 1) / m)
+    fine = O.prolong(nH, 1.0 + 2.0 * X - 0.5 * Y)
+    Xf, Yf = np.meshgrid(np.arange(2 * m + 1) / (2 * m), np.arange(2 * m + 1) / (2 * m))
+    assert np.abs(fine - (1.0 + 2.0 * Xf - 0.5 * Yf)).max() < 1e-15
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal((m + 1, m + 1))
+    vf = O.prolong(nH, v)
+    nh = 2 * m - 1
+    for x, y in rng.uniform(0, 1, (200, 2)):
+        assert abs(O.point_value(nh, vf, x, y) - O.point_value(nH, v, x, y)) < 1e-14
