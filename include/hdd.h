@@ -215,6 +215,21 @@ int hdd_solve_full(hdd_handle h);
  */
 int hdd_solve_rhs(hdd_handle h, const double* f, const double* g, int32_t mem);
 
+/*
+ * Two-grid data (Section 3.5, multiple scales): a smooth load given on the
+ * mesh of twice the step, H = 2h, and the solution read on that mesh.
+ * hdd_solve_rhs_coarse: as hdd_solve_rhs with the fine load taken as the P1
+ *   interpolant of f_coarse (mem, float64 [Nc/2+1][Nc/2+1] nodal, both meshes
+ *   split along SW-NE diagonals, so a fine node takes the coarse value or the
+ *   mean of a coarse edge's two ends); g as in hdd_solve_rhs (fine mesh).
+ * hdd_get_solution_coarse: the field of sample `sample` at the nodes of the
+ *   coarse mesh, u_out (mem) float64 [Nc/2+1][Nc/2+1] (requires the full
+ *   field: after hdd_solve_full, hdd_solve_rhs(_coarse), or any query in
+ *   HDD_FP32_REFINE mode; HDD_ESTATE otherwise).
+ */
+int hdd_solve_rhs_coarse(hdd_handle h, const double* f_coarse, const double* g, int32_t mem);
+int hdd_get_solution_coarse(hdd_handle h, int32_t sample, double* u_out, int32_t mem);
+
 /* The nodal field of one sample, u_out (mem) float64 [N+2][N+2]; requires
  * hdd_solve_full. */
 int hdd_get_solution(hdd_handle h, int32_t sample, double* u_out, int32_t mem);

@@ -418,6 +418,24 @@ int prepare_values(hdd_tree* h, const std::vector<std::vector<uint8_t>>& need) {
   return partial_topdown(h, need);
 }
 
+hipMemcpyKind copy_kind(int mem) { return mem == HDD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice; }
+
+// The full field for the load already in h->f and Dirichlet data g (nodal,
+// outer-boundary entries read; nullptr = zero): u = g on the boundary and 0
+// inside, then the correction sweeps, the first of which is the solve.  g is
+// staged in the residual field, which the first sweep overwrites.
+int solve_loaded_rhs(hdd_tree* h, const double* g, int mem) {
+  if (g) HIP_TRY(hipMemcpyAsync(h->r, g, size_t(h->nn) * 8, copy_kind(mem), h->st));
+  HIP_TRY(hdd::launch_lift_init(h->plan.nc, h->n_samples, g ? h->r : nullptr, h->u, h->st));
+  for (auto& v : h->solved) std::fill(v.begin(), v.end(), 1);
+  h->full = true;
+  h->sweeps = 0;
+  std::fill(h->est.begin(), h->est.end(), 0.0);
+  const int refine = std::max(0, h->opt.max_refine);
+  HDD_TRY(correction_sweeps(h, 1 + refine, refine > 0));
+  return check_deferred(h);
+}
+
 int copy_out(hdd_tree* h, double* dst, const double* src_dev, size_t n, int mem) {
   if (mem == HDD_MEM_DEVICE) return hip_status(hipMemcpyAsync(dst, src_dev, n * 8, hipMemcpyDeviceToDevice, h->st));
   HIP_TRY(hipMemcpyAsync(dst, src_dev, n * 8, hipMemcpyDeviceToHost, h->st));
@@ -909,23 +927,41 @@ int hdd_solve_rhs(hdd_handle h, const double* f, const double* g, int32_t mem) {
   if (!h || !f || (mem != HDD_MEM_HOST && mem != HDD_MEM_DEVICE)) return HDD_EINVAL;
   if (!h->built) return HDD_ESTATE;
   const size_t fbytes = size_t(h->nn) * 8;
-  const hipMemcpyKind kind = mem == HDD_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
   if (mem == HDD_MEM_HOST) {
     for (long long i = 0; i < h->nn; ++i)
       if (!std::isfinite(f[i]) || (g && !std::isfinite(g[i]))) return HDD_EINVAL;
   }
-  // the new load replaces the build's (the residual reads it); g is staged in
-  // the residual field, which the first sweep overwrites
-  HIP_TRY(hipMemcpyAsync(h->f, f, fbytes, kind, h->st));
-  if (g) HIP_TRY(hipMemcpyAsync(h->r, g, fbytes, kind, h->st));
-  HIP_TRY(hdd::launch_lift_init(h->plan.nc, h->n_samples, g ? h->r : nullptr, h->u, h->st));
-  for (auto& v : h->solved) std::fill(v.begin(), v.end(), 1);
-  h->full = true;
-  h->sweeps = 0;
-  std::fill(h->est.begin(), h->est.end(), 0.0);
-  const int refine = std::max(0, h->opt.max_refine);
-  HDD_TRY(correction_sweeps(h, 1 + refine, refine > 0));
-  return check_deferred(h);
+  // the new load replaces the build's (the residual reads it)
+  HIP_TRY(hipMemcpyAsync(h->f, f, fbytes, copy_kind(mem), h->st));
+  return solve_loaded_rhs(h, g, mem);
+}
+
+int hdd_solve_rhs_coarse(hdd_handle h, const double* f_coarse, const double* g, int32_t mem) {
+  if (!h || !f_coarse || (mem != HDD_MEM_HOST && mem != HDD_MEM_DEVICE)) return HDD_EINVAL;
+  if (!h->built) return HDD_ESTATE;
+  const long long m1 = h->plan.nc / 2 + 1;
+  if (mem == HDD_MEM_HOST) {
+    for (long long i = 0; i < m1 * m1; ++i)
+      if (!std::isfinite(f_coarse[i])) return HDD_EINVAL;
+    if (g)
+      for (long long i = 0; i < h->nn; ++i)
+        if (!std::isfinite(g[i])) return HDD_EINVAL;
+  }
+  // coarse values staged in the correction field, prolonged into the load
+  HIP_TRY(hipMemcpyAsync(h->d, f_coarse, size_t(m1 * m1) * 8, copy_kind(mem), h->st));
+  HIP_TRY(hdd::launch_prolong(h->plan.nc, h->d, h->f, h->st));
+  return solve_loaded_rhs(h, g, mem);
+}
+
+int hdd_get_solution_coarse(hdd_handle h, int32_t sample, double* u_out, int32_t mem) {
+  if (!h || !u_out || sample < 0 || sample >= h->n_samples || (mem != HDD_MEM_HOST && mem != HDD_MEM_DEVICE))
+    return HDD_EINVAL;
+  if (!h->built || !h->full) return HDD_ESTATE;
+  const long long m1 = h->plan.nc / 2 + 1;
+  double* dst = mem == HDD_MEM_DEVICE ? u_out : h->d;
+  HIP_TRY(hdd::launch_inject(h->plan.nc, h->u + (long long)sample * h->nn, dst, h->st));
+  if (mem == HDD_MEM_DEVICE) return HDD_OK;
+  return copy_out(h, u_out, h->d, size_t(m1 * m1), HDD_MEM_HOST);
 }
 
 int hdd_get_solution(hdd_handle h, int32_t sample, double* u_out, int32_t mem) {

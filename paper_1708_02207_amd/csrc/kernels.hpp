@@ -42,6 +42,8 @@ hipError_t launch_forward(const DevLevel& L, const DevLevel& child, int n_sample
 
 // Full-field and readout kernels (FP64)
 hipError_t launch_fill(double* p, long long n, double v, hipStream_t st);
+hipError_t launch_prolong(int nc, const double* vc, double* vf, hipStream_t st);
+hipError_t launch_inject(int nc, const double* u, double* out, hipStream_t st);
 hipError_t launch_lift_init(int nc, int n_samples, const double* g, double* u, hipStream_t st);
 hipError_t launch_residual(int nc, int n_samples, const double* kappa, const double* f, const double* u,
                            double* r, hipStream_t st);

@@ -524,6 +524,31 @@ __global__ void k_lift_init(int nc, int n_samples, const double* __restrict__ g,
   u[t] = (bnd && g) ? g[id] : 0.0;
 }
 
+// Fine-mesh nodal values of a P1 function given on the mesh of twice the
+// step (both meshes split every cell along its SW-NE diagonal): a fine node
+// is a coarse node or the midpoint of a coarse edge (horizontal, vertical or
+// diagonal) and takes the coarse value or the mean of the edge's two ends.
+// vc: [nc/2 + 1]^2, vf: [nc + 1]^2.
+__global__ void k_prolong(int nc, const double* __restrict__ vc, double* __restrict__ vf) {
+  const long long nn = (long long)(nc + 1) * (nc + 1);
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nn) return;
+  const int i = int(t % (nc + 1)), j = int(t / (nc + 1));
+  const int m1 = nc / 2 + 1;
+  const int I0 = i / 2, J0 = j / 2;
+  const int I1 = (i + 1) / 2, J1 = (j + 1) / 2;  // the other end of the edge (or the node itself)
+  vf[t] = 0.5 * (vc[(long long)J0 * m1 + I0] + vc[(long long)J1 * m1 + I1]);
+}
+
+// Values of the field at the nodes of the mesh of twice the step.
+__global__ void k_inject(int nc, const double* __restrict__ u, double* __restrict__ out) {
+  const int m1 = nc / 2 + 1;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)m1 * m1) return;
+  const int I = int(t % m1), J = int(t / m1);
+  out[t] = u[(long long)(2 * J) * (nc + 1) + 2 * I];
+}
+
 __device__ __forceinline__ void atomic_max_abs(unsigned long long* p, double v) {
   atomicMax(p, (unsigned long long)__double_as_longlong(fabs(v)));
 }
@@ -816,6 +841,18 @@ hipError_t launch_fill(double* p, long long n, double v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   dim3 grid(std::max(1, std::min(ceil_div(n, 256), 65536))), block(256);
   hipLaunchKernelGGL(k_fill, grid, block, 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong(int nc, const double* vc, double* vf, hipStream_t st) {
+  const long long n = (long long)(nc + 1) * (nc + 1);
+  hipLaunchKernelGGL(k_prolong, dim3(ceil_div(n, 256)), dim3(256), 0, st, nc, vc, vf);
+  return hipGetLastError();
+}
+
+hipError_t launch_inject(int nc, const double* u, double* out, hipStream_t st) {
+  const long long n = (long long)(nc / 2 + 1) * (nc / 2 + 1);
+  hipLaunchKernelGGL(k_inject, dim3(ceil_div(n, 256)), dim3(256), 0, st, nc, u, out);
   return hipGetLastError();
 }
 

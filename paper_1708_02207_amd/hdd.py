@@ -33,7 +33,7 @@ HDD_FLAG_BLOCK8 = 4
 
 EXPORTED = [
     "hdd_default_opts", "hdd_workspace_size", "hdd_create", "hdd_build", "hdd_query_points",
-    "hdd_query_interface", "hdd_query_mean", "hdd_query_node_means", "hdd_loglik", "hdd_solve_full", "hdd_solve_rhs", "hdd_get_solution",
+    "hdd_query_interface", "hdd_query_mean", "hdd_query_node_means", "hdd_loglik", "hdd_solve_full", "hdd_solve_rhs", "hdd_solve_rhs_coarse", "hdd_get_solution_coarse", "hdd_get_solution",
     "hdd_error_estimate", "hdd_sync", "hdd_last_node", "hdd_destroy", "hdd_strerror",
     "hdd_plan_summary", "hdd_plan_node", "hdd_plan_level", "hdd_debug_node_schur",
     "hdd_timing_enable", "hdd_timing_get", "hdd_mfma_selftest", "hdd_debug_frame",
@@ -87,6 +87,8 @@ def _load() -> ctypes.CDLL:
         "hdd_query_mean": [P, P, P, i32],
         "hdd_query_node_means": [P, P, i32],
         "hdd_solve_rhs": [P, P, P, i32],
+        "hdd_solve_rhs_coarse": [P, P, P, i32],
+        "hdd_get_solution_coarse": [P, i32, P, i32],
         "hdd_loglik": [P, i32, P, P, dbl, i32, P, i32],
         "hdd_solve_full": [P],
         "hdd_get_solution": [P, i32, P, i32],
@@ -331,9 +333,10 @@ class HDD:
             _check(code, "hdd_solve_full")
         return code
 
-    def solve_rhs(self, f, g=None, check: bool = True) -> int:
+    def solve_rhs(self, f, g=None, check: bool = True, coarse: bool = False) -> int:
         """Field for another load f (and Dirichlet data g, nodal [N+2][N+2])
-        on the built operators; numpy arrays or CUDA tensors."""
+        on the built operators; numpy arrays or CUDA tensors.  coarse: f is
+        nodal on the mesh of twice the step, [Nc/2+1]^2."""
         if _is_torch_cuda(f):
             fp, mem = _ptr(f)
             gp = _ptr(g)[0] if g is not None else None
@@ -343,12 +346,20 @@ class HDD:
             if g is not None:
                 g = np.ascontiguousarray(g, dtype=np.float64)
             gp = _np_ptr(g) if g is not None else None
-        assert tuple(f.shape) == (self.nc + 1, self.nc + 1) and (g is None or tuple(g.shape) == tuple(f.shape))
+        fshape = (self.nc // 2 + 1,) * 2 if coarse else (self.nc + 1,) * 2
+        assert tuple(f.shape) == fshape and (g is None or tuple(g.shape) == (self.nc + 1, self.nc + 1))
         self._keep_rhs = (f, g)
-        code = _lib.hdd_solve_rhs(self.h, fp, gp, mem)
+        fn = _lib.hdd_solve_rhs_coarse if coarse else _lib.hdd_solve_rhs
+        code = fn(self.h, fp, gp, mem)
         if check:
-            _check(code, "hdd_solve_rhs")
+            _check(code, "hdd_solve_rhs_coarse" if coarse else "hdd_solve_rhs")
         return code
+
+    def solution_coarse(self, sample: int) -> np.ndarray:
+        m1 = self.nc // 2 + 1
+        u = np.zeros((m1, m1))
+        _check(_lib.hdd_get_solution_coarse(self.h, int(sample), _np_ptr(u), HDD_MEM_HOST), "hdd_get_solution_coarse")
+        return u
 
     def solution(self, sample: int) -> np.ndarray:
         u = np.zeros((self.nc + 1, self.nc + 1))

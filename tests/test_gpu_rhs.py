@@ -156,3 +156,28 @@ def test_rhs_1023(H, oracle_mod):
         e = rel(fields[1][s], fields[0][s])
         say(f"  sample {s}: float32 + refinement vs float64 {e:.2e}")
         assert e < TOL[1]
+
+
+@pytest.mark.parametrize("n,leaf,prec", [(3, 2, 0), (15, 4, 0), (63, 8, 0), (63, 8, 1), (255, 16, 1)])
+def test_rhs_coarse(H, oracle_mod, n, leaf, prec):
+    """Load on the mesh of twice the step (Section 3.5): the field equals the
+    oracle's for the prolonged load, and the solution on the coarse mesh is
+    the field at the coarse nodes."""
+    O = oracle_mod
+    say(f"coarse load n={n} leaf={leaf} precision={prec}")
+    kap = _kappa(n, 1, 70 + n)
+    m1 = (n + 1) // 2 + 1
+    xc = np.arange(m1) / (m1 - 1)
+    X, Y = np.meshgrid(xc, xc)
+    f_coarse = np.exp(-((X - 0.3) ** 2 + (Y - 0.7) ** 2) / (2 * 0.1 ** 2))
+    g = _boundary_data(n, 4)
+    o = H.hdd_default_opts(n, prec, leaf=leaf)
+    t = H.HDD(o, 1)
+    t.build(kap, rhs_nodal(n, "one"))
+    t.solve_rhs(f_coarse, g, coarse=True)
+    ref = O.solve_dirichlet(n, kap[0], O.prolong(m1 - 2, f_coarse), g)
+    e = rel(t.solution(0), ref)
+    ec = float(np.abs(t.solution_coarse(0) - ref[::2, ::2]).max() / np.abs(ref).max())
+    say(f"  field {e:.2e} coarse-mesh values {ec:.2e}")
+    assert max(e, ec) < TOL[prec]
+    t.close()
