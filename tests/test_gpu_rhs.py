@@ -181,3 +181,26 @@ def test_rhs_coarse(H, oracle_mod, n, leaf, prec):
     say(f"  field {e:.2e} coarse-mesh values {ec:.2e}")
     assert max(e, ec) < TOL[prec]
     t.close()
+
+
+def test_new_entry_points_errors(H):
+    """Calls out of order and bad inputs return their codes and leave the
+    handle usable."""
+    n, leaf = 15, 4
+    o = H.hdd_default_opts(n, H.HDD_FP64, leaf=leaf)
+    t = H.HDD(o, 1)
+    f = rhs_nodal(n, "bump")
+    assert t.solve_rhs(f, check=False) == H.HDD_ESTATE
+    nodes = H.hdd_plan_summary(o)["nodes"]
+    res = np.zeros((1, nodes))
+    assert H._lib.hdd_query_node_means(t.h, H._np_ptr(res), H.HDD_MEM_HOST) == H.HDD_ESTATE
+    kap = _kappa(n, 1, 3)
+    t.build(kap, f)
+    u = np.zeros((n // 2 + 2, n // 2 + 2))
+    assert H._lib.hdd_get_solution_coarse(t.h, 0, H._np_ptr(u), H.HDD_MEM_HOST) == H.HDD_ESTATE  # no full field yet
+    bad = f.copy()
+    bad[3, 4] = np.nan
+    assert t.solve_rhs(bad, check=False) == H.HDD_EINVAL
+    assert H._lib.hdd_get_solution_coarse(t.h, 1, H._np_ptr(u), H.HDD_MEM_HOST) == H.HDD_EINVAL  # sample out of range
+    t.solve_rhs(f)
+    t.close()
