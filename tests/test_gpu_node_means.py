@@ -134,16 +134,16 @@ def test_node_means_device_output_and_rebuild(H, oracle_mod):
 
 
 def test_node_means_1023_functional(H):
-    """1023^2, 32 x 32-cell leaves, the four samples with stored oracle
-    values: the functional route in float64 (8191 nodes per sample).  The
-    node [0.25, 0.5]^2 (depth 4) matches the oracle's stored mean; every
-    father's mean is the area-weighted average of its sons' (a property at any
-    size); the root and depth-1 means agree with the float32 + refinement path
-    (direct route) to 1e-8."""
+    """1023^2, 32 x 32-cell leaves, the benchmark's batch of 32 samples: the
+    functional route in float64 (8191 nodes per sample).  For the samples
+    with stored oracle values the node [0.25, 0.5]^2 (depth 4) matches the
+    oracle's stored mean; for all samples every father's mean is the
+    area-weighted average of its sons' (a property at any size), and all
+    means agree with the float32 + refinement path (direct route) to 1e-8."""
     with open(os.path.join(HERE, "golden", "c2_1023.json")) as fh:
         g = json.load(fh)
-    w = make_workload("c2_1023")
-    ns = len(g["samples"])
+    ns = 32
+    w = make_workload("c2_1023", n_samples=ns)
     say("node means 1023^2 fp64 functional, samples", ns)
     kd = torch.from_numpy(w.kappa[:ns]).cuda()
     fd = torch.from_numpy(w.f).cuda()
@@ -173,12 +173,8 @@ def test_node_means_1023_functional(H):
         e = rel([got[s["sample"], idx]], [s["mean"]])
         say(f"  sample {s['sample']}: node {idx} (depth {d}) vs stored oracle mean {e:.2e}")
         assert e < TOL[0]
-    # sons average to the father at every node
+    # sons (halves of their father) average to the father at every node
     nodes = got.shape[1]
-    area = np.empty(nodes)
-    area[0] = 1.0
-    for p in range((nodes - 1) // 2):
-        area[2 * p + 1] = area[2 * p + 2] = area[p] / 2
     for p in range((nodes - 1) // 2):
         fa = got[:, p]
         av = (got[:, 2 * p + 1] + got[:, 2 * p + 2]) / 2

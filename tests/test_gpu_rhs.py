@@ -128,13 +128,14 @@ def test_rhs_device_inputs(H, oracle_mod):
 
 
 def test_rhs_1023(H, oracle_mod):
-    """1023^2, 32 x 32-cell leaves, two samples of the workload: the float64
-    field for a bump load with boundary data is certified by its
-    extended-precision residual (computed with the oracle's lifted load), and
-    the float32 + refinement field agrees with it to 1e-8 on every node."""
+    """1023^2, 32 x 32-cell leaves, the benchmark's batch of 32 samples: the
+    float64 field of sample 0 for a bump load with boundary data is certified
+    by its extended-precision residual (computed with the oracle's lifted
+    load), and for every sample the float32 + refinement field agrees with the
+    float64 field to 1e-8 on every node."""
     O = oracle_mod
-    w = make_workload("c2_1023")
-    ns = 2
+    ns = 32
+    w = make_workload("c2_1023", n_samples=ns)
     f = rhs_nodal(w.n, "bump")
     g = _boundary_data(w.n, 9)
     kd = torch.from_numpy(w.kappa[:ns]).cuda()
@@ -147,15 +148,15 @@ def test_rhs_1023(H, oracle_mod):
         t.solve_rhs(f, g)
         fields[prec] = [t.solution(s) for s in range(ns)]
         t.close()
+        torch.cuda.empty_cache()
     fl = O.lifted_load(w.n, w.kappa[0], f, g)
     r = O.residual(w.n, w.kappa[0], fl, fields[0][0])
     bound = O.error_bound_l2(w.n, w.kappa[0], r)
     say(f"  float64 residual error bound (l2) {bound:.2e}, field norm {np.linalg.norm(fields[0][0]):.2e}")
     assert bound <= 1e-8 * np.linalg.norm(fields[0][0])
-    for s in range(ns):
-        e = rel(fields[1][s], fields[0][s])
-        say(f"  sample {s}: float32 + refinement vs float64 {e:.2e}")
-        assert e < TOL[1]
+    worst = max(rel(fields[1][s], fields[0][s]) for s in range(ns))
+    say(f"  float32 + refinement vs float64, worst over {ns} samples: {worst:.2e}")
+    assert worst < TOL[1]
 
 
 @pytest.mark.parametrize("n,leaf,prec", [(3, 2, 0), (15, 4, 0), (63, 8, 0), (63, 8, 1), (255, 16, 1)])
