@@ -182,7 +182,7 @@ def main():
         t.build(kd, fd)
         t.loglik(w.points, yd, w.sigma_y, False, out=ll)
         t.query_points(w.points, out=pts)
-        H._check(H._lib.hdd_query_interface(t.h, H.ctypes.c_void_p(iface.data_ptr()), None, H.HDD_MEM_DEVICE),
+        H._check(H._lib.hdd_query_interface(t.h, 0, 0, H.ctypes.c_void_p(iface.data_ptr()), None, H.HDD_MEM_DEVICE),
                  "hdd_query_interface")
         H._check(H._lib.hdd_query_mean(t.h, H._np_ptr(rect), H.ctypes.c_void_p(mean.data_ptr()), H.HDD_MEM_DEVICE),
                  "hdd_query_mean")
@@ -311,7 +311,7 @@ def main():
                     c.solve_full()
                 c.loglik(w.points, yd, w.sigma_y, False, out=ll)
                 c.query_points(w.points, out=pts)
-                H._check(H._lib.hdd_query_interface(c.h, H.ctypes.c_void_p(iface.data_ptr()), None,
+                H._check(H._lib.hdd_query_interface(c.h, 0, 0, H.ctypes.c_void_p(iface.data_ptr()), None,
                                                     H.HDD_MEM_DEVICE), "hdd_query_interface")
                 H._check(H._lib.hdd_query_mean(c.h, H._np_ptr(rect), H.ctypes.c_void_p(mean.data_ptr()),
                                                H.HDD_MEM_DEVICE), "hdd_query_mean")

@@ -42,6 +42,9 @@
 extern "C" {
 #endif
 
+/* largest total number of sites of one ragged query (all samples together) */
+#define HDD_MAX_QUERY_POINTS 4096
+
 /* status codes */
 #define HDD_OK 0
 #define HDD_EINVAL (-1)         /* bad argument, shape or non-positive/non-finite kappa */
@@ -129,10 +132,32 @@ int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double
 int hdd_query_points(hdd_handle h, int32_t n_pts, const double* xy, double* u_out, int32_t mem);
 
 /*
- * u on the root interface gamma_Omega, the vertical midline x = 1/2
- * (setup (a) of Fig. HDDidea): u_out (mem) float64 [n_samples][N], *len = N.
+ * u on the interface gamma_omega of one tree node (eq. gamma_def: the cut
+ * that splits omega into its two sons, without the cut's two end points;
+ * Section 2.1), for every built sample.  The node is (depth, index) as in
+ * hdd_plan_node, 0 <= depth <= the depth of the blocks; (0, 0) is the root,
+ * whose gamma is the vertical midline x = 1/2 (setup (a) of Fig. HDDidea).
+ *   u_out (mem) float64 [n_samples][|gamma|], entry k at the global node
+ *         ids[k] of hdd_plan_node (nodes along the cut, increasing
+ *         coordinate); *len (may be NULL) = |gamma|.
+ * Without the full field (HDD_FP64 with max_refine = 0, before
+ * hdd_solve_full) only the interfaces on the path root -> node are solved
+ * (Root to Leaves restricted to that path, Section 5.3).  Errors: HDD_EINVAL
+ * (no such node), HDD_ESTATE before a build.
  */
-int hdd_query_interface(hdd_handle h, double* u_out, int32_t* len, int32_t mem);
+int hdd_query_interface(hdd_handle h, int32_t depth, int32_t index, double* u_out, int32_t* len, int32_t mem);
+
+/*
+ * Status of every built sample of the batch (host int32 [n_samples]):
+ * HDD_EINVAL (its kappa was non-positive or non-finite), HDD_ENOTSPD (an
+ * interface factorization of this sample met a non-positive pivot; its
+ * values are not usable), HDD_ENOTCONVERGED (its refinement did not reach
+ * refine_tol in max_refine sweeps; values still usable), else HDD_OK.
+ * Samples are independent: one sample's status never changes another's
+ * values.  The calls above return the first non-OK code of the batch.
+ * Synchronizes.  Errors: HDD_ESTATE before a build.
+ */
+int hdd_sample_status(hdd_handle h, int32_t* status);
 
 /*
  * Mean of u over the cell-aligned rectangle rect = {x0, x1, y0, y1} (eq. mean;
@@ -176,7 +201,7 @@ int hdd_loglik(hdd_handle h, int32_t n_y, const double* xy, const double* y, dou
  * Sample-specific observation sites (each sample of the batch has its own
  * points, e.g. independent requests batched together).  Sample s owns points
  * offsets[s] .. offsets[s+1]-1 of xy; offsets: host int32 [n_samples+1] with
- * offsets[0] = 0, non-decreasing, total at most 4096.
+ * offsets[0] = 0, non-decreasing, total at most HDD_MAX_QUERY_POINTS.
  * hdd_query_points_ragged: u_out (mem) float64 [offsets[n_samples]], the P1
  *   interpolated values in the order of xy.
  * hdd_loglik_ragged: out (mem) float64 [n_samples], sample s's Gaussian
@@ -236,7 +261,9 @@ int hdd_get_solution(hdd_handle h, int32_t sample, double* u_out, int32_t mem);
 
 /* Last refinement correction max|du| / max|u| per sample (0 if none ran); it
  * bounds the error left after the sweep before it:
- * rel_est host float64 [n_samples]; *sweeps = refinement sweeps done. */
+ * rel_est host float64 [n_samples]; *sweeps = the most sweeps any sample
+ * ran.  Each sample stops refining on its own once its predicted error is
+ * below refine_tol (later corrections of the batch are not applied to it). */
 int hdd_error_estimate(hdd_handle h, double* rel_est, int32_t* sweeps);
 
 /* Wait for the handle's stream and report deferred device-side errors. */
@@ -318,8 +345,9 @@ int hdd_mfma_selftest(int32_t dtype, double* out);
  * one parameter sample (kappa of its mesh), its observation sites and
  * optional observations; the answer is the P1 values at the sites and the
  * unnormalized Gaussian log-likelihood (0 without observations).  Requests
- * queue per mesh; a free mesh takes all waiting requests up to its slot
- * count as one batch (Leaves to Root, then hdd_query_points_ragged and
+ * queue per mesh; a free mesh takes the waiting requests in order, up to
+ * its slot count and HDD_MAX_QUERY_POINTS sites in total, as one batch
+ * (Leaves to Root, then hdd_query_points_ragged and
  * hdd_loglik_ragged), so requests arriving while others run are admitted as
  * soon as a slot frees up, and batches of different meshes overlap on the
  * GPU.  Device workspaces for full batches are allocated at creation: slots
@@ -338,7 +366,8 @@ typedef struct {
   int32_t precision;                     /* HDD_FP64 or HDD_FP32_REFINE */
   int32_t slots;                         /* samples per batch per mesh (0: 32) */
   double hbm_budget;                     /* bytes for all device workspaces (0: no limit) */
-  int32_t reserved[8];                   /* must be zero */
+  int32_t max_refine;                    /* refinement sweeps allowed per batch (0: the default of hdd_default_opts) */
+  int32_t reserved[7];                   /* must be zero */
 } hdd_server_opts;
 
 /* f: per mesh host float64 [(n+2)^2] nodal right-hand side copied at
@@ -357,7 +386,9 @@ int hdd_server_poll(hdd_server_t s, int64_t id, int32_t* done);
 /* Wait for a request, copy its values (host float64 [n_pts]) and
  * log-likelihood, and release it.  times (host float64 [4], may be NULL):
  * queue wait, batch time, submit-to-done seconds, and the batch size.
- * Returns the batch's status code. */
+ * Returns the request's own status: its sample's code from
+ * hdd_sample_status (HDD_ENOTCONVERGED: values and log-likelihood still
+ * delivered), or the batch's code when the batch failed as a whole. */
 int hdd_server_result(hdd_server_t s, int64_t id, double* values, double* loglik, double* times);
 /* out int64 [4]: submitted, completed, batches run, queued now. */
 int hdd_server_stats(hdd_server_t s, int64_t* out);

@@ -13,6 +13,7 @@ Contents
   residual(n, kappa, f, u)       b - A u in extended precision (oracle.c)
   point_values / interface / mean / loglik    the measurement operators
   tree_rects / node_means        subdomains of the tree and their means
+  node_interface                 u on the interface gamma of one tree node
   element_matrix_dense(...)      independent element-loop assembly (dense)
   subdomain_schur(...)           brute-force dense Schur complement of one
                                  subdomain's own matrix (Section 2.4)
@@ -256,6 +257,23 @@ def tree_rects(n: int, block: int) -> list:
         level = nxt
         out += level
     return out
+
+
+def node_interface(n: int, u_full: np.ndarray, block: int, k: int):
+    """(ids, values) of u on the interface gamma of tree node k (order of
+    tree_rects): the cut that splits the node's rectangle into its two sons
+    without the cut's two end points (eq. gamma_def, Section 2.1), nodes in
+    increasing coordinate along the cut; ids are j (Nc + 1) + i."""
+    nc = n + 1
+    i0, i1, j0, j1 = tree_rects(n, block)[k]
+    if i1 - i0 >= j1 - j0:
+        m = (i0 + i1) // 2
+        nodes = [(m, j) for j in range(j0 + 1, j1)]
+    else:
+        m = (j0 + j1) // 2
+        nodes = [(i, m) for i in range(i0 + 1, i1)]
+    ids = np.array([j * (nc + 1) + i for i, j in nodes], dtype=np.int64)
+    return ids, np.array([u_full[j, i] for i, j in nodes])
 
 
 def node_means(n: int, u_full: np.ndarray, block: int, nodes=None) -> np.ndarray:

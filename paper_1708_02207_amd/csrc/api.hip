@@ -76,7 +76,7 @@ bool make_plan(const hdd_opts& o, Plan& p) {
 // Byte offsets of everything the handle keeps in its device workspace.
 struct Layout {
   std::vector<int64_t> frames, nodes, maps, ids, vec, panel;
-  int64_t kappa, f, u, d, r, info, bad, maxbits, qout, qxy, qy, qsmp, qoff, qsig, lists, iota;
+  int64_t kappa, f, u, d, r, info, bad, act, maxbits, qout, qxy, qy, qsmp, qoff, qsig, lists, iota;
   int64_t cst, bvec, tmaps, tlids, tmicro, origin, text;
   int64_t wts, mu, nmean;  // node means: weight vector, subtree functionals, output staging
   int64_t max_q;
@@ -119,6 +119,7 @@ Layout make_layout(const Plan& p, const hdd_opts& o, int ms) {
   L.r = take(int64_t(ms) * nn * 8);
   L.info = take(int64_t(ms) * 4);
   L.bad = take(int64_t(ms) * 4);
+  L.act = take(int64_t(ms) * 4);
   L.maxbits = take(int64_t(ms) * 16);
   L.qout = take((int64_t(ms) + 1) * L.max_q * 8);
   L.qxy = take(L.max_q * 16);
@@ -170,12 +171,18 @@ struct hdd_tree {
   double *wts = nullptr, *mu = nullptr, *nmean = nullptr;
   long long total_nodes = 0;
   bool wts_ready = false;
-  int* pinned_lists = nullptr;
-  hipEvent_t lists_done = nullptr;
+  int* pinned_lists = nullptr;       // host staging of the node lists (pinned, or lists_host)
+  hipEvent_t lists_done = nullptr;   // the last list upload has completed (null: synchronize instead)
+  std::vector<int> lists_host;       // pageable staging when the handle may not allocate
+  bool no_alloc = false;             // no device, pinned or event allocation after creation
   bool built = false, full = false;
   std::vector<std::vector<uint8_t>> solved;
   std::vector<double> est;
-  int sweeps = 0;
+  int sweeps = 0;                 // most sweeps any sample ran
+  std::vector<int> sweeps_s;      // sweeps per sample
+  std::vector<int> sstat;         // per-sample refinement status (HDD_OK / HDD_ENOTCONVERGED)
+  std::vector<int> act_host;      // samples still refining
+  int* act = nullptr;             // device copy of act_host
   int last_node = 0;
   int deferred = HDD_OK;
   // timing
@@ -253,6 +260,14 @@ double syrk_bytes(const hdd_tree* h, int d, int k0, int k1, int r0, int c0, int 
   return tot * esz * h->n_samples;
 }
 
+void reset_refine_state(hdd_tree* h) {
+  const int ns = h->n_samples;
+  h->sweeps = 0;
+  h->est.assign(ns, 0.0);
+  h->sweeps_s.assign(ns, 0);
+  h->sstat.assign(ns, HDD_OK);
+}
+
 int check_deferred(hdd_tree* h) {
   HIP_TRY(hipStreamSynchronize(h->st));
   if (!h->built) return h->deferred;
@@ -293,18 +308,21 @@ int full_topdown(hdd_tree* h, double* target, bool from_vec) {
 
 // Up to max_it correction sweeps u += d, with d from the bottom-up
 // elimination of the residual r = b - A u (forward pass) and a full top-down
-// on it, stopped by the predicted-error test below.  With u holding only
-// boundary data the first sweep is the solve itself.  With `test` false the
-// sweeps never report non-convergence (a single solve sweep has nothing to
-// compare with).
+// on it, stopped per sample by the predicted-error test below.  With u
+// holding only boundary data the first sweep is the solve itself.  A sample
+// that has passed the test keeps its field (its later corrections are
+// computed but not applied), so its result does not depend on the other
+// samples of the batch.  With `test` false the sweeps never report
+// non-convergence (a single solve sweep has nothing to compare with).
 int correction_sweeps(hdd_tree* h, int max_it, bool test) {
   const int D = int(h->lev.size()) - 1;
   const int nc = h->plan.nc;
   const int ns = h->n_samples;
   std::vector<unsigned long long> mb(2 * ns);
   std::vector<double> prev(ns, 0.0);
-  bool converged = false;
-  for (int it = 0; it < max_it; ++it) {
+  h->act_host.assign(ns, 1);
+  int n_active = ns;
+  for (int it = 0; it < max_it && n_active > 0; ++it) {
     h->cur_level = -1;
     HDD_TRY(timed(h, K_RESIDUAL, 0.0, [&] { return hdd::launch_residual(nc, ns, h->kappa, h->f, h->u, h->r, h->st); }));
     h->cur_level = D;
@@ -315,8 +333,10 @@ int correction_sweeps(hdd_tree* h, int max_it, bool test) {
     }
     HIP_TRY(hdd::launch_fill(h->d, (long long)ns * h->nn, 0.0, h->st));
     HDD_TRY(full_topdown(h, h->d, true));
-    HIP_TRY(hipMemsetAsync(h->maxbits, 0, sizeof(unsigned long long) * 2 * ns, h->st));
-    HIP_TRY(hdd::launch_axpy_maxabs(nc, ns, h->u, h->d, h->maxbits, h->st));
+    // all-zero bits are +0.0: the fill kernel clears the max-norm words
+    HIP_TRY(hdd::launch_fill(reinterpret_cast<double*>(h->maxbits), 2LL * ns, 0.0, h->st));
+    HIP_TRY(hipMemcpyAsync(h->act, h->act_host.data(), sizeof(int) * ns, hipMemcpyHostToDevice, h->st));
+    HIP_TRY(hdd::launch_axpy_maxabs(nc, ns, h->u, h->d, h->maxbits, h->act, h->st));
     HIP_TRY(hipMemcpyAsync(mb.data(), h->maxbits, sizeof(unsigned long long) * 2 * ns, hipMemcpyDeviceToHost, h->st));
     HIP_TRY(hipStreamSynchronize(h->st));
     h->sweeps = it + 1;
@@ -325,8 +345,8 @@ int correction_sweeps(hdd_tree* h, int max_it, bool test) {
     // left after a correction of size c is at most c r / (1 - r); r is the
     // observed ratio of the last two corrections.  A sample whose ratio is
     // not below 1/2 (or that has only one correction) does not stop.
-    double worst = 0.0;
     for (int s = 0; s < ns; ++s) {
+      if (!h->act_host[s]) continue;
       double md, mu;
       std::memcpy(&md, &mb[2 * s], 8);
       std::memcpy(&mu, &mb[2 * s + 1], 8);
@@ -339,15 +359,20 @@ int correction_sweeps(hdd_tree* h, int max_it, bool test) {
         if (r < 0.5) pred = c * r / (1.0 - r);
       }
       h->est[s] = c;
+      h->sweeps_s[s] = it + 1;
       prev[s] = c;
-      worst = std::max(worst, pred);
-    }
-    if (worst <= h->opt.refine_tol) {
-      converged = true;
-      break;
+      if (pred <= h->opt.refine_tol) {
+        h->act_host[s] = 0;
+        --n_active;
+      }
     }
   }
-  if (!converged && test) h->deferred = HDD_ENOTCONVERGED;
+  if (test)
+    for (int s = 0; s < ns; ++s)
+      if (h->act_host[s]) {
+        h->sstat[s] = HDD_ENOTCONVERGED;
+        h->deferred = HDD_ENOTCONVERGED;
+      }
   return HDD_OK;
 }
 
@@ -356,15 +381,15 @@ int ensure_full(hdd_tree* h) {
   HDD_TRY(full_topdown(h, h->u, false));
   for (auto& v : h->solved) std::fill(v.begin(), v.end(), 1);
   h->full = true;
-  h->sweeps = 0;
-  std::fill(h->est.begin(), h->est.end(), 0.0);
+  reset_refine_state(h);
   if (h->opt.max_refine <= 0) return HDD_OK;
   return correction_sweeps(h, h->opt.max_refine, true);
 }
 
 // Solve, root first, the nodes marked in `need` that are not solved yet.
 int partial_topdown(hdd_tree* h, const std::vector<std::vector<uint8_t>>& need) {
-  HIP_TRY(hipEventSynchronize(h->lists_done));
+  if (h->lists_done) HIP_TRY(hipEventSynchronize(h->lists_done));
+  else HIP_TRY(hipStreamSynchronize(h->st));
   int64_t total = 0;
   std::vector<int> counts(h->lev.size(), 0);
   for (size_t d = 0; d < h->lev.size(); ++d) {
@@ -378,7 +403,7 @@ int partial_topdown(hdd_tree* h, const std::vector<std::vector<uint8_t>>& need) 
   if (total == 0) return HDD_OK;
   HIP_TRY(hipMemcpyAsync(h->lists, h->pinned_lists, sizeof(int) * (h->lev_list_off.back() + h->lev.back().n_nodes),
                          hipMemcpyHostToDevice, h->st));
-  HIP_TRY(hipEventRecord(h->lists_done, h->st));
+  if (h->lists_done) HIP_TRY(hipEventRecord(h->lists_done, h->st));
   const size_t DB = h->lev.size() - 1;
   for (size_t d = 0; d < h->lev.size(); ++d) {
     if (!counts[d]) continue;
@@ -429,8 +454,7 @@ int solve_loaded_rhs(hdd_tree* h, const double* g, int mem) {
   HIP_TRY(hdd::launch_lift_init(h->plan.nc, h->n_samples, g ? h->r : nullptr, h->u, h->st));
   for (auto& v : h->solved) std::fill(v.begin(), v.end(), 1);
   h->full = true;
-  h->sweeps = 0;
-  std::fill(h->est.begin(), h->est.end(), 0.0);
+  reset_refine_state(h);
   const int refine = std::max(0, h->opt.max_refine);
   HDD_TRY(correction_sweeps(h, 1 + refine, refine > 0));
   return check_deferred(h);
@@ -470,9 +494,17 @@ int hdd_workspace_size(const hdd_opts* o, int32_t max_samples, size_t* bytes) {
   return HDD_OK;
 }
 
-int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* workspace, size_t workspace_bytes,
-               hdd_handle* out) {
+}  // extern "C"
+
+namespace {
+
+// hdd_create; with no_alloc the handle takes a caller workspace and a stream
+// (null: the null stream) and makes no device, pinned-host or event
+// allocation, now or later (node lists are staged in pageable memory).
+int create_impl(const hdd_opts* o, int32_t max_samples, void* stream, void* workspace, size_t workspace_bytes,
+                bool no_alloc, hdd_handle* out) {
   HDD_TRY(validate_opts(o));
+  if (no_alloc && !workspace) return HDD_EINVAL;
   if (max_samples < 1 || !out) return HDD_EINVAL;
   hdd_tree* h = new (std::nothrow) hdd_tree();
   if (!h) return HDD_ENOMEM;
@@ -488,7 +520,8 @@ int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* works
     return code;
   };
   if (hipGetDevice(&h->device) != hipSuccess) return fail(HDD_EDEVICE);
-  if (stream) {
+  h->no_alloc = no_alloc;
+  if (stream || no_alloc) {
     h->st = static_cast<hipStream_t>(stream);
   } else {
     if (hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking) != hipSuccess) return fail(HDD_EDEVICE);
@@ -613,6 +646,7 @@ int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* works
   h->r = L.r >= 0 ? reinterpret_cast<double*>(h->ws + L.r) : nullptr;
   h->info = reinterpret_cast<int*>(h->ws + L.info);
   h->bad = reinterpret_cast<int*>(h->ws + L.bad);
+  h->act = reinterpret_cast<int*>(h->ws + L.act);
   h->maxbits = reinterpret_cast<unsigned long long*>(h->ws + L.maxbits);
   h->qout = reinterpret_cast<double*>(h->ws + L.qout);
   h->qxy = reinterpret_cast<double*>(h->ws + L.qxy);
@@ -627,7 +661,10 @@ int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* works
   h->nmean = reinterpret_cast<double*>(h->ws + L.nmean);
   h->total_nodes = 0;
   for (auto& lv : h->lev) h->total_nodes += lv.n_nodes;
-  if (hipHostMalloc(&h->pinned_lists, sizeof(int) * size_t(std::max<int64_t>(list_off, 1))) != hipSuccess) {
+  if (no_alloc) {
+    h->lists_host.assign(size_t(std::max<int64_t>(list_off, 1)), 0);
+    h->pinned_lists = h->lists_host.data();
+  } else if (hipHostMalloc(&h->pinned_lists, sizeof(int) * size_t(std::max<int64_t>(list_off, 1))) != hipSuccess) {
     h->pinned_lists = nullptr;
     return fail(HDD_ENOMEM);
   }
@@ -638,13 +675,31 @@ int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* works
     for (int64_t k = 0; k < mx; ++k) io[k] = int(k);
     if (hipMemcpy(h->iota, io.data(), io.size() * 4, hipMemcpyHostToDevice) != hipSuccess) return fail(HDD_EDEVICE);
   }
-  if (hipEventCreateWithFlags(&h->lists_done, hipEventDisableTiming) != hipSuccess) {
-    h->lists_done = nullptr;
-    return fail(HDD_EDEVICE);
+  if (!no_alloc) {
+    if (hipEventCreateWithFlags(&h->lists_done, hipEventDisableTiming) != hipSuccess) {
+      h->lists_done = nullptr;
+      return fail(HDD_EDEVICE);
+    }
+    if (hipEventRecord(h->lists_done, h->st) != hipSuccess) return fail(HDD_EDEVICE);
   }
-  if (hipEventRecord(h->lists_done, h->st) != hipSuccess) return fail(HDD_EDEVICE);
   *out = h;
   return HDD_OK;
+}
+
+}  // namespace
+
+namespace hdd {
+int create_handle(const hdd_opts* o, int32_t max_samples, void* stream, void* workspace, size_t workspace_bytes,
+                  bool no_alloc, hdd_handle* out) {
+  return create_impl(o, max_samples, stream, workspace, workspace_bytes, no_alloc, out);
+}
+}  // namespace hdd
+
+extern "C" {
+
+int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* workspace, size_t workspace_bytes,
+               hdd_handle* out) {
+  return create_impl(o, max_samples, stream, workspace, workspace_bytes, false, out);
 }
 
 int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double* f, const double* g, int32_t mem) {
@@ -667,11 +722,10 @@ int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double
   h->full = false;
   h->deferred = HDD_OK;
   h->last_node = 0;
-  h->est.assign(n_samples, 0.0);
-  h->sweeps = 0;
+  reset_refine_state(h);
   for (auto& v : h->solved) std::fill(v.begin(), v.end(), 0);
-  HIP_TRY(hipMemsetAsync(h->info, 0, sizeof(int) * n_samples, h->st));
-  HIP_TRY(hipMemsetAsync(h->bad, 0, sizeof(int) * n_samples, h->st));
+  HIP_TRY(hdd::launch_fill_i32(h->info, n_samples, 0, h->st));
+  HIP_TRY(hdd::launch_fill_i32(h->bad, n_samples, 0, h->st));
   const int D = int(h->lev.size()) - 1;
   const bool mfma = !(h->opt.flags & HDD_FLAG_NO_MFMA);
   auto eliminate = [&](int d) -> int {
@@ -804,18 +858,37 @@ int hdd_loglik_ragged(hdd_handle h, const int32_t* offsets, const double* xy, co
   return copy_out(h, out, dst, size_t(ns), HDD_MEM_HOST);
 }
 
-int hdd_query_interface(hdd_handle h, double* u_out, int32_t* len, int32_t mem) {
-  if (!h || !u_out) return HDD_EINVAL;
+int hdd_query_interface(hdd_handle h, int32_t depth, int32_t index, double* u_out, int32_t* len, int32_t mem) {
+  if (!h || !u_out || (mem != HDD_MEM_HOST && mem != HDD_MEM_DEVICE)) return HDD_EINVAL;
   if (!h->built) return HDD_ESTATE;
+  if (depth < 0 || depth >= int(h->lev.size()) || index < 0 || index >= h->lev[depth].n_nodes) return HDD_EINVAL;
+  const auto& nd = h->plan.levels[depth].nodes[index];
+  // the path root -> node: the node's gamma is solved once its ancestors'
+  // interfaces (its boundary data) are known
   auto need = empty_need(h);
-  need[0][0] = 1;
+  int k = index;
+  for (int d = depth; d >= 0; --d, k >>= 1) need[d][k] = 1;
   HDD_TRY(prepare_values(h, need));
-  const int n = h->plan.nc - 1;
-  if (len) *len = n;
+  const int g = int(nd.gam.size());
+  if (len) *len = g;
   double* dst = mem == HDD_MEM_DEVICE ? u_out : h->qout;
-  HIP_TRY(hdd::launch_interface(h->plan.nc, h->n_samples, h->u, dst, h->st));
+  const int* ids = h->lev[depth].ids + nd.ids_off;  // [gamma ; Gamma] global ids, gamma first
+  HIP_TRY(hdd::launch_gather(g, h->n_samples, ids, h->u, h->nn, dst, h->st));
   if (mem == HDD_MEM_DEVICE) return HDD_OK;
-  return copy_out(h, u_out, h->qout, size_t(n) * h->n_samples, HDD_MEM_HOST);
+  return copy_out(h, u_out, h->qout, size_t(g) * h->n_samples, HDD_MEM_HOST);
+}
+
+int hdd_sample_status(hdd_handle h, int32_t* status) {
+  if (!h || !status) return HDD_EINVAL;
+  if (!h->built) return HDD_ESTATE;
+  HIP_TRY(hipStreamSynchronize(h->st));
+  const int ns = h->n_samples;
+  std::vector<int> info(ns), bad(ns);
+  HIP_TRY(hipMemcpy(info.data(), h->info, sizeof(int) * ns, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(bad.data(), h->bad, sizeof(int) * ns, hipMemcpyDeviceToHost));
+  for (int s = 0; s < ns; ++s)
+    status[s] = bad[s] ? HDD_EINVAL : info[s] ? HDD_ENOTSPD : h->sstat.empty() ? HDD_OK : h->sstat[s];
+  return HDD_OK;
 }
 
 int hdd_query_mean(hdd_handle h, const double rect[4], double* out, int32_t mem) {
@@ -989,7 +1062,7 @@ int hdd_destroy(hdd_handle h) {
   if (h->st) (void)hipStreamSynchronize(h->st);
   for (auto e : h->ev_pool) (void)hipEventDestroy(e);
   if (h->lists_done) (void)hipEventDestroy(h->lists_done);
-  if (h->pinned_lists) (void)hipHostFree(h->pinned_lists);
+  if (h->pinned_lists && !h->no_alloc) (void)hipHostFree(h->pinned_lists);
   if (h->own_ws && h->ws) (void)hipFree(h->ws);
   if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
   delete h;

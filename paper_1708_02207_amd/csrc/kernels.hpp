@@ -4,8 +4,15 @@
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
+#include "hdd.h"
 
 namespace hdd {
+
+// hdd_create with an extra mode: no_alloc takes the caller's workspace and
+// stream (null: the null stream) and makes no device, pinned-host or event
+// allocation, at creation or later.
+int create_handle(const hdd_opts* o, int32_t max_samples, void* stream, void* workspace, size_t workspace_bytes,
+                  bool no_alloc, hdd_handle* out);
 
 constexpr int kPanelNB = 32;  // panel width of the interface factorization
 
@@ -42,16 +49,18 @@ hipError_t launch_forward(const DevLevel& L, const DevLevel& child, int n_sample
 
 // Full-field and readout kernels (FP64)
 hipError_t launch_fill(double* p, long long n, double v, hipStream_t st);
+hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st);
 hipError_t launch_prolong(int nc, const double* vc, double* vf, hipStream_t st);
 hipError_t launch_inject(int nc, const double* u, double* out, hipStream_t st);
 hipError_t launch_lift_init(int nc, int n_samples, const double* g, double* u, hipStream_t st);
 hipError_t launch_residual(int nc, int n_samples, const double* kappa, const double* f, const double* u,
                            double* r, hipStream_t st);
 hipError_t launch_axpy_maxabs(int nc, int n_samples, double* u, const double* d, unsigned long long* maxbits,
-                              hipStream_t st);
+                              const int* active, hipStream_t st);
 hipError_t launch_points(int nc, int n_samples, int n_pts, const double* xy, const double* u, double* out,
                          hipStream_t st);
-hipError_t launch_interface(int nc, int n_samples, const double* u, double* out, hipStream_t st);
+hipError_t launch_gather(int n_ids, int n_samples, const int* ids, const double* u, long long ustride, double* out,
+                         hipStream_t st);
 hipError_t launch_mean(int nc, int n_samples, int i0, int i1, int j0, int j1, const double* u, double* out,
                        hipStream_t st);
 hipError_t launch_points_ragged(int nc, int n_total, const double* xy, const int* smp, const double* u, double* out,

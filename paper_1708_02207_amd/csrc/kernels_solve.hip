@@ -463,6 +463,11 @@ __global__ void k_fill(double* p, long long n, double v) {
     p[i] = v;
 }
 
+__global__ void k_fill_i32(int* p, long long n, int v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
 // Residual r = b - A u at every interior node, FP64, assembled on the fly
 // from the six triangles around the node with the element matrices of
 // eq. coefA and the vertex-rule load of eq. coefc.  Zero on the boundary.
@@ -556,12 +561,16 @@ __device__ __forceinline__ void atomic_max_abs(unsigned long long* p, double v) 
 // u += d and per-sample max |d|, max |u| (as ordered bit patterns of
 // non-negative doubles, so the maximum is exact and order independent).
 // One atomic per workgroup and quantity: the waves reduce through LDS first.
+// Samples with active[s] == 0 (a sample whose refinement has stopped) keep
+// their field; active == nullptr updates every sample.
 __global__ void __launch_bounds__(256) k_axpy_maxabs(int nc, int n_samples, double* __restrict__ u,
                                                      const double* __restrict__ d,
-                                                     unsigned long long* __restrict__ maxbits) {
+                                                     unsigned long long* __restrict__ maxbits,
+                                                     const int* __restrict__ active) {
   __shared__ double red[2][4];
   const long long nn = (long long)(nc + 1) * (nc + 1);
   const int s = blockIdx.y;
+  if (active && !active[s]) return;  // uniform over the workgroup
   double* us = u + (long long)s * nn;
   const double* ds = d + (long long)s * nn;
   double md = 0.0, mu = 0.0;
@@ -631,12 +640,13 @@ __global__ void k_points_ragged(int nc, int n_total, const double* __restrict__ 
   out[t] = v;
 }
 
-__global__ void k_interface(int nc, int n_samples, const double* __restrict__ u, double* __restrict__ out) {
-  const int n = nc - 1;
+// u at a list of global node ids, for every sample: out[s][k] = u_s(ids[k]).
+__global__ void k_gather(int n_ids, int n_samples, const int* __restrict__ ids, const double* __restrict__ u,
+                         long long ustride, double* __restrict__ out) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)n * n_samples) return;
-  const int s = int(t / n), j = int(t % n) + 1;
-  out[t] = u[(long long)s * (nc + 1) * (nc + 1) + (long long)j * (nc + 1) + nc / 2];
+  if (t >= (long long)n_ids * n_samples) return;
+  const int s = int(t / n_ids), k = int(t % n_ids);
+  out[t] = u[(long long)s * ustride + ids[k]];
 }
 
 // eq. mean: sum over triangles of (|t|/3)(u1+u2+u3) / |R|, one block per
@@ -844,6 +854,13 @@ hipError_t launch_fill(double* p, long long n, double v, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  dim3 grid(std::max(1, std::min(ceil_div(n, 256), 65536))), block(256);
+  hipLaunchKernelGGL(k_fill_i32, grid, block, 0, st, p, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_prolong(int nc, const double* vc, double* vf, hipStream_t st) {
   const long long n = (long long)(nc + 1) * (nc + 1);
   hipLaunchKernelGGL(k_prolong, dim3(ceil_div(n, 256)), dim3(256), 0, st, nc, vc, vf);
@@ -870,12 +887,12 @@ hipError_t launch_residual(int nc, int n_samples, const double* kappa, const dou
 }
 
 hipError_t launch_axpy_maxabs(int nc, int n_samples, double* u, const double* d, unsigned long long* maxbits,
-                              hipStream_t st) {
+                              const int* active, hipStream_t st) {
   const long long nn = (long long)(nc + 1) * (nc + 1);
   // about 16 elements per thread: 4096 / n_samples workgroups per sample at most
   const int per = std::max(1, std::min(ceil_div(nn, 256 * 16), std::max(16, 4096 / std::max(n_samples, 1))));
   dim3 grid(per, n_samples);
-  hipLaunchKernelGGL(k_axpy_maxabs, grid, dim3(256), 0, st, nc, n_samples, u, d, maxbits);
+  hipLaunchKernelGGL(k_axpy_maxabs, grid, dim3(256), 0, st, nc, n_samples, u, d, maxbits, active);
   return hipGetLastError();
 }
 
@@ -887,9 +904,11 @@ hipError_t launch_points(int nc, int n_samples, int n_pts, const double* xy, con
   return hipGetLastError();
 }
 
-hipError_t launch_interface(int nc, int n_samples, const double* u, double* out, hipStream_t st) {
-  const long long n = (long long)(nc - 1) * n_samples;
-  hipLaunchKernelGGL(k_interface, dim3(ceil_div(n, 256)), dim3(256), 0, st, nc, n_samples, u, out);
+hipError_t launch_gather(int n_ids, int n_samples, const int* ids, const double* u, long long ustride, double* out,
+                         hipStream_t st) {
+  const long long n = (long long)n_ids * n_samples;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather, dim3(ceil_div(n, 256)), dim3(256), 0, st, n_ids, n_samples, ids, u, ustride, out);
   return hipGetLastError();
 }
 

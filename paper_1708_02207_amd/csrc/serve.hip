@@ -76,13 +76,20 @@ void run_mesh(hdd_server* S, Mesh* m) {
   std::vector<std::shared_ptr<Request>> batch;
   std::vector<int32_t> off;
   std::vector<double> xy, y, sig, vals, ll;
+  std::vector<int32_t> sstat;
   for (;;) {
     batch.clear();
     {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv_work.wait(lk, [&] { return S->stop || !m->queue.empty(); });
       if (S->stop) return;
+      // up to the slot count, and up to the handle's limit on the sites of
+      // one ragged query (a request never exceeds it alone)
+      int pts = 0;
       while (!m->queue.empty() && int(batch.size()) < m->slots) {
+        const int np = int(m->queue.front()->xy.size() / 2);
+        if (!batch.empty() && pts + np > HDD_MAX_QUERY_POINTS) break;
+        pts += np;
         batch.push_back(m->queue.front());
         m->queue.pop_front();
       }
@@ -104,9 +111,19 @@ void run_mesh(hdd_server* S, Mesh* m) {
     }
     vals.assign(off[B], 0.0);
     ll.assign(B, 0.0);
+    sstat.assign(B, HDD_OK);
+    // Codes that concern single samples (a failed pivot, a refinement that
+    // did not converge) still deliver every sample's values; each request
+    // then gets its own sample's status.  Any other code fails the batch.
+    auto per_sample = [](int c) { return c == HDD_OK || c == HDD_ENOTSPD || c == HDD_ENOTCONVERGED; };
     int st = hdd_build(m->h, B, m->pinned, m->f.data(), nullptr, HDD_MEM_HOST);
-    if (st == HDD_OK) st = hdd_query_points_ragged(m->h, off.data(), xy.data(), vals.data(), HDD_MEM_HOST);
-    if (st == HDD_OK) st = hdd_loglik_ragged(m->h, off.data(), xy.data(), y.data(), sig.data(), 0, ll.data(), HDD_MEM_HOST);
+    if (per_sample(st)) st = hdd_query_points_ragged(m->h, off.data(), xy.data(), vals.data(), HDD_MEM_HOST);
+    if (per_sample(st)) st = hdd_loglik_ragged(m->h, off.data(), xy.data(), y.data(), sig.data(), 0, ll.data(), HDD_MEM_HOST);
+    if (per_sample(st)) {
+      const int st2 = hdd_sample_status(m->h, sstat.data());
+      if (st2 != HDD_OK) st = st2;
+    }
+    if (!per_sample(st)) sstat.assign(B, st);
     const double t1 = now_s();
     {
       std::lock_guard<std::mutex> lk(S->mu);
@@ -114,7 +131,7 @@ void run_mesh(hdd_server* S, Mesh* m) {
         Request& r = *batch[b];
         r.values.assign(vals.begin() + off[b], vals.begin() + off[b + 1]);
         r.loglik = r.y.empty() ? 0.0 : ll[b];
-        r.status = st;
+        r.status = sstat[b];
         r.t_start = t0;
         r.t_done = t1;
         r.batch = B;
@@ -159,8 +176,9 @@ extern "C" {
 int hdd_server_create(const hdd_server_opts* o, const double* const* f, hdd_server_t* out) {
   if (!o || !out || o->n_meshes < 1 || o->n_meshes > HDD_SERVER_MAX_MESHES || o->slots < 0 || o->hbm_budget < 0.0)
     return HDD_EINVAL;
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < 7; ++i)
     if (o->reserved[i] != 0) return HDD_EINVAL;
+  if (o->max_refine < 0) return HDD_EINVAL;
   *out = nullptr;
   hdd_server* S = new (std::nothrow) hdd_server;
   if (!S) return HDD_ENOMEM;
@@ -174,6 +192,7 @@ int hdd_server_create(const hdd_server_opts* o, const double* const* f, hdd_serv
   for (int i = 0; i < o->n_meshes; ++i) {
     int st = hdd_default_opts(o->n[i], o->precision, &opts[i]);
     if (st == HDD_OK && o->leaf[i] > 0) opts[i].leaf = o->leaf[i];
+    if (st == HDD_OK && o->max_refine > 0) opts[i].max_refine = o->max_refine;
     if (st != HDD_OK) {
       delete S;
       return st;

@@ -39,8 +39,9 @@ EXPORTED = [
     "hdd_timing_enable", "hdd_timing_get", "hdd_mfma_selftest", "hdd_debug_frame",
     "hdd_timing_get_level", "hdd_query_points_ragged", "hdd_loglik_ragged",
     "hdd_server_create", "hdd_server_slots", "hdd_server_submit", "hdd_server_poll", "hdd_server_result",
-    "hdd_server_stats", "hdd_server_destroy",
+    "hdd_server_stats", "hdd_server_destroy", "hdd_sample_status",
 ]
+MAX_QUERY_POINTS = 4096
 
 SERVER_MAX_MESHES = 8
 SERVER_MAX_POINTS = 256
@@ -58,7 +59,7 @@ class ServerOpts(ctypes.Structure):
     _fields_ = [
         ("n_meshes", ctypes.c_int32), ("n", ctypes.c_int32 * SERVER_MAX_MESHES),
         ("leaf", ctypes.c_int32 * SERVER_MAX_MESHES), ("precision", ctypes.c_int32), ("slots", ctypes.c_int32),
-        ("hbm_budget", ctypes.c_double), ("reserved", ctypes.c_int32 * 8),
+        ("hbm_budget", ctypes.c_double), ("max_refine", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7),
     ]
 
 
@@ -83,7 +84,8 @@ def _load() -> ctypes.CDLL:
         "hdd_create": [popts, i32, P, P, ctypes.c_size_t, ctypes.POINTER(P)],
         "hdd_build": [P, i32, P, P, P, i32],
         "hdd_query_points": [P, i32, P, P, i32],
-        "hdd_query_interface": [P, P, ctypes.POINTER(i32), i32],
+        "hdd_query_interface": [P, i32, i32, P, ctypes.POINTER(i32), i32],
+        "hdd_sample_status": [P, P],
         "hdd_query_mean": [P, P, P, i32],
         "hdd_query_node_means": [P, P, i32],
         "hdd_solve_rhs": [P, P, P, i32],
@@ -268,12 +270,27 @@ class HDD:
         _check(_lib.hdd_query_points(self.h, len(xy), _np_ptr(xy), op, mem), "hdd_query_points")
         return out
 
-    def query_interface(self) -> np.ndarray:
-        res = np.zeros((self.n_samples, self.n))
+    def query_interface(self, depth: int = 0, index: int = 0, out=None) -> np.ndarray:
+        """u on the interface gamma of tree node (depth, index), [n_samples][|gamma|],
+        entries in the order of hdd_plan_node's ids; (0, 0) is the root midline."""
         ln = ctypes.c_int32(0)
-        _check(_lib.hdd_query_interface(self.h, _np_ptr(res), ctypes.byref(ln), HDD_MEM_HOST), "hdd_query_interface")
-        assert ln.value == self.n
-        return res
+        if out is None:
+            g = hdd_plan_node(self.opts, depth, index)["gam"]
+            res = np.zeros((self.n_samples, g))
+            _check(_lib.hdd_query_interface(self.h, int(depth), int(index), _np_ptr(res), ctypes.byref(ln),
+                                            HDD_MEM_HOST), "hdd_query_interface")
+            assert ln.value == g
+            return res
+        op, mem = _ptr(out)
+        _check(_lib.hdd_query_interface(self.h, int(depth), int(index), op, ctypes.byref(ln), mem),
+               "hdd_query_interface")
+        return out
+
+    def sample_status(self) -> np.ndarray:
+        """Per-sample status codes (HDD_OK, HDD_EINVAL, HDD_ENOTSPD, HDD_ENOTCONVERGED)."""
+        st = np.zeros(max(self.n_samples, 1), dtype=np.int32)
+        _check(_lib.hdd_sample_status(self.h, _np_ptr(st)), "hdd_sample_status")
+        return st[: self.n_samples]
 
     def query_mean(self, rect: Sequence[float]) -> np.ndarray:
         r = np.ascontiguousarray(rect, dtype=np.float64)
@@ -418,7 +435,7 @@ class Server:
     one HDD handle, stream and worker thread per mesh size."""
 
     def __init__(self, meshes, precision: int = HDD_FP32_REFINE, slots: int = 0, hbm_budget: float = 0.0,
-                 leaves=None, f=None):
+                 leaves=None, f=None, max_refine: int = 0):
         o = ServerOpts()
         o.n_meshes = len(meshes)
         for i, n in enumerate(meshes):
@@ -427,6 +444,7 @@ class Server:
         o.precision = int(precision)
         o.slots = int(slots)
         o.hbm_budget = float(hbm_budget)
+        o.max_refine = int(max_refine)
         self.meshes = list(meshes)
         self._f = None
         fp = None
@@ -458,13 +476,17 @@ class Server:
         _check(_lib.hdd_server_poll(self.h, int(rid), ctypes.byref(d)), "hdd_server_poll")
         return bool(d.value)
 
-    def result(self, rid: int, n_pts: int):
-        """(values [n_pts], loglik, times [queue, batch, total seconds, batch size])."""
+    def result(self, rid: int, n_pts: int, with_status: bool = False):
+        """(values [n_pts], loglik, times [queue, batch, total seconds, batch size]);
+        with_status: the request's status code is returned as a fourth item
+        instead of raising on a non-OK code."""
         vals = np.zeros(n_pts)
         ll = ctypes.c_double(0)
         times = np.zeros(4)
-        _check(_lib.hdd_server_result(self.h, int(rid), _np_ptr(vals), ctypes.byref(ll), _np_ptr(times)),
-               "hdd_server_result")
+        code = _lib.hdd_server_result(self.h, int(rid), _np_ptr(vals), ctypes.byref(ll), _np_ptr(times))
+        if with_status:
+            return vals, ll.value, times, code
+        _check(code, "hdd_server_result")
         return vals, ll.value, times
 
     def stats(self):

@@ -4,8 +4,9 @@ The 255^2 configuration is checked on all 256 samples built in one batch; the
 1023^2 configuration on its first 4 samples (points, root midline interface,
 mean over [0.25,0.5]^2).  A property that holds at any size certifies the
 float64 field at 1023^2: the extended-precision residual bounds its error.
-The refined float32 field is compared with that float64 field on every node,
-and the 32-sample batch the benchmark times is compared path against path.
+The refined float32 field is compared with that float64 field on every node;
+in the 32-sample batch the benchmark times every float64 field is certified
+by its residual bound and the float32 path is compared against it.
 Tolerances (normwise relative): HDD_FP64 1e-10, HDD_FP32_REFINE 1e-8.
 """
 import json
@@ -118,10 +119,14 @@ def test_c2_1023(H, oracle_mod, prec):
     t.close()
 
 
-def test_c2_1023_bench_batch(H):
+def test_c2_1023_bench_batch(H, oracle_mod):
     """The bench's launch configuration (32 samples of the 1023^2 workload in
-    one batch, default options): every sample's measurements on the FP32
-    matrix-core + refinement path agree with the float64 path to 1e-8."""
+    one batch, default options).  Every sample's float64 field is certified
+    against the exact discrete solution by its extended-precision residual
+    bound (a property that holds at any size: ||u - u_h||_2 <= ||b - A u||_2 /
+    lambda_min(A)); every sample's measurements on the FP32 matrix-core +
+    refinement path agree with that certified float64 path to 1e-8, and the
+    first 4 samples with the stored oracle values."""
     g = gold("c2_1023")
     B = 32
     w = make_workload("c2_1023", n_samples=B)
@@ -136,6 +141,16 @@ def test_c2_1023_bench_batch(H):
         out[prec] = (t.query_points(xy), t.query_interface(), t.query_mean(g["mean_rect"]))
         if prec == H.HDD_FP32_REFINE:
             say("  refinement sweeps", t.error_estimate()[1])
+        else:
+            t.solve_full()
+            worst_b = 0.0
+            for s in range(B):
+                u = t.solution(s)
+                r = oracle_mod.residual(w.n, w.kappa[s], w.f, u)
+                b = oracle_mod.error_bound_l2(w.n, w.kappa[s], r) / np.linalg.norm(u)
+                worst_b = max(worst_b, b)
+                assert b <= 1e-8, (s, b)
+            say("  float64 fields: worst certified relative l2 error bound over", B, "samples", worst_b)
         t.close()
     worst = 0.0
     for s in range(B):
@@ -143,15 +158,22 @@ def test_c2_1023_bench_batch(H):
             worst = max(worst, rel(np.atleast_1d(a[s]), np.atleast_1d(b[s])))
     say("  worst rel difference over", B, "samples", worst)
     assert worst < TOL[1]
+    for smp in g["samples"]:
+        k = smp["sample"]
+        for prec in (H.HDD_FP64, H.HDD_FP32_REFINE):
+            assert rel(out[prec][0][k], smp["points"]) < TOL[prec]
+            assert rel(out[prec][1][k], smp["interface"]) < TOL[prec]
 
 
 def test_c4_2047_stress(H, oracle_mod):
     """High-contrast stress workload (2047^2 interior nodes, kappa variance 4,
-    correlation length 0.02, 200 modes, Gaussian-bump load): the float64
-    field is certified by its extended-precision residual bound; the float32
-    matrix-core + refinement path's difference from it is stated (the
-    configuration is reported, not gated at 1e-8), with a loose gate that
-    catches breakage only."""
+    correlation length 0.02, 200 modes, Gaussian-bump load).  The oracle's
+    banded solve does not fit a test here, so parity with it is unpinned at
+    this size; instead the float64 field is certified by its
+    extended-precision residual bound, which carries kappa_max / kappa_min
+    (about 1e4 here) and h^-2 and was measured at 8.5e-8 relative (gate
+    1e-6).  The float32 matrix-core + refinement path matches that float64
+    field to 1e-8 (measured 1.6e-10)."""
     w = make_workload("c4_2047")
     xy = np.asarray(w.points)
     kd = torch.from_numpy(w.kappa[:1]).cuda()
@@ -172,10 +194,8 @@ def test_c4_2047_stress(H, oracle_mod):
     r = oracle_mod.residual(w.n, w.kappa[0], w.f, out[H.HDD_FP64][2])
     bound = oracle_mod.error_bound_l2(w.n, w.kappa[0], r)
     say("  float64 residual error bound (l2)", bound, "field norm", np.linalg.norm(out[H.HDD_FP64][2]))
-    # the bound carries kappa_max / kappa_min (about 1e4 here) and h^-2: it is
-    # stated, and gated only against gross failure
-    assert bound <= 1e-4 * np.linalg.norm(out[H.HDD_FP64][2])
+    assert bound <= 1e-6 * np.linalg.norm(out[H.HDD_FP64][2])
     e = max(rel(out[H.HDD_FP32_REFINE][0], out[H.HDD_FP64][0]), rel(out[H.HDD_FP32_REFINE][1], out[H.HDD_FP64][1]),
             rel(out[H.HDD_FP32_REFINE][2], out[H.HDD_FP64][2]))
     say("  float32+refinement vs float64 (max over points, midline, field)", e)
-    assert e < 1e-6
+    assert e < 1e-8

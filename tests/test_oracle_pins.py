@@ -241,6 +241,37 @@ def test_mean_and_interface(oracle_mod):
     assert np.allclose(iv, 1.0 + 1.5 + 5.0 * x[1:-1])
 
 
+def test_node_interface(oracle_mod):
+    """The interface of every tree node (eq. gamma_def) is the shared edge of
+    its two sons without the edge's end points: every node on it lies on both
+    sons' boundaries and strictly inside the father; |gamma| = cut length - 1;
+    the root's is the midline.  Values are read off the affine field."""
+    O = oracle_mod
+    n, block = 63, 8
+    nc = n + 1
+    h = 1.0 / nc
+    x = np.arange(nc + 1) * h
+    X, Y = np.meshgrid(x, x)
+    u = 1.0 + 3.0 * X + 5.0 * Y
+    rects = O.tree_rects(n, block)
+    n_inner = len(rects) - (nc // block) ** 2
+    for k in range(n_inner):
+        ids, vals = O.node_interface(n, u, block, k)
+        i0, i1, j0, j1 = rects[k]
+        sons = (rects[2 * k + 1], rects[2 * k + 2])
+        assert len(ids) == (j1 - j0 - 1 if i1 - i0 >= j1 - j0 else i1 - i0 - 1)
+        for q, v in zip(ids, vals):
+            i, j = int(q % (nc + 1)), int(q // (nc + 1))
+            assert i0 < i < i1 or j0 < j < j1
+            assert i0 <= i <= i1 and j0 <= j <= j1
+            for a0, a1, b0, b1 in sons:
+                on_edge = (i in (a0, a1) and b0 <= j <= b1) or (j in (b0, b1) and a0 <= i <= a1)
+                assert on_edge
+            assert abs(v - (1.0 + 3.0 * i * h + 5.0 * j * h)) < 1e-13
+    ids, vals = O.node_interface(n, u, block, 0)
+    assert np.array_equal(vals, O.interface_values(n, u))
+
+
 # P12: likelihood against scipy's normal log-density -------------------------------------
 def test_loglik(oracle_mod):
     O = oracle_mod

@@ -7,6 +7,8 @@ imported from here.
 """
 from .gen import (  # noqa: F401
     CONFIGS,
+    edge_sites,
+    off_tree_rects,
     Workload,
     kl_modes,
     kappa_from_q,

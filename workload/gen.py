@@ -101,6 +101,46 @@ def coefficient_field(n: int, z: np.ndarray, var: float, corr: float) -> np.ndar
     return out
 
 
+def edge_sites(n: int) -> np.ndarray:
+    """Observation sites on the places where locating the holding triangle is
+    delicate, shape [m, 2]: the corners and edges of the unit square, the
+    root midline x = 1/2 and the line y = 1/2, lines x or y = k * 16 h
+    (boundaries of 16 x 16-cell blocks and of the leaves above them), exact
+    mesh nodes (block corners among them), and points on cell diagonals
+    (fx = fy).  Cells have the dyadic side h = 1/(N+1), so every coordinate
+    here is exact in binary."""
+    nc = n + 1
+    h = 1.0 / nc
+    q = nc // 4
+    pts = [(0.0, 0.0), (1.0, 1.0), (0.0, 1.0), (1.0, 0.0), (0.0, 0.375), (1.0, 0.625), (0.3125, 0.0),
+           (0.6875, 1.0), (0.5, 0.5), (0.5, 0.125), (0.5, 1.0 - h), (0.75, 0.5), (h, 0.5)]
+    # exact mesh nodes, block and leaf corners among them
+    for i, j in ((1, 1), (nc - 1, nc - 1), (min(16, nc - 1), min(16, nc - 1)), (nc // 2, q), (q, 3 * q),
+                 (min(17, nc - 1), min(33, nc - 1)), (nc // 2 - 1, nc // 2 + 1)):
+        pts.append((i * h, j * h))
+    # block / leaf boundaries off the nodes: x or y a multiple of 16 h
+    for k in sorted({min(16, nc // 2), nc // 2, q, 3 * q}):
+        pts.append((k * h, (k // 2 + 0.375) * h))
+        pts.append(((k // 2 + 0.625) * h, k * h))
+    # cell diagonals, fx == fy
+    for i, j, t in ((5, 9, 0.25), (nc // 2 - 1, q, 0.5), (q, nc // 2, 0.75), (nc - 2, 3, 0.5)):
+        pts.append(((i + t) * h, (j + t) * h))
+    return np.array(pts, dtype=np.float64)
+
+
+def off_tree_rects(n: int):
+    """Cell-aligned rectangles (x0, x1, y0, y1) that are not nodes of the
+    tree: one crossing the root midline and the line y = 1/2, one thin strip
+    on the outer boundary, and a small one (inside one 16 x 16-cell block
+    when N + 1 >= 128)."""
+    nc = n + 1
+    h = 1.0 / nc
+    q = nc // 4
+    return [((3) * h, (nc // 2 + 5) * h, (nc // 8 + 1) * h, (3 * q - 3) * h),
+            (0.0, 1.0, 0.0, 2 * h),
+            ((q + 2) * h, (q + 9) * h, (q + 4) * h, (q + 6) * h)]
+
+
 def kappa_from_q(q_minus: np.ndarray, q_plus: np.ndarray) -> np.ndarray:
     """Stack per-triangle log-coefficients [Nc, Nc] into kappa [1, Nc, Nc, 2]."""
     return np.exp(np.stack([q_minus, q_plus], axis=-1))[None]
