@@ -108,6 +108,34 @@ int hdd_create(const hdd_opts* opts, int32_t max_samples, void* stream, void* wo
                hdd_handle* out);
 
 /*
+ * hdd_create for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * workspace is a static device array of the library, HDD_STATIC_WORKSPACE_BYTES
+ * per GPU (held by every GPU the library runs on until the process ends), so
+ * neither this call nor any later call on the handle makes a device,
+ * pinned-host or event allocation.  Everything else is as hdd_create: same
+ * plan, kernels and results.
+ *   stream  hipStream_t for all work (NULL: the null stream)
+ * Limits and sharing:
+ *  - hdd_workspace_size(opts, max_samples) must be at most
+ *    HDD_STATIC_WORKSPACE_BYTES (64 MiB: e.g. 63^2 with 24 samples, 127^2 with
+ *    4 in float64 or 7 in float32 + refinement), else HDD_ENOMEM and nothing
+ *    is created.
+ *  - All static handles of one GPU share its array, so at most one lives per
+ *    GPU at a time: HDD_ESTATE while another exists (after hdd_destroy the
+ *    next one may be created).  The array keeps the previous handle's
+ *    contents; creation clears the part the new handle uses to zero.  Work of
+ *    the handle that overlaps other users of the array would race; the
+ *    single-owner rule prevents that within the library.
+ *  - hdd_timing_enable with a non-zero mask is refused (HDD_EINVAL): timing
+ *    events would be allocations.
+ * Errors: HDD_EINVAL (options), HDD_ENOMEM (too large), HDD_ESTATE (array in
+ * use), HDD_EDEVICE.
+ */
+#define HDD_STATIC_WORKSPACE_BYTES (64 << 20)
+int hdd_create_static(const hdd_opts* opts, int32_t max_samples, void* stream, hdd_handle* out);
+
+/*
  * Leaves to Root for n_samples (<= max_samples) samples: assemble every leaf,
  * eliminate every interface, keep all factors (Section 3.4).
  *   kappa  (mem) float64 [n_samples][Nc][Nc][2]

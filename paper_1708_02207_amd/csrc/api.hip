@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -16,6 +17,13 @@
 using hdd::DevLevel;
 using hdd::DevNode;
 using hdd::Plan;
+
+// Workspace of hdd_create_static: one array per GPU that the library runs
+// on, held until the process ends.  Host code never uses the name as an
+// address (on the host it is only a stand-in): the device address of each
+// GPU's copy is resolved once per device with hipGetSymbolAddress and kept
+// per device (static_slots below).
+static __device__ __align__(256) unsigned char scratch[HDD_STATIC_WORKSPACE_BYTES];
 
 namespace {
 
@@ -175,6 +183,7 @@ struct hdd_tree {
   hipEvent_t lists_done = nullptr;   // the last list upload has completed (null: synchronize instead)
   std::vector<int> lists_host;       // pageable staging when the handle may not allocate
   bool no_alloc = false;             // no device, pinned or event allocation after creation
+  int static_dev = -1;               // device whose static scratch this handle owns (hdd_create_static)
   bool built = false, full = false;
   std::vector<std::vector<uint8_t>> solved;
   std::vector<double> est;
@@ -537,6 +546,12 @@ int create_impl(const hdd_opts* o, int32_t max_samples, void* stream, void* work
     }
     h->own_ws = true;
   }
+  if (no_alloc) {
+    // a reused workspace keeps the previous handle's contents: start from zeros
+    if (hdd::launch_fill(reinterpret_cast<double*>(h->ws), h->lay.total / 8, 0.0, h->st) != hipSuccess ||
+        hipStreamSynchronize(h->st) != hipSuccess)
+      return fail(HDD_EDEVICE);
+  }
   const Layout& L = h->lay;
   const int nd = int(h->plan.levels.size());
   h->lev.resize(nd);
@@ -686,6 +701,15 @@ int create_impl(const hdd_opts* o, int32_t max_samples, void* stream, void* work
   return HDD_OK;
 }
 
+constexpr int kMaxStaticDevices = 64;
+struct StaticSlot {
+  void* ptr = nullptr;       // device address of this GPU's scratch
+  bool resolved = false;
+  hdd_tree* owner = nullptr; // the live static handle on this GPU, if any
+};
+std::mutex static_mu;
+StaticSlot static_slots[kMaxStaticDevices];
+
 }  // namespace
 
 namespace hdd {
@@ -700,6 +724,31 @@ extern "C" {
 int hdd_create(const hdd_opts* o, int32_t max_samples, void* stream, void* workspace, size_t workspace_bytes,
                hdd_handle* out) {
   return create_impl(o, max_samples, stream, workspace, workspace_bytes, false, out);
+}
+
+int hdd_create_static(const hdd_opts* o, int32_t max_samples, void* stream, hdd_handle* out) {
+  HDD_TRY(validate_opts(o));
+  if (max_samples < 1 || !out) return HDD_EINVAL;
+  size_t need = 0;
+  HDD_TRY(hdd_workspace_size(o, max_samples, &need));
+  if (need > size_t(HDD_STATIC_WORKSPACE_BYTES)) return HDD_ENOMEM;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxStaticDevices) return HDD_EDEVICE;
+  std::lock_guard<std::mutex> lock(static_mu);
+  StaticSlot& slot = static_slots[dev];
+  if (!slot.resolved) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HDD_EDEVICE;
+    slot.ptr = p;
+    slot.resolved = true;
+  }
+  if (slot.owner) return HDD_ESTATE;
+  hdd_handle h = nullptr;
+  HDD_TRY(create_impl(o, max_samples, stream, slot.ptr, size_t(HDD_STATIC_WORKSPACE_BYTES), true, &h));
+  h->static_dev = dev;
+  slot.owner = h;
+  *out = h;
+  return HDD_OK;
 }
 
 int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double* f, const double* g, int32_t mem) {
@@ -1065,6 +1114,10 @@ int hdd_destroy(hdd_handle h) {
   if (h->pinned_lists && !h->no_alloc) (void)hipHostFree(h->pinned_lists);
   if (h->own_ws && h->ws) (void)hipFree(h->ws);
   if (h->own_stream && h->st) (void)hipStreamDestroy(h->st);
+  if (h->static_dev >= 0) {
+    std::lock_guard<std::mutex> lock(static_mu);
+    if (static_slots[h->static_dev].owner == h) static_slots[h->static_dev].owner = nullptr;
+  }
   delete h;
   return HDD_OK;
 }
@@ -1199,7 +1252,7 @@ int hdd_debug_frame(hdd_handle h, int32_t sample, int32_t depth, int32_t index, 
 }
 
 int hdd_timing_enable(hdd_handle h, int32_t mask) {
-  if (!h) return HDD_EINVAL;
+  if (!h || (h->no_alloc && mask != 0)) return HDD_EINVAL;  // timing events would be allocations
   HIP_TRY(hipStreamSynchronize(h->st));
   h->timing_mask = mask;
   h->recs.clear();

@@ -39,9 +39,10 @@ EXPORTED = [
     "hdd_timing_enable", "hdd_timing_get", "hdd_mfma_selftest", "hdd_debug_frame",
     "hdd_timing_get_level", "hdd_query_points_ragged", "hdd_loglik_ragged",
     "hdd_server_create", "hdd_server_slots", "hdd_server_submit", "hdd_server_poll", "hdd_server_result",
-    "hdd_server_stats", "hdd_server_destroy", "hdd_sample_status",
+    "hdd_server_stats", "hdd_server_destroy", "hdd_sample_status", "hdd_create_static",
 ]
 MAX_QUERY_POINTS = 4096
+STATIC_WORKSPACE_BYTES = 64 << 20
 
 SERVER_MAX_MESHES = 8
 SERVER_MAX_POINTS = 256
@@ -82,6 +83,7 @@ def _load() -> ctypes.CDLL:
         "hdd_default_opts": [i32, i32, popts],
         "hdd_workspace_size": [popts, i32, ctypes.POINTER(ctypes.c_size_t)],
         "hdd_create": [popts, i32, P, P, ctypes.c_size_t, ctypes.POINTER(P)],
+        "hdd_create_static": [popts, i32, P, ctypes.POINTER(P)],
         "hdd_build": [P, i32, P, P, P, i32],
         "hdd_query_points": [P, i32, P, P, i32],
         "hdd_query_interface": [P, i32, i32, P, ctypes.POINTER(i32), i32],
@@ -210,6 +212,9 @@ class HDD:
     """One handle: a planned tree with device memory for up to max_samples samples."""
 
     def __init__(self, opts: HddOpts, max_samples: int, stream=None, workspace: str = "torch"):
+        """workspace: "torch" (a torch device buffer passed to hdd_create),
+        "library" (hdd_create allocates it) or "static" (hdd_create_static:
+        the library's static device array, no allocation)."""
         import torch
 
         self.opts = opts
@@ -228,8 +233,12 @@ class HDD:
             sptr = ctypes.c_void_p(stream.cuda_stream)
         self.stream = stream
         h = ctypes.c_void_p()
-        _check(_lib.hdd_create(ctypes.byref(opts), self.max_samples, sptr, wptr, ctypes.c_size_t(wbytes),
-                               ctypes.byref(h)), "hdd_create")
+        if workspace == "static":
+            _check(_lib.hdd_create_static(ctypes.byref(opts), self.max_samples, sptr, ctypes.byref(h)),
+                   "hdd_create_static")
+        else:
+            _check(_lib.hdd_create(ctypes.byref(opts), self.max_samples, sptr, wptr, ctypes.c_size_t(wbytes),
+                                   ctypes.byref(h)), "hdd_create")
         self.h = h
 
     def close(self):
