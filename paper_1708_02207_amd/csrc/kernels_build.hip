@@ -233,13 +233,14 @@ struct SyrkArgs {
   int k0, k1, r0, c0, c1;
   int tiles_c;  // number of tile columns
   int tiles_r;  // number of tile rows
+  int sep;      // 1: matrix-core tiles (rows <= U - 1; the load row U by the diagonal tiles)
 };
 
 // One K chunk of the A rows (rowA0..) and B rows (rowB0..) into LDS.  Rows
 // past U are clamped to U (they only feed outputs that are never stored);
 // columns past k1 read a clamped address and are replaced by zero, so the
 // loads carry no branches.
-template <typename T>
+template <typename T, bool WZ = false>
 __device__ __forceinline__ void syrk_load_chunk(T (*As)[SyrkCfg<T>::KC + 1], T (*Bs)[SyrkCfg<T>::KC + 1],
                                                 const T* F, int ld, int U, int rowA0, int rowB0, int kbeg,
                                                 int k1) {
@@ -250,7 +251,7 @@ __device__ __forceinline__ void syrk_load_chunk(T (*As)[SyrkCfg<T>::KC + 1], T (
   const int col0 = (tid % (KC / PER)) * PER;
   const T* pa = F + (long long)min(rowA0 + row, U) * ld;
   const T* pb = F + (long long)min(rowB0 + row, U) * ld;
-  T va[PER], vb[PER];
+  T va[PER], vb[PER], vz = T(0);
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const int k = kbeg + col0 + q;
@@ -258,14 +259,16 @@ __device__ __forceinline__ void syrk_load_chunk(T (*As)[SyrkCfg<T>::KC + 1], T (
     va[q] = pa[kc];
     vb[q] = pb[kc];
   }
+  // WZ: row 64 of As receives the chunk of the load row U (z)
+  if (WZ && tid < KC) vz = F[(long long)U * ld + min(kbeg + tid, k1 - 1)];
 #pragma unroll
   for (int q = 0; q < PER; ++q) {
     const bool kin = kbeg + col0 + q < k1;
     As[row][col0 + q] = kin ? va[q] : T(0);
     Bs[row][col0 + q] = kin ? vb[q] : T(0);
   }
+  if (WZ && tid < KC) As[64][tid] = kbeg + tid < k1 ? vz : T(0);
 }
-
 // Output element (i, j) of the update belongs to this call's region.
 __device__ __forceinline__ bool syrk_in(int U, int i, int j, const SyrkArgs& a, int c1e) {
   return i <= U && i >= a.r0 && j >= a.c0 && j < c1e && j <= i;
@@ -283,35 +286,55 @@ __device__ __forceinline__ T syrk_old(const T* F, int ld, int U, int i, int j) {
   return F[(long long)min(i, U) * ld + min(j, U)];
 }
 
+// The 64 x 64 matrix-core tiles leave the load row U to the diagonal tiles'
+// idle wave: in a diagonal tile the upper-right 32 x 32 wave block lies
+// strictly above the diagonal, so that wave instead forms the update of the
+// load row, F[U][j] -= sum_k z_k F[j][k] (g_omega = g~ - P z, eq. SchurC1),
+// for the tile's 64 columns from the B rows in LDS and z staged as row 64 of
+// As.  Without this the single row U would cost a whole row of tiles.
 __global__ void __launch_bounds__(256) k_syrk_mfma_f32(DevLevel L, SyrkArgs a, int n_samples) {
   constexpr int KC = SyrkCfg<float>::KC;
-  __shared__ float As[64][KC + 1];
+  __shared__ float As[65][KC + 1];
   __shared__ float Bs[64][KC + 1];
   const int pair = blockIdx.x;
   const int node = pair / n_samples, s = pair % n_samples;
   const DevNode nd = L.nodes[node];
   const int U = nd.U;
-  const int c1e = a.c1 < 0 ? U + 1 : a.c1;
+  const int Ue = U - 1;  // last row of the tiles; row U is the load row
+  const int c1e = min(a.c1 < 0 ? U + 1 : a.c1, U);
   const int ti = blockIdx.y / a.tiles_c, tj = blockIdx.y % a.tiles_c;
   const int i0 = a.r0 + ti * 64, j0 = a.c0 + tj * 64;
-  if (i0 > U || j0 >= c1e || i0 + 63 < j0) return;
+  if (i0 > Ue || j0 >= c1e || i0 + 63 < j0) return;
   float* F = frame_ptr<float>(L, node, s);
   const int ld = nd.ld;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1;
+  const bool diag = i0 == j0;
+  const bool rhs_wave = diag && wr == 0 && wc == 1;  // wave-uniform
   floatx16 acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  float racc = 0.f;
   for (int kb = a.k0; kb < a.k1; kb += KC) {
     __syncthreads();
-    syrk_load_chunk<float>(As, Bs, F, ld, U, i0, j0, kb, a.k1);
+    syrk_load_chunk<float, true>(As, Bs, F, ld, U, i0, j0, kb, a.k1);
     __syncthreads();
+    if (rhs_wave) {
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 2) {
-      const float av = As[wr * 32 + (lane & 31)][kk + (lane >> 5)];
-      const float bv = Bs[wc * 32 + (lane & 31)][kk + (lane >> 5)];
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+      for (int kk = 0; kk < KC; ++kk) racc += As[64][kk] * Bs[lane][kk];
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 2) {
+        const float av = As[wr * 32 + (lane & 31)][kk + (lane >> 5)];
+        const float bv = Bs[wc * 32 + (lane & 31)][kk + (lane >> 5)];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+      }
     }
+  }
+  if (rhs_wave) {
+    const int j = j0 + lane;
+    if (j < c1e) F[(long long)U * ld + j] -= racc;
+    return;
   }
   float old[16];
 #pragma unroll
@@ -324,26 +347,29 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f32(DevLevel L, SyrkArgs a, i
   for (int v = 0; v < 16; ++v) {
     const int i = i0 + wr * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
     const int j = j0 + wc * 32 + (lane & 31);
-    if (syrk_in(U, i, j, a, c1e)) F[(long long)i * ld + j] = old[v] - acc[v];
+    if (syrk_in(Ue, i, j, a, c1e)) F[(long long)i * ld + j] = old[v] - acc[v];
   }
 }
 
+// float64 version of the same tile (16 x 16 x 4 MFMA, 2 x 2 per wave).
 __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, int n_samples) {
   constexpr int KC = SyrkCfg<double>::KC;
-  __shared__ double As[64][KC + 1];
+  __shared__ double As[65][KC + 1];
   __shared__ double Bs[64][KC + 1];
   const int pair = blockIdx.x;
   const int node = pair / n_samples, s = pair % n_samples;
   const DevNode nd = L.nodes[node];
   const int U = nd.U;
-  const int c1e = a.c1 < 0 ? U + 1 : a.c1;
+  const int Ue = U - 1;  // last row of the tiles; row U is the load row
+  const int c1e = min(a.c1 < 0 ? U + 1 : a.c1, U);
   const int ti = blockIdx.y / a.tiles_c, tj = blockIdx.y % a.tiles_c;
   const int i0 = a.r0 + ti * 64, j0 = a.c0 + tj * 64;
-  if (i0 > U || j0 >= c1e || i0 + 63 < j0) return;
+  if (i0 > Ue || j0 >= c1e || i0 + 63 < j0) return;
   double* F = frame_ptr<double>(L, node, s);
   const int ld = nd.ld;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1;
+  const bool rhs_wave = i0 == j0 && wr == 0 && wc == 1;  // wave-uniform
   doublex4 acc[2][2];
 #pragma unroll
   for (int x = 0; x < 2; ++x)
@@ -351,22 +377,34 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[x][y][v] = 0.0;
+  double racc = 0.0;
   for (int kb = a.k0; kb < a.k1; kb += KC) {
     __syncthreads();
-    syrk_load_chunk<double>(As, Bs, F, ld, U, i0, j0, kb, a.k1);
+    syrk_load_chunk<double, true>(As, Bs, F, ld, U, i0, j0, kb, a.k1);
     __syncthreads();
+    if (rhs_wave) {
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-      double av[2], bv[2];
+      for (int kk = 0; kk < KC; ++kk) racc += As[64][kk] * Bs[lane][kk];
+    } else {
 #pragma unroll
-      for (int x = 0; x < 2; ++x) av[x] = As[wr * 32 + x * 16 + (lane & 15)][kk + (lane >> 4)];
+      for (int kk = 0; kk < KC; kk += 4) {
+        double av[2], bv[2];
 #pragma unroll
-      for (int y = 0; y < 2; ++y) bv[y] = Bs[wc * 32 + y * 16 + (lane & 15)][kk + (lane >> 4)];
+        for (int x = 0; x < 2; ++x) av[x] = As[wr * 32 + x * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y) bv[y] = Bs[wc * 32 + y * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y)
+            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+      }
     }
+  }
+  if (rhs_wave) {
+    const int j = j0 + lane;
+    if (j < c1e) F[(long long)U * ld + j] -= racc;
+    return;
   }
   double old[2][2][4];
 #pragma unroll
@@ -387,40 +425,25 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
       for (int v = 0; v < 4; ++v) {
         const int i = i0 + wr * 32 + x * 16 + 4 * v + (lane >> 4);
         const int j = j0 + wc * 32 + y * 16 + (lane & 15);
-        if (syrk_in(U, i, j, a, c1e)) F[(long long)i * ld + j] = old[x][y][v] - acc[x][y][v];
+        if (syrk_in(Ue, i, j, a, c1e)) F[(long long)i * ld + j] = old[x][y][v] - acc[x][y][v];
       }
 }
 
 // Large-tile version for the upper levels: 128 x 128 output tile per
 // workgroup (4 waves, 64 x 64 each as 2 x 2 blocks of 32 x 32 x 2 MFMA),
-// K chunks of 32 staged through LDS, the next chunk prefetched into registers
-// while the current one is multiplied.  Requires ld % 4 == 0 and k0 % 4 == 0
-// (16-byte aligned rows), which holds for frames with 64 or more rows.
-__global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int n_samples) {
-  constexpr int KC = 32, TM = 128;
-  // two LDS buffers: the MFMAs read one while the prefetched chunk is
-  // stored into the other, one barrier per K chunk
-  __shared__ float As[2][TM][KC + 1];
-  __shared__ float Bs[2][TM][KC + 1];
-  // XCD-aware order: workgroup b runs on XCD b % 8; all tiles of one (node,
-  // sample) frame go to the same XCD in consecutive order, so its panel
-  // columns stay in that XCD's L2 while its tiles are computed.
-  const int n_pairs = L.n_nodes * n_samples;
-  const int n_tiles = a.tiles_r * a.tiles_c;
-  const int b = blockIdx.x;
-  const int loc = b >> 3;
-  const int pair = (loc / n_tiles) * 8 + (b & 7);
-  if (pair >= n_pairs) return;
-  const int tile = loc % n_tiles;
-  const int node = pair / n_samples, s = pair % n_samples;
-  const DevNode nd = L.nodes[node];
-  const int U = nd.U;
-  const int c1e = a.c1 < 0 ? U + 1 : a.c1;
-  const int ti = tile / a.tiles_c, tj = tile % a.tiles_c;
-  const int i0 = a.r0 + ti * TM, j0 = a.c0 + tj * TM;
-  if (i0 > U || j0 >= c1e || i0 + TM - 1 < j0) return;
-  float* F = frame_ptr<float>(L, node, s);
-  const int ld = nd.ld;
+// K chunks of 32 staged through two LDS buffers, one barrier per chunk.  The
+// next chunk's global loads are in flight while the current chunk is
+// multiplied: the loop body has no branch, every chunk is read at addresses
+// clamped into the node's frame (rows past U to U, columns to the last
+// column of the row), and entries outside [k0, k1) are zeroed when the chunk
+// is stored to LDS, after the MFMAs, so no load result is waited for before
+// the MFMAs of the chunk it is prefetched behind.  The last chunk is peeled
+// so that its MFMAs overlap the epilogue's first reads.  V4: 16-byte loads
+// (ld % 4 == 0 and k0 % 4 == 0, frames with 64 or more rows).
+template <bool V4>
+__device__ __forceinline__ void syrk128_tile(float (*As)[128][33], float (*Bs)[128][33], float* F, int ld, int U,
+                                             int Ue, int i0, int j0, const SyrkArgs& a, int c1e) {
+  constexpr int KC = 32;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;
   // loader mapping: thread -> (row lr, 16 consecutive k) for A and B.  Rows
@@ -428,39 +451,47 @@ __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int
   const int lr = tid >> 1, lk = (tid & 1) * 16;
   const float* rowA = F + (long long)min(i0 + lr, U) * ld;
   const float* rowB = F + (long long)min(j0 + lr, U) * ld;
-  const bool vec4 = (ld % 4) == 0;  // 16-byte aligned rows (k0 % 4 == 0)
-  float4 pa[4], pb[4];
+  const float* rowZ = F + (long long)U * ld;
+  // in a diagonal tile the upper-right wave block lies above the diagonal;
+  // that wave forms the load row instead (see k_syrk_mfma_f32), with the
+  // chunk of z staged as row 128 of As by the first 8 threads
+  const bool diag = i0 == j0;
+  float4 pa[4], pb[4], pz;
   auto load = [&](int kb) {
-    if (vec4 && kb + KC <= a.k1) {  // uniform: a whole chunk inside [k0, k1)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        pa[q] = *reinterpret_cast<const float4*>(rowA + kb + lk + 4 * q);
-        pb[q] = *reinterpret_cast<const float4*>(rowB + kb + lk + 4 * q);
-      }
-    } else {  // ragged tail: clamped addresses, out-of-range k selected to 0
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 4; ++q) {
+      const int k = kb + lk + 4 * q;
+      if constexpr (V4) {
+        const int kc = min(k, ld - 4);  // ld % 4 == 0: stays 16-byte aligned
+        pa[q] = *reinterpret_cast<const float4*>(rowA + kc);
+        pb[q] = *reinterpret_cast<const float4*>(rowB + kc);
+      } else {
         float ta[4], tb[4];
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
-          const int k = kb + lk + 4 * q + x;
-          const int kc = min(k, a.k1 - 1);
-          const float va = rowA[kc], vb = rowB[kc];
-          ta[x] = k < a.k1 ? va : 0.f;
-          tb[x] = k < a.k1 ? vb : 0.f;
+          const int kc = min(k + x, ld - 1);
+          ta[x] = rowA[kc];
+          tb[x] = rowB[kc];
         }
         pa[q] = make_float4(ta[0], ta[1], ta[2], ta[3]);
         pb[q] = make_float4(tb[0], tb[1], tb[2], tb[3]);
       }
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, int kb) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      As[buf][lr][lk + 4 * q + 0] = pa[q].x; As[buf][lr][lk + 4 * q + 1] = pa[q].y;
-      As[buf][lr][lk + 4 * q + 2] = pa[q].z; As[buf][lr][lk + 4 * q + 3] = pa[q].w;
-      Bs[buf][lr][lk + 4 * q + 0] = pb[q].x; Bs[buf][lr][lk + 4 * q + 1] = pb[q].y;
-      Bs[buf][lr][lk + 4 * q + 2] = pb[q].z; Bs[buf][lr][lk + 4 * q + 3] = pb[q].w;
+      const int k = kb + lk + 4 * q;
+      // select, not multiply: entries past k1 may hold any bit pattern
+      const bool m0 = k + 0 < a.k1, m1 = k + 1 < a.k1, m2 = k + 2 < a.k1, m3 = k + 3 < a.k1;
+      As[buf][lr][lk + 4 * q + 0] = m0 ? pa[q].x : 0.f;
+      As[buf][lr][lk + 4 * q + 1] = m1 ? pa[q].y : 0.f;
+      As[buf][lr][lk + 4 * q + 2] = m2 ? pa[q].z : 0.f;
+      As[buf][lr][lk + 4 * q + 3] = m3 ? pa[q].w : 0.f;
+      Bs[buf][lr][lk + 4 * q + 0] = m0 ? pb[q].x : 0.f;
+      Bs[buf][lr][lk + 4 * q + 1] = m1 ? pb[q].y : 0.f;
+      Bs[buf][lr][lk + 4 * q + 2] = m2 ? pb[q].z : 0.f;
+      Bs[buf][lr][lk + 4 * q + 3] = m3 ? pb[q].w : 0.f;
     }
   };
   floatx16 acc[2][2];
@@ -470,6 +501,20 @@ __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[x][y][v] = 0.f;
+  auto mma = [&](int buf) {
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 2) {
+      float av[2], bv[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) av[x] = As[buf][wr * 64 + x * 32 + (lane & 31)][kk + (lane >> 5)];
+#pragma unroll
+      for (int y = 0; y < 2; ++y) bv[y] = Bs[buf][wc * 64 + y * 32 + (lane & 31)][kk + (lane >> 5)];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[x], bv[y], acc[x][y], 0, 0, 0);
+    }
+  };
   // epilogue reads of accumulator tile q = 2 x + y (issued ahead of use)
   auto load_old = [&](int q, float* o) {
     const int x = q >> 1, y = q & 1;
@@ -485,34 +530,40 @@ __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int i = ib + (v >> 2) * 8 + (v & 3);
-      if (syrk_in(U, i, j, a, c1e)) F[(long long)i * ld + j] = o[v] - c[v];
+      if (syrk_in(Ue, i, j, a, c1e)) F[(long long)i * ld + j] = o[v] - c[v];
     }
   };
-  float o0[16], o1[16];
-  load(a.k0);
-  store(0);
-  __syncthreads();
-  int buf = 0;
-  for (int kb = a.k0; kb < a.k1; kb += KC) {
-    const bool more = kb + KC < a.k1;  // uniform
-    if (more) load(kb + KC);
-    else load_old(0, o0);  // last chunk: the first epilogue reads overlap its MFMAs
+  // a wave whose 64 x 64 block lies strictly above the diagonal (the upper
+  // right block of a diagonal tile) stores no block: it forms the load row
+  const bool active = i0 + wr * 64 + 63 >= j0 + wc * 64;  // wave-uniform
+  float racc[2] = {0.f, 0.f};
+  auto rhs = [&](int buf) {
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 2) {
-      float av[2], bv[2];
-#pragma unroll
-      for (int x = 0; x < 2; ++x) av[x] = As[buf][wr * 64 + x * 32 + (lane & 31)][kk + (lane >> 5)];
-#pragma unroll
-      for (int y = 0; y < 2; ++y) bv[y] = Bs[buf][wc * 64 + y * 32 + (lane & 31)][kk + (lane >> 5)];
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[x], bv[y], acc[x][y], 0, 0, 0);
+    for (int kk = 0; kk < KC; ++kk) {
+      const float zk = As[buf][128][kk];
+      racc[0] += zk * Bs[buf][lane][kk];
+      racc[1] += zk * Bs[buf][64 + lane][kk];
     }
-    if (more) store(buf ^ 1);
+  };
+  load(a.k0);
+  store(0, a.k0);
+  __syncthreads();
+  int buf = 0, kb = a.k0;
+  for (; kb + KC < a.k1; kb += KC) {
+    load(kb + KC);
+    // keep the prefetch ahead of the MFMAs (the scheduler would otherwise
+    // sink the loads next to their LDS stores)
+    __builtin_amdgcn_sched_barrier(0);
+    mma(buf);
+    __builtin_amdgcn_sched_barrier(0);
+    store(buf ^ 1, kb + KC);
     __syncthreads();
     buf ^= 1;
   }
+  float o0[16], o1[16];
+  load_old(0, o0);  // the first epilogue reads overlap the last chunk's MFMAs
+  __builtin_amdgcn_sched_barrier(0);
+  mma(buf);
   // epilogue, software pipelined: reads of the next accumulator tile are in
   // flight while the current one is written
   load_old(1, o1);
@@ -523,6 +574,37 @@ __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int
   store_new(2, o0, acc[1][0]);
   store_new(3, o1, acc[1][1]);
 }
+
+__global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int n_samples) {
+  constexpr int TM = 128;
+  __shared__ float As[2][TM][33];
+  __shared__ float Bs[2][TM][33];
+  // XCD-aware order: workgroup b runs on XCD b % 8; all tiles of one (node,
+  // sample) frame go to the same XCD in consecutive order, so its panel
+  // columns stay in that XCD's L2 while its tiles are computed.
+  const int n_pairs = L.n_nodes * n_samples;
+  const int n_tiles = a.tiles_r * a.tiles_c;
+  const int b = blockIdx.x;
+  const int loc = b >> 3;
+  const int pair = (loc / n_tiles) * 8 + (b & 7);
+  if (pair >= n_pairs) return;
+  const int tile = loc % n_tiles;
+  const int node = pair / n_samples, s = pair % n_samples;
+  const DevNode nd = L.nodes[node];
+  const int U = nd.U;
+  const int Ue = U;
+  const int c1e = a.c1 < 0 ? U + 1 : a.c1;
+  const int ti = tile / a.tiles_c, tj = tile % a.tiles_c;
+  const int i0 = a.r0 + ti * TM, j0 = a.c0 + tj * TM;
+  if (i0 > Ue || j0 >= c1e || i0 + TM - 1 < j0) return;
+  float* F = frame_ptr<float>(L, node, s);
+  const int ld = nd.ld;
+  if ((ld % 4) == 0 && (a.k0 % 4) == 0)  // uniform per workgroup
+    syrk128_tile<true>(As, Bs, F, ld, U, Ue, i0, j0, a, c1e);
+  else
+    syrk128_tile<false>(As, Bs, F, ld, U, Ue, i0, j0, a, c1e);
+}
+
 
 // ---------------------------------------------------------------------------
 // Fused merge of one node for narrow interfaces (gamma <= GP - 1, float32,
@@ -670,8 +752,10 @@ __global__ void __launch_bounds__(NT) k_merge_small(DevLevel F, DevLevel S, int 
       if (c < g && c <= r) Fo[(long long)r * ld + c] = P[r * KP + c];
     }
   }
-  // 4. Schur update tiles over rows / columns g..U (lower tiles only)
-  const int nt = (n - g + 31) / 32;
+  // 4. Schur update tiles over rows / columns g..U-1 (lower tiles only); the
+  // load row U follows in step 5 (as its own tile row it would cost a whole
+  // row of tiles)
+  const int nt = (n - 1 - g + 31) / 32;
   for (int t = wv; t < nt * (nt + 1) / 2; t += NW) {
     const int ti = tri_row(t), tj = t - ti * (ti + 1) / 2;
     const int i0 = g + ti * 32, j0 = g + tj * 32;
@@ -694,8 +778,17 @@ __global__ void __launch_bounds__(NT) k_merge_small(DevLevel F, DevLevel S, int 
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int i = i0 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-      if (i < n && j <= i) Fo[(long long)i * ld + j] = va[v] + vb[v] - acc[v];
+      if (i < n - 1 && j <= i) Fo[(long long)i * ld + j] = va[v] + vb[v] - acc[v];
     }
+  }
+  // 5. the load row: g_omega = g~ - P z (eq. SchurC1), one column per thread
+  for (int j = g + tid; j < n; j += NT) {
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < GP; ++k) acc += P[U * KP + k] * P[j * KP + k];
+    float va, vb;
+    gather(U, j, va, vb);
+    Fo[(long long)U * ld + j] = va + vb - acc;
   }
 }
 
@@ -816,40 +909,43 @@ hipError_t launch_panel(const DevLevel& L, int k0, int kb, int n_samples, int* i
 bool syrk_uses_big_tile(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, bool mfma) {
   const int rows = L.max_U + 1 - r0;
   const int cols = (c1 < 0 ? L.max_U + 1 : c1) - c0;
-  if (k1 - k0 < 96 && rows >= 384) return false;
+  if (k1 - k0 < 96) return false;
   return mfma && !L.is_double && k1 > k0 && rows >= 192 && cols >= 128 && (k0 % 4) == 0 && L.max_U + 1 >= 64;
 }
 
 hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, int n_samples, bool mfma,
                        hipStream_t st) {
   if (k1 <= k0) return hipSuccess;
-  SyrkArgs a{k0, k1, r0, c0, c1, 0, 0};
+  SyrkArgs a{k0, k1, r0, c0, c1, 0, 0, 0};
   const int rows = L.max_U + 1 - r0;
   const int cols = (c1 < 0 ? L.max_U + 1 : c1) - c0;
   if (rows <= 0 || cols <= 0) return hipSuccess;
   const bool big = syrk_uses_big_tile(L, k0, k1, r0, c0, c1, mfma);
   const int TM = big ? 128 : 64;
-  const int tr = ceil_div(rows, TM);
-  a.tiles_c = ceil_div(cols, TM);
+  // the matrix-core tiles cover rows r0 .. U-1; the load row U is formed by
+  // the idle wave of the diagonal tiles
+  a.sep = (mfma && !big) ? 1 : 0;
+  const int tr = ceil_div(rows - a.sep, TM);
+  a.tiles_c = ceil_div(c1 < 0 ? cols - a.sep : cols, TM);
   a.tiles_r = tr;
-  dim3 grid(L.n_nodes * n_samples, tr * a.tiles_c), block(256);
-  if (big) {
-    const long long pairs8 = (long long)ceil_div(L.n_nodes * n_samples, 8) * 8;
-    const long long nwg = pairs8 * tr * a.tiles_c;
-    if (nwg > 0x7fffffffll) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_syrk128_f32, dim3(unsigned(nwg)), block, 0, st, L, a, n_samples);
-    return hipGetLastError();
-  }
-  if (L.is_double) {
-    if (mfma)
-      hipLaunchKernelGGL(k_syrk_mfma_f64, grid, block, 0, st, L, a, n_samples);
-    else
-      hipLaunchKernelGGL(k_syrk_simple<double>, grid, block, 0, st, L, a, n_samples);
-  } else {
-    if (mfma)
-      hipLaunchKernelGGL(k_syrk_mfma_f32, grid, block, 0, st, L, a, n_samples);
-    else
-      hipLaunchKernelGGL(k_syrk_simple<float>, grid, block, 0, st, L, a, n_samples);
+  if (tr > 0 && a.tiles_c > 0) {
+    dim3 grid(L.n_nodes * n_samples, tr * a.tiles_c), block(256);
+    if (big) {
+      const long long pairs8 = (long long)ceil_div(L.n_nodes * n_samples, 8) * 8;
+      const long long nwg = pairs8 * tr * a.tiles_c;
+      if (nwg > 0x7fffffffll) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(k_syrk128_f32, dim3(unsigned(nwg)), block, 0, st, L, a, n_samples);
+    } else if (L.is_double) {
+      if (mfma)
+        hipLaunchKernelGGL(k_syrk_mfma_f64, grid, block, 0, st, L, a, n_samples);
+      else
+        hipLaunchKernelGGL(k_syrk_simple<double>, grid, block, 0, st, L, a, n_samples);
+    } else {
+      if (mfma)
+        hipLaunchKernelGGL(k_syrk_mfma_f32, grid, block, 0, st, L, a, n_samples);
+      else
+        hipLaunchKernelGGL(k_syrk_simple<float>, grid, block, 0, st, L, a, n_samples);
+    }
   }
   return hipGetLastError();
 }
