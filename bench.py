@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--config", default="c2_1023")
     ap.add_argument("--precision", default="fp32_refine", choices=["fp32_refine", "fp64"])
     ap.add_argument("--no-comparator", action="store_true")

@@ -70,6 +70,11 @@ extern "C" {
                                      the blocks too: a cross-check of the matrix-core lane layouts */
 #define HDD_FLAG_KEEP_DIRICHLET 2 /* plan only: keep outer-boundary nodes in every Gamma */
 #define HDD_FLAG_BLOCK8 4         /* eliminate leaf interiors in 8 x 8-cell blocks (default 16 x 16) */
+#define HDD_FLAG_KEEP_FRAMES 8    /* keep every node's whole frame (its Schur complement S_omega) after the
+                                     build, for hdd_debug_node_schur / hdd_debug_frame.  By default only
+                                     the retained factors of every node stay (Section 3.4: the sons' Schur
+                                     complements are not needed once the father is built) and frame memory
+                                     is reused by every second level */
 
 typedef struct hdd_opts {
   int32_t n;               /* N, interior nodes per side */
@@ -118,9 +123,9 @@ int hdd_create(const hdd_opts* opts, int32_t max_samples, void* stream, void* wo
  *   stream  hipStream_t for all work (NULL: the null stream)
  * Limits and sharing:
  *  - hdd_workspace_size(opts, max_samples) must be at most
- *    HDD_STATIC_WORKSPACE_BYTES (64 MiB: e.g. 63^2 with 24 samples, 127^2 with
- *    4 in float64 or 7 in float32 + refinement), else HDD_ENOMEM and nothing
- *    is created.
+ *    HDD_STATIC_WORKSPACE_BYTES (64 MiB: e.g. 127^2 with 5 samples in float64
+ *    or 10 in float32 + refinement, 255^2 with 1 or 2), else HDD_ENOMEM and
+ *    nothing is created.
  *  - All static handles of one GPU share its array, so at most one lives per
  *    GPU at a time: HDD_ESTATE while another exists (after hdd_destroy the
  *    next one may be created).  The array keeps the previous handle's
@@ -323,14 +328,16 @@ int hdd_plan_node(const hdd_opts* opts, int32_t depth, int32_t index, int32_t in
  * out[3] 1 if the level is float64 in this precision mode.  Host-only. */
 int hdd_plan_level(const hdd_opts* opts, int32_t depth, int32_t out[4]);
 
-/* Schur complement data of one built node: S (host float64 [|Gamma|+1]^2,
+/* Schur complement data of one built node (handles created with
+ * HDD_FLAG_KEEP_FRAMES; HDD_ESTATE otherwise): S (host float64 [|Gamma|+1]^2,
  * row-major, full symmetric, last row/column = condensed load g_omega and
  * its transpose, corner undefined) and ids (host, |Gamma| global node ids).
  * After the build S is the Schur complement S_omega = Psi^g_omega on the
  * node's boundary (Section 2.4).  Synchronizes. */
 int hdd_debug_node_schur(hdd_handle h, int32_t sample, int32_t depth, int32_t index, double* S, int32_t* ids);
 
-/* Raw frame of one built node (lower triangle, [gamma ; Gamma ; rhs] order,
+/* Raw frame of one built node (HDD_FLAG_KEEP_FRAMES; HDD_ESTATE otherwise)
+ * (lower triangle, [gamma ; Gamma ; rhs] order,
  * upper triangle returned as zeros): out host float64 [(U+1)^2] with room for
  * the largest frame of the level; *U_out = U.  The first gamma columns are the
  * retained [L ; P ; z] (read from the level's panel store where it has one).

@@ -66,9 +66,14 @@ bool merge_level(const Plan& p, const hdd_opts& o, int d) {
   return hdd::merge_small_ok(t, true) && !level_double(o, d + 1);
 }
 
+bool keep_frames(const hdd_opts& o) { return (o.flags & HDD_FLAG_KEEP_FRAMES) != 0; }
+
+// Row stride of a panel store: gamma rounded up to 4 elements (16-byte rows).
+int panel_ld(int g) { return (g + 3) / 4 * 4; }
+
 int64_t panel_elems(const Plan& p, int d) {
   int64_t e = 0;
-  for (const auto& nd : p.levels[d].nodes) e += int64_t(nd.U() + 1) * p.levels[d].gam;
+  for (const auto& nd : p.levels[d].nodes) e += int64_t(nd.U() + 1) * panel_ld(p.levels[d].gam);
   return e;
 }
 
@@ -102,17 +107,32 @@ Layout make_layout(const Plan& p, const hdd_opts& o, int ms) {
   const int nd = int(p.levels.size());
   L.frames.resize(nd); L.nodes.resize(nd); L.maps.resize(nd); L.ids.resize(nd); L.vec.resize(nd); L.panel.resize(nd);
   const bool refine = refinement_possible(o);
+  const bool keep = keep_frames(o);
+  // Frames: by default two buffers, level d in buffer d % 2.  A level's
+  // frames are written by its extend-add (or the block build) and read by
+  // its own elimination and by the father's extend-add; by the time level
+  // d - 2 writes the buffer, level d is consumed.  Every level above the
+  // blocks keeps its retained columns [L ; P ; z] in its panel store.
+  int64_t pingpong[2] = {-1, -1};
+  if (!keep) {
+    int64_t need[2] = {0, 0};
+    for (int d = 0; d < nd; ++d)
+      need[d % 2] = std::max<int64_t>(need[d % 2], p.levels[d].frame_elems * (level_double(o, d) ? 8 : 4) * ms);
+    pingpong[0] = take(need[0]);
+    pingpong[1] = take(need[1]);
+  }
   int64_t total_nodes = 0, max_nodes = 0;
   for (int d = 0; d < nd; ++d) {
     const auto& lv = p.levels[d];
     const int64_t esz = level_double(o, d) ? 8 : 4;
-    L.frames[d] = take(lv.frame_elems * esz * ms);
+    L.frames[d] = keep ? take(lv.frame_elems * esz * ms) : pingpong[d % 2];
     L.nodes[d] = take(int64_t(lv.nodes.size()) * int64_t(sizeof(DevNode)));
     L.maps[d] = take(int64_t(lv.maps.size()) * 4);
     L.ids[d] = take(int64_t(lv.ids.size()) * 4);
     // forward-pass vectors: refinement, and the functional propagation of the node means
     L.vec[d] = take(int64_t(lv.ids.size()) * 8 * ms);
-    L.panel[d] = merge_level(p, o, d) ? take(panel_elems(p, d) * 4 * ms) : -1;
+    const bool store = d < nd - 1 && (!keep || merge_level(p, o, d));
+    L.panel[d] = store ? take(panel_elems(p, d) * esz * ms) : -1;
     total_nodes += int64_t(lv.nodes.size());
     max_nodes = std::max<int64_t>(max_nodes, int64_t(lv.nodes.size()));
   }
@@ -565,7 +585,7 @@ int create_impl(const hdd_opts* o, int32_t max_samples, void* stream, void* work
     for (size_t k = 0; k < pl.nodes.size(); ++k) {
       const auto& p = pl.nodes[k];
       dn[k].panel_off = poff;
-      poff += int64_t(p.U() + 1) * pl.gam;
+      poff += int64_t(p.U() + 1) * panel_ld(pl.gam);
       dn[k].frame_off = p.frame_off;
       dn[k].map_off = p.map_off;
       dn[k].U = p.U();
@@ -582,6 +602,7 @@ int create_impl(const hdd_opts* o, int32_t max_samples, void* stream, void* work
     lv.stride = pl.frame_elems;
     lv.panel = L.panel[d] >= 0 ? h->ws + L.panel[d] : nullptr;
     lv.panel_stride = L.panel[d] >= 0 ? panel_elems(h->plan, d) : 0;
+    lv.panel_ld = panel_ld(pl.gam);
     lv.nodes = reinterpret_cast<const DevNode*>(h->ws + L.nodes[d]);
     lv.maps = reinterpret_cast<const int*>(h->ws + L.maps[d]);
     lv.ids = reinterpret_cast<const int*>(h->ws + L.ids[d]);
@@ -653,6 +674,16 @@ int create_impl(const hdd_opts* o, int32_t max_samples, void* stream, void* work
         hdd::block_forward_lds(B, bdbl) > 160 * 1024)
       return fail(HDD_EINVAL);
   }
+  // panel stores: the entries above the diagonal of L are never written by a
+  // build and must read as zero
+  for (int d = 0; d < nd; ++d)
+    if (L.panel[d] >= 0) {
+      const int64_t bytes = panel_elems(h->plan, d) * (h->lev[d].is_double ? 8 : 4) * max_samples;
+      if (hdd::launch_fill(reinterpret_cast<double*>(h->ws + L.panel[d]), (bytes + 7) / 8, 0.0, h->st) !=
+          hipSuccess)
+        return fail(HDD_EDEVICE);
+    }
+  if (hipStreamSynchronize(h->st) != hipSuccess) return fail(HDD_EDEVICE);
   h->nn = (long long)(h->plan.nc + 1) * (h->plan.nc + 1);
   h->kappa = reinterpret_cast<double*>(h->ws + L.kappa);
   h->f = reinterpret_cast<double*>(h->ws + L.f);
@@ -1189,7 +1220,7 @@ int hdd_plan_level(const hdd_opts* o, int32_t depth, int32_t out[4]) {
 
 int hdd_debug_node_schur(hdd_handle h, int32_t sample, int32_t depth, int32_t index, double* S, int32_t* ids) {
   if (!h || !S || !ids) return HDD_EINVAL;
-  if (!h->built) return HDD_ESTATE;
+  if (!h->built || !keep_frames(h->opt)) return HDD_ESTATE;
   if (sample < 0 || sample >= h->n_samples || depth < 0 || depth >= int(h->lev.size())) return HDD_EINVAL;
   const auto& pl = h->plan.levels[depth];
   if (index < 0 || index >= int(pl.nodes.size())) return HDD_EINVAL;
@@ -1216,7 +1247,7 @@ int hdd_debug_node_schur(hdd_handle h, int32_t sample, int32_t depth, int32_t in
 
 int hdd_debug_frame(hdd_handle h, int32_t sample, int32_t depth, int32_t index, double* out, int32_t* U_out) {
   if (!h || !out || !U_out) return HDD_EINVAL;
-  if (!h->built) return HDD_ESTATE;
+  if (!h->built || !keep_frames(h->opt)) return HDD_ESTATE;
   if (sample < 0 || sample >= h->n_samples || depth < 0 || depth >= int(h->lev.size())) return HDD_EINVAL;
   const auto& pl = h->plan.levels[depth];
   if (index < 0 || index >= int(pl.nodes.size())) return HDD_EINVAL;
@@ -1236,16 +1267,20 @@ int hdd_debug_frame(hdd_handle h, int32_t sample, int32_t depth, int32_t index, 
                                                   : double(reinterpret_cast<const float*>(buf.data())[k]))
                                           : 0.0;
     }
-  if (h->lev[depth].panel) {  // retained columns kept in the level's panel store (float32)
-    const int g = pl.gam;
+  if (h->lev[depth].panel) {  // retained columns kept in the level's panel store
+    const int g = pl.gam, pld = panel_ld(g);
     int64_t poff = 0;
-    for (int k = 0; k < index; ++k) poff += int64_t(pl.nodes[k].U() + 1) * g;
-    std::vector<float> pan(size_t(n) * g);
-    const float* psrc = static_cast<const float*>(h->lev[depth].panel) +
-                        size_t(sample) * h->lev[depth].panel_stride + size_t(poff);
-    HIP_TRY(hipMemcpy(pan.data(), psrc, pan.size() * sizeof(float), hipMemcpyDeviceToHost));
+    for (int k = 0; k < index; ++k) poff += int64_t(pl.nodes[k].U() + 1) * pld;
+    std::vector<char> pan(size_t(n) * pld * esz);
+    const char* psrc = static_cast<const char*>(h->lev[depth].panel) +
+                       (size_t(sample) * h->lev[depth].panel_stride + size_t(poff)) * esz;
+    HIP_TRY(hipMemcpy(pan.data(), psrc, pan.size(), hipMemcpyDeviceToHost));
     for (int r = 0; r < n; ++r)
-      for (int c = 0; c < g && c <= r; ++c) out[size_t(r) * n + c] = double(pan[size_t(r) * g + c]);
+      for (int c = 0; c < g && c <= r; ++c) {
+        const size_t k = size_t(r) * pld + c;
+        out[size_t(r) * n + c] = dbl ? reinterpret_cast<const double*>(pan.data())[k]
+                                     : double(reinterpret_cast<const float*>(pan.data())[k]);
+      }
   }
   *U_out = n - 1;
   return HDD_OK;

@@ -33,12 +33,14 @@ struct DevNode {
 struct DevLevel {
   void* frames;          // float* or double*
   long long stride;      // per-sample elements of this level
-  // Levels built by the fused merge keep the retained columns [L ; P ; z] of
-  // every node in a dense panel store, (U+1) x gamma per node with row stride
-  // gamma, instead of in the frame's first gamma columns (the sweeps then
-  // read contiguous rows).  nullptr elsewhere.
+  // Panel store: the retained columns [L ; P ; z] of every node, (U+1) x
+  // gamma per node with row stride panel_ld (zero above the diagonal of L), kept
+  // after the build while the frames are reused; the sweeps read contiguous
+  // rows.  nullptr for the block level, and, in handles that keep all frames,
+  // for the levels whose frames hold the retained columns.
   void* panel;
   long long panel_stride;  // per-sample elements of the panel store
+  int panel_ld;            // row stride of the panel store: gamma rounded up to 4 (16-byte rows)
   const DevNode* nodes;
   const int* maps;
   const int* ids;
@@ -87,11 +89,16 @@ template <typename T> __device__ __forceinline__ T* frame_ptr(const DevLevel& L,
   return reinterpret_cast<T*>(L.frames) + (long long)s * L.stride + L.nodes[node].frame_off;
 }
 
+// A node's block of the level's panel store ((U+1) x gamma, row stride panel_ld).
+template <typename T> __device__ __forceinline__ T* panel_ptr(const DevLevel& L, int node, int s) {
+  return reinterpret_cast<T*>(L.panel) + (long long)s * L.panel_stride + L.nodes[node].panel_off;
+}
+
 // Retained columns [L ; P ; z] of a node and their row stride: the panel
 // store when the level has one, else the frame's first gamma columns.
 template <typename T> __device__ __forceinline__ T* retained_ptr(const DevLevel& L, int node, int s, int& ld) {
   if (L.panel) {
-    ld = L.gam;
+    ld = L.panel_ld;
     return reinterpret_cast<T*>(L.panel) + (long long)s * L.panel_stride + L.nodes[node].panel_off;
   }
   ld = L.nodes[node].ld;

@@ -144,6 +144,12 @@ __global__ void __launch_bounds__(64) k_panel_diag(DevLevel L, int k0, int kb, i
 #pragma unroll
   for (int k = 0; k < NB; ++k)
     if (lane < kb && k <= lane) Dg[(long long)lane * ld + k] = a[k];
+  if (L.panel) {  // the final columns also go to the level's panel store
+    T* Pp = panel_ptr<T>(L, node, s) + (long long)(k0 + lane) * L.panel_ld + k0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+      if (lane < kb && k <= lane) Pp[k] = a[k];
+  }
   if (lane == 0 && bp && info) atomicCAS(info + s, 0, L.node_base + node + 1);
 }
 
@@ -211,6 +217,11 @@ __global__ void __launch_bounds__(PanelCfg<T>::RW) k_panel_rows(DevLevel L, int 
   }
   __syncthreads();
   for (int e = tid; e < total; e += RW) F[(long long)(r0 + e / kb) * ld + k0 + e % kb] = X[e / kb][e % kb];
+  if (L.panel) {  // the final columns also go to the level's panel store
+    T* Pp = panel_ptr<T>(L, node, s);
+    const int pld = L.panel_ld;
+    for (int e = tid; e < total; e += RW) Pp[(long long)(r0 + e / kb) * pld + k0 + e % kb] = X[e / kb][e % kb];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -745,7 +756,8 @@ __global__ void __launch_bounds__(NT) k_merge_small(DevLevel F, DevLevel S, int 
   // diagonal of L), or the frame's first gamma columns
   if (F.panel) {
     float* Po = reinterpret_cast<float*>(F.panel) + (long long)s * F.panel_stride + nd.panel_off;
-    for (int e = tid; e < n * g; e += NT) Po[e] = P[(e / g) * KP + e % g];
+    const int pld = F.panel_ld;
+    for (int e = tid; e < n * g; e += NT) Po[(e / g) * pld + e % g] = P[(e / g) * KP + e % g];
   } else {
     for (int e = tid; e < n * GP; e += NT) {
       const int r = e / GP, c = e % GP;

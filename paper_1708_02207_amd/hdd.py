@@ -30,6 +30,7 @@ HDD_MEM_DEVICE = 1
 HDD_FLAG_NO_MFMA = 1
 HDD_FLAG_KEEP_DIRICHLET = 2
 HDD_FLAG_BLOCK8 = 4
+HDD_FLAG_KEEP_FRAMES = 8
 
 EXPORTED = [
     "hdd_default_opts", "hdd_workspace_size", "hdd_create", "hdd_build", "hdd_query_points",

@@ -114,3 +114,13 @@ def test_precision_levels(H):
     assert not H.hdd_plan_level(o, 2)["fp64"]
     o = H.hdd_default_opts(255, H.HDD_FP64, leaf=16)
     assert all(H.hdd_plan_level(o, d)["fp64"] for d in range(H.hdd_plan_summary(o)["levels"]))
+
+
+def test_reused_frames_shrink_the_workspace(H):
+    """Only the retained factors of every node stay after the build (the
+    sons' Schur complements are dropped once the father is built): the
+    default workspace at 1023^2 is under half of one that keeps every frame."""
+    for prec in (0, 1):
+        o = H.hdd_default_opts(1023, prec)
+        keep = H.hdd_default_opts(1023, prec, flags=H.HDD_FLAG_KEEP_FRAMES)
+        assert H.hdd_workspace_size(o, 8) < 0.5 * H.hdd_workspace_size(keep, 8)

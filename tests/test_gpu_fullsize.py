@@ -5,7 +5,7 @@ The 255^2 configuration is checked on all 256 samples built in one batch; the
 mean over [0.25,0.5]^2).  A property that holds at any size certifies the
 float64 field at 1023^2: the extended-precision residual bounds its error.
 The refined float32 field is compared with that float64 field on every node;
-in the 32-sample batch the benchmark times every float64 field is certified
+in the 128-sample batch the benchmark times every float64 field is certified
 by its residual bound and the float32 path is compared against it.
 Tolerances (normwise relative): HDD_FP64 1e-10, HDD_FP32_REFINE 1e-8.
 """
@@ -120,15 +120,15 @@ def test_c2_1023(H, oracle_mod, prec):
 
 
 def test_c2_1023_bench_batch(H, oracle_mod):
-    """The bench's launch configuration (32 samples of the 1023^2 workload in
-    one batch, default options).  Every sample's float64 field is certified
+    """The bench's launch configuration (128 samples of the 1023^2 workload
+    in one batch, default options).  Every sample's float64 field is certified
     against the exact discrete solution by its extended-precision residual
     bound (a property that holds at any size: ||u - u_h||_2 <= ||b - A u||_2 /
     lambda_min(A)); every sample's measurements on the FP32 matrix-core +
     refinement path agree with that certified float64 path to 1e-8, and the
     first 4 samples with the stored oracle values."""
     g = gold("c2_1023")
-    B = 32
+    B = 128
     w = make_workload("c2_1023", n_samples=B)
     kd = torch.from_numpy(w.kappa).cuda()
     fd = torch.from_numpy(w.f).cuda()

@@ -134,7 +134,7 @@ def test_node_means_device_output_and_rebuild(H, oracle_mod):
 
 
 def test_node_means_1023_functional(H):
-    """1023^2, 32 x 32-cell leaves, the benchmark's batch of 32 samples: the
+    """1023^2, 32 x 32-cell leaves, the benchmark's batch of 128 samples: the
     functional route in float64 (8191 nodes per sample).  For the samples
     with stored oracle values the node [0.25, 0.5]^2 (depth 4) matches the
     oracle's stored mean; for all samples every father's mean is the
@@ -142,7 +142,7 @@ def test_node_means_1023_functional(H):
     means agree with the float32 + refinement path (direct route) to 1e-8."""
     with open(os.path.join(HERE, "golden", "c2_1023.json")) as fh:
         g = json.load(fh)
-    ns = 32
+    ns = 128
     w = make_workload("c2_1023", n_samples=ns)
     say("node means 1023^2 fp64 functional, samples", ns)
     kd = torch.from_numpy(w.kappa[:ns]).cuda()

@@ -89,7 +89,7 @@ def test_node_schur_bruteforce(H, oracle_mod, n, leaf, flags):
     O = oracle_mod
     kappa = np.random.default_rng(3).uniform(0.2, 5.0, size=(1, n + 1, n + 1, 2))
     f = np.random.default_rng(4).uniform(0.0, 1.0, size=(n + 2, n + 2))
-    o = H.hdd_default_opts(n, H.HDD_FP64, leaf=leaf, flags=flags)
+    o = H.hdd_default_opts(n, H.HDD_FP64, leaf=leaf, flags=flags | H.HDD_FLAG_KEEP_FRAMES)
     t = H.HDD(o, 1)
     t.build(kappa, f)
     nc = n + 1
@@ -134,7 +134,7 @@ def test_node_schur_fp32(H, oracle_mod, n, leaf):
     O = oracle_mod
     kappa = np.random.default_rng(5).uniform(0.2, 5.0, size=(1, n + 1, n + 1, 2))
     f = np.random.default_rng(6).uniform(0.0, 1.0, size=(n + 2, n + 2))
-    o = H.hdd_default_opts(n, H.HDD_FP32_REFINE, leaf=leaf)
+    o = H.hdd_default_opts(n, H.HDD_FP32_REFINE, leaf=leaf, flags=H.HDD_FLAG_KEEP_FRAMES)
     t = H.HDD(o, 1)
     t.build(kappa, f)
     nc = n + 1
@@ -253,3 +253,26 @@ def test_invalid_kappa(H):
     t.build(kd, fd)
     assert t.sync() == H.HDD_EINVAL
     t.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_reused_frames_match_kept_frames(H, prec):
+    """Handles that reuse frame memory across levels (the default: only the
+    retained factors of every node stay) give the same values, bit for bit,
+    as handles that keep every frame, and refuse the frame inspection calls."""
+    from workload import make_workload
+
+    w = make_workload("s_255", n_samples=3)
+    outs = []
+    for flags in (0, H.HDD_FLAG_KEEP_FRAMES):
+        o = H.hdd_default_opts(w.n, prec, leaf=w.leaf, flags=flags)
+        t = H.HDD(o, 3)
+        t.build(w.kappa, w.f)
+        outs.append((t.query_points(w.points), t.query_interface(2, 1), t.query_mean([0.25, 0.5, 0.25, 0.5])))
+        if flags == 0:
+            with pytest.raises(H.HddError) as e:
+                t.node_schur(0, 2, 0)
+            assert e.value.code == H.HDD_ESTATE
+        t.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)

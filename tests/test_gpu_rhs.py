@@ -128,13 +128,13 @@ def test_rhs_device_inputs(H, oracle_mod):
 
 
 def test_rhs_1023(H, oracle_mod):
-    """1023^2, 32 x 32-cell leaves, the benchmark's batch of 32 samples: the
+    """1023^2, 32 x 32-cell leaves, the benchmark's batch of 128 samples: the
     float64 field of sample 0 for a bump load with boundary data is certified
     by its extended-precision residual (computed with the oracle's lifted
     load), and for every sample the float32 + refinement field agrees with the
     float64 field to 1e-8 on every node."""
     O = oracle_mod
-    ns = 32
+    ns = 128
     w = make_workload("c2_1023", n_samples=ns)
     f = rhs_nodal(w.n, "bump")
     g = _boundary_data(w.n, 9)

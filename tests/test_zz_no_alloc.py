@@ -66,7 +66,7 @@ def test_static_workspace_limits():
     from paper_1708_02207_amd import hdd as H
 
     torch.cuda.set_device(0)
-    big = H.hdd_default_opts(255, H.HDD_FP64)
+    big = H.hdd_default_opts(511, H.HDD_FP64)
     assert H.hdd_workspace_size(big, 1) > H.STATIC_WORKSPACE_BYTES
     with pytest.raises(H.HddError) as e:
         H.HDD(big, 1, workspace="static")
