@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the float64 batched full / partial top-down steps reported beside the headline")
     ap.add_argument("--serve-requests", type=int, default=96, help="requests per arrival rate in the serving mix")
+    ap.add_argument("--no-graph", action="store_true", help="issue every launch eagerly (no captured HIP graphs)")
+    ap.add_argument("--no-autotune", action="store_true", help="built-in tile rule instead of the autotuner")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run 3 device-to-device copies of BYTES (calibrates HBM byte counters) and exit")
     return ap.parse_args()
@@ -169,7 +171,7 @@ def main():
     fd = torch.from_numpy(w.f).to(dev)
     yd = torch.from_numpy(y).to(dev)
     prec = H.HDD_FP32_REFINE if a.precision == "fp32_refine" else H.HDD_FP64
-    opts = H.hdd_default_opts(w.n, prec, leaf=w.leaf)
+    opts = H.hdd_default_opts(w.n, prec, leaf=w.leaf, flags=H.HDD_FLAG_NO_GRAPH if a.no_graph else 0)
     t = H.HDD(opts, a.batch, stream=stream)
     B = a.batch
     ll = torch.empty(B, dtype=torch.float64, device=dev)
@@ -187,6 +189,9 @@ def main():
         H._check(H._lib.hdd_query_mean(t.h, H._np_ptr(rect), H.ctypes.c_void_p(mean.data_ptr()), H.HDD_MEM_DEVICE),
                  "hdd_query_mean")
 
+    step()
+    # per-level tile choices of the Schur updates, timed on this GPU
+    tiles = None if a.no_autotune else t.autotune(1).tolist()
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
@@ -201,6 +206,7 @@ def main():
     dt = time.perf_counter() - t0
     code = t.sync()
     est, sweeps = t.error_estimate()
+    graphs = t.graph_info()
 
     # accuracy of this run's outputs against the stored oracle values
     err = None
@@ -385,6 +391,12 @@ def main():
         "accuracy": {"max_rel_err_vs_oracle": err, "refine_sweeps": sweeps,
                      "max_refine_estimate": float(np.max(est)) if len(est) else None, "status": H.strerror(code)},
         "roofline": roofline,
+        "launches": {"build_graph_nodes": graphs["build_nodes"], "solve_graph_nodes": graphs["solve_nodes"],
+                     "sweep_graph_nodes": graphs["sweep_nodes"], "graph_launches_per_step":
+                         graphs["launches"] / max(1, a.steps + a.warmup + 1),
+                     "note": "kernel launches per step = build + solve + sweeps x sweep graph nodes, "
+                             "replayed from captured HIP graphs"},
+        "autotune_tiles": tiles,
         "ablation": ablation,
         "node_means": node_means,
         "multi_rhs": multi_rhs,

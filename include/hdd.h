@@ -70,6 +70,7 @@ extern "C" {
                                      the blocks too: a cross-check of the matrix-core lane layouts */
 #define HDD_FLAG_KEEP_DIRICHLET 2 /* plan only: keep outer-boundary nodes in every Gamma */
 #define HDD_FLAG_BLOCK8 4         /* eliminate leaf interiors in 8 x 8-cell blocks (default 16 x 16) */
+#define HDD_FLAG_NO_GRAPH 16      /* issue every launch eagerly instead of replaying captured HIP graphs */
 #define HDD_FLAG_KEEP_FRAMES 8    /* keep every node's whole frame (its Schur complement S_omega) after the
                                      build, for hdd_debug_node_schur / hdd_debug_frame.  By default only
                                      the retained factors of every node stay (Section 3.4: the sons' Schur
@@ -298,6 +299,29 @@ int hdd_get_solution(hdd_handle h, int32_t sample, double* u_out, int32_t mem);
  * ran.  Each sample stops refining on its own once its predicted error is
  * below refine_tol (later corrections of the batch are not applied to it). */
 int hdd_error_estimate(hdd_handle h, double* rel_est, int32_t* sweeps);
+
+/*
+ * Autotuner for the Schur updates (a6): on the kappa and load of the last
+ * hdd_build, every float32 matrix-core level's updates are timed with HIP
+ * events on the 64 x 64 tile kernel and on the 128 x 128 tile kernel, reps
+ * builds each, and each level keeps the faster for later builds (replacing
+ * the built-in rule: 128 x 128 for K >= 96 on large frames).  The handle is
+ * left built with the chosen tiles.  choices (host int32 [levels], may be
+ * NULL): per level 64 or 128, or 0 where the level has no choice (float64
+ * levels, fused narrow merges, the blocks).  Errors: HDD_ESTATE before a
+ * build, HDD_EINVAL (reps < 1, or a handle from hdd_create_static).
+ */
+int hdd_autotune(hdd_handle h, int32_t reps, int32_t* choices);
+
+/*
+ * Captured launch sequences: the build, the first full Root to Leaves and
+ * each refinement sweep are captured once per sample count as HIP graphs and
+ * replayed (unless HDD_FLAG_NO_GRAPH, timing is enabled, or the handle comes
+ * from hdd_create_static).  out (host int64 [4]): nodes of the build graph,
+ * of the full Root to Leaves graph and of the sweep graph for the current
+ * sample count (0 if not captured), and graph launches so far.
+ */
+int hdd_graph_info(hdd_handle h, int64_t out[4]);
 
 /* Wait for the handle's stream and report deferred device-side errors. */
 int hdd_sync(hdd_handle h);

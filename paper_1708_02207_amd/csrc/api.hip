@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -212,6 +213,17 @@ struct hdd_tree {
   std::vector<int> sstat;         // per-sample refinement status (HDD_OK / HDD_ENOTCONVERGED)
   std::vector<int> act_host;      // samples still refining
   int* act = nullptr;             // device copy of act_host
+  // captured launch sequences (HIP graphs), replayed while n_samples and the
+  // tile choices are unchanged: the build, the first full Root to Leaves, one
+  // refinement sweep
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    int64_t nodes = 0;
+  };
+  using Graphs = std::map<int, Graph>;  // by sample count (a server batch varies it)
+  Graphs g_build, g_solve, g_sweep;
+  int64_t graph_launches = 0;
+  std::vector<int> tile;          // per level: Schur-update tile (0 rule, 64, 128), set by hdd_autotune
   int last_node = 0;
   int deferred = HDD_OK;
   // timing
@@ -254,6 +266,55 @@ int timed(hdd_tree* h, int kind, double flops, F&& launch, double bytes = 0.0) {
   HIP_TRY(hipEventRecord(b, h->st));
   h->recs.push_back({kind, h->cur_level, a, b, flops, bytes});
   return HDD_OK;
+}
+
+bool graphs_on(const hdd_tree* h) {
+  // timing brackets launches with events; a handle that may not allocate
+  // does not instantiate graphs; capture needs a stream other than the null one
+  return !(h->opt.flags & HDD_FLAG_NO_GRAPH) && h->timing_mask == 0 && !h->no_alloc && h->st != nullptr;
+}
+
+void drop_graphs(hdd_tree::Graphs& gs) {
+  for (auto& kv : gs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  gs.clear();
+}
+
+void drop_graphs(hdd_tree* h) {
+  drop_graphs(h->g_build);
+  drop_graphs(h->g_solve);
+  drop_graphs(h->g_sweep);
+}
+
+// Runs `body` (device work on h->st only: kernel launches, no host
+// synchronization or host copies) through a captured HIP graph, captured on
+// the first call for the current sample count and replayed afterwards; eager
+// when graphs are off.
+template <typename F>
+int run_graph(hdd_tree* h, hdd_tree::Graphs& gs, F&& body) {
+  if (!graphs_on(h)) return body();
+  auto it = gs.find(h->n_samples);
+  if (it == gs.end()) {
+    if (gs.size() >= 64) drop_graphs(gs);  // bounded cache
+    HIP_TRY(hipStreamBeginCapture(h->st, hipStreamCaptureModeRelaxed));
+    const int rc = body();
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->st, &graph);
+    if (rc != HDD_OK || e != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc != HDD_OK ? rc : HDD_EDEVICE;
+    }
+    size_t n = 0;
+    (void)hipGraphGetNodes(graph, nullptr, &n);
+    hdd_tree::Graph g;
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return HDD_EDEVICE;
+    g.nodes = int64_t(n);
+    it = gs.emplace(h->n_samples, g).first;
+  }
+  ++h->graph_launches;
+  return hip_status(hipGraphLaunch(it->second.exec, h->st));
 }
 
 // lower-triangle elements (i, j) with r0 <= i <= U, c0 <= j < c1e, j <= i
@@ -301,8 +362,11 @@ int check_deferred(hdd_tree* h) {
   HIP_TRY(hipStreamSynchronize(h->st));
   if (!h->built) return h->deferred;
   std::vector<int> info(h->n_samples), bad(h->n_samples);
-  HIP_TRY(hipMemcpy(info.data(), h->info, sizeof(int) * h->n_samples, hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(bad.data(), h->bad, sizeof(int) * h->n_samples, hipMemcpyDeviceToHost));
+  // copies on the handle's stream: no legacy-stream operation that could
+  // disturb a capture running on another handle's stream
+  HIP_TRY(hipMemcpyAsync(info.data(), h->info, sizeof(int) * h->n_samples, hipMemcpyDeviceToHost, h->st));
+  HIP_TRY(hipMemcpyAsync(bad.data(), h->bad, sizeof(int) * h->n_samples, hipMemcpyDeviceToHost, h->st));
+  HIP_TRY(hipStreamSynchronize(h->st));
   for (int s = 0; s < h->n_samples; ++s)
     if (bad[s]) return HDD_EINVAL;
   for (int s = 0; s < h->n_samples; ++s)
@@ -352,20 +416,24 @@ int correction_sweeps(hdd_tree* h, int max_it, bool test) {
   h->act_host.assign(ns, 1);
   int n_active = ns;
   for (int it = 0; it < max_it && n_active > 0; ++it) {
-    h->cur_level = -1;
-    HDD_TRY(timed(h, K_RESIDUAL, 0.0, [&] { return hdd::launch_residual(nc, ns, h->kappa, h->f, h->u, h->r, h->st); }));
-    h->cur_level = D;
-    HDD_TRY(timed(h, K_FORWARD, 0.0, [&] { return hdd::launch_block_forward(h->blk, ns, nc, h->r, h->nn, h->st); }));
-    for (int d = D - 1; d >= 0; --d) {
-      h->cur_level = d;
-      HDD_TRY(timed(h, K_FORWARD, 0.0, [&] { return hdd::launch_forward(h->lev[d], h->lev[d + 1], ns, h->st); }));
-    }
-    HIP_TRY(hdd::launch_fill(h->d, (long long)ns * h->nn, 0.0, h->st));
-    HDD_TRY(full_topdown(h, h->d, true));
-    // all-zero bits are +0.0: the fill kernel clears the max-norm words
-    HIP_TRY(hdd::launch_fill(reinterpret_cast<double*>(h->maxbits), 2LL * ns, 0.0, h->st));
+    // which samples still refine; read by the update at the end of the sweep
     HIP_TRY(hipMemcpyAsync(h->act, h->act_host.data(), sizeof(int) * ns, hipMemcpyHostToDevice, h->st));
-    HIP_TRY(hdd::launch_axpy_maxabs(nc, ns, h->u, h->d, h->maxbits, h->act, h->st));
+    HDD_TRY(run_graph(h, h->g_sweep, [&]() -> int {
+      h->cur_level = -1;
+      HDD_TRY(timed(h, K_RESIDUAL, 0.0,
+                    [&] { return hdd::launch_residual(nc, ns, h->kappa, h->f, h->u, h->r, h->st); }));
+      h->cur_level = D;
+      HDD_TRY(timed(h, K_FORWARD, 0.0, [&] { return hdd::launch_block_forward(h->blk, ns, nc, h->r, h->nn, h->st); }));
+      for (int d = D - 1; d >= 0; --d) {
+        h->cur_level = d;
+        HDD_TRY(timed(h, K_FORWARD, 0.0, [&] { return hdd::launch_forward(h->lev[d], h->lev[d + 1], ns, h->st); }));
+      }
+      HIP_TRY(hdd::launch_fill(h->d, (long long)ns * h->nn, 0.0, h->st));
+      HDD_TRY(full_topdown(h, h->d, true));
+      // all-zero bits are +0.0: the fill kernel clears the max-norm words
+      HIP_TRY(hdd::launch_fill(reinterpret_cast<double*>(h->maxbits), 2LL * ns, 0.0, h->st));
+      return hip_status(hdd::launch_axpy_maxabs(nc, ns, h->u, h->d, h->maxbits, h->act, h->st));
+    }));
     HIP_TRY(hipMemcpyAsync(mb.data(), h->maxbits, sizeof(unsigned long long) * 2 * ns, hipMemcpyDeviceToHost, h->st));
     HIP_TRY(hipStreamSynchronize(h->st));
     h->sweeps = it + 1;
@@ -407,7 +475,7 @@ int correction_sweeps(hdd_tree* h, int max_it, bool test) {
 
 int ensure_full(hdd_tree* h) {
   if (h->full) return HDD_OK;
-  HDD_TRY(full_topdown(h, h->u, false));
+  HDD_TRY(run_graph(h, h->g_solve, [&] { return full_topdown(h, h->u, false); }));
   for (auto& v : h->solved) std::fill(v.begin(), v.end(), 1);
   h->full = true;
   reset_refine_state(h);
@@ -572,6 +640,13 @@ int create_impl(const hdd_opts* o, int32_t max_samples, void* stream, void* work
         hipStreamSynchronize(h->st) != hipSuccess)
       return fail(HDD_EDEVICE);
   }
+  // host tables to the device on the handle's stream (the source vectors are
+  // live until the copy has completed)
+  auto upload = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    const hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->st);
+    return e != hipSuccess ? e : hipStreamSynchronize(h->st);
+  };
   const Layout& L = h->lay;
   const int nd = int(h->plan.levels.size());
   h->lev.resize(nd);
@@ -615,10 +690,9 @@ int create_impl(const hdd_opts* o, int32_t max_samples, void* stream, void* work
     lv.depth = d;
     lv.node_base = int(node_base);
     node_base += lv.n_nodes;
-    if (hipMemcpy(h->ws + L.nodes[d], dn.data(), dn.size() * sizeof(DevNode), hipMemcpyHostToDevice) != hipSuccess ||
-        (!pl.maps.empty() &&
-         hipMemcpy(h->ws + L.maps[d], pl.maps.data(), pl.maps.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
-        hipMemcpy(h->ws + L.ids[d], pl.ids.data(), pl.ids.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    if (upload(h->ws + L.nodes[d], dn.data(), dn.size() * sizeof(DevNode)) != hipSuccess ||
+        upload(h->ws + L.maps[d], pl.maps.data(), pl.maps.size() * 4) != hipSuccess ||
+        upload(h->ws + L.ids[d], pl.ids.data(), pl.ids.size() * 4) != hipSuccess)
       return fail(HDD_EDEVICE);
     h->lev_list_off[d] = list_off;
     list_off += lv.n_nodes;
@@ -656,11 +730,10 @@ int create_impl(const hdd_opts* o, int32_t max_samples, void* stream, void* work
       org.push_back(nd.x0);
       org.push_back(nd.y0);
     }
-    if ((!T.maps.empty() &&
-         hipMemcpy(h->ws + L.tmaps, T.maps.data(), T.maps.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
-        hipMemcpy(h->ws + L.tlids, T.lids.data(), T.lids.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(h->ws + L.tmicro, T.micro_xy.data(), T.micro_xy.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(h->ws + L.origin, org.data(), org.size() * 4, hipMemcpyHostToDevice) != hipSuccess)
+    if (upload(h->ws + L.tmaps, T.maps.data(), T.maps.size() * 4) != hipSuccess ||
+        upload(h->ws + L.tlids, T.lids.data(), T.lids.size() * 4) != hipSuccess ||
+        upload(h->ws + L.tmicro, T.micro_xy.data(), T.micro_xy.size() * 4) != hipSuccess ||
+        upload(h->ws + L.origin, org.data(), org.size() * 4) != hipSuccess)
       return fail(HDD_EDEVICE);
     const bool bdbl = B.top.is_double != 0;
     if (!hdd::block_shape_ok(B)) return fail(HDD_EINVAL);
@@ -719,7 +792,7 @@ int create_impl(const hdd_opts* o, int32_t max_samples, void* stream, void* work
     for (auto& lv : h->lev) mx = std::max<int64_t>(mx, lv.n_nodes);
     std::vector<int> io(mx);
     for (int64_t k = 0; k < mx; ++k) io[k] = int(k);
-    if (hipMemcpy(h->iota, io.data(), io.size() * 4, hipMemcpyHostToDevice) != hipSuccess) return fail(HDD_EDEVICE);
+    if (upload(h->iota, io.data(), io.size() * 4) != hipSuccess) return fail(HDD_EDEVICE);
   }
   if (!no_alloc) {
     if (hipEventCreateWithFlags(&h->lists_done, hipEventDisableTiming) != hipSuccess) {
@@ -782,28 +855,16 @@ int hdd_create_static(const hdd_opts* o, int32_t max_samples, void* stream, hdd_
   return HDD_OK;
 }
 
-int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double* f, const double* g, int32_t mem) {
-  if (!h || !kappa || !f || g != nullptr || n_samples < 1 || n_samples > h->max_samples) return HDD_EINVAL;
-  if (mem != HDD_MEM_HOST && mem != HDD_MEM_DEVICE) return HDD_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// The device part of Leaves to Root for h->n_samples samples whose kappa and
+// load are in the workspace: kernel launches on h->st only (captured as one
+// HIP graph by run_graph).
+int build_device(hdd_tree* h) {
+  const int n_samples = h->n_samples;
   const int nc = h->plan.nc;
-  const size_t kbytes = size_t(n_samples) * nc * nc * 2 * 8;
-  const size_t fbytes = size_t(h->nn) * 8;
-  if (mem == HDD_MEM_HOST) {
-    for (size_t i = 0; i < kbytes / 8; ++i)
-      if (!(kappa[i] > 0.0) || !std::isfinite(kappa[i])) return HDD_EINVAL;
-    HIP_TRY(hipMemcpyAsync(h->kappa, kappa, kbytes, hipMemcpyHostToDevice, h->st));
-    HIP_TRY(hipMemcpyAsync(h->f, f, fbytes, hipMemcpyHostToDevice, h->st));
-  } else {
-    HIP_TRY(hipMemcpyAsync(h->kappa, kappa, kbytes, hipMemcpyDeviceToDevice, h->st));
-    HIP_TRY(hipMemcpyAsync(h->f, f, fbytes, hipMemcpyDeviceToDevice, h->st));
-  }
-  h->n_samples = n_samples;
-  h->built = false;
-  h->full = false;
-  h->deferred = HDD_OK;
-  h->last_node = 0;
-  reset_refine_state(h);
-  for (auto& v : h->solved) std::fill(v.begin(), v.end(), 0);
   HIP_TRY(hdd::launch_fill_i32(h->info, n_samples, 0, h->st));
   HIP_TRY(hdd::launch_fill_i32(h->bad, n_samples, 0, h->st));
   const int D = int(h->lev.size()) - 1;
@@ -813,13 +874,17 @@ int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double
     const DevLevel& L = h->lev[d];
     const int g = L.gam;
     const int syrk_kind = L.is_double ? K_SYRK64 : K_SYRK;
-    // Rank-K update C[r0.., c0..c1) -= F[.., k0..k1) F[.., k0..k1)^T, timed.
+    const int tile_final = h->tile.empty() ? 0 : h->tile[d];
+    // Rank-K update C[r0.., c0..c1) -= F[.., k0..k1) F[.., k0..k1)^T, timed;
+    // the autotuned tile applies to the Schur update of Gamma, the trailing
+    // updates inside the interface follow the built-in rule.
     auto syrk = [&](int k0, int k1, int r0, int c1) -> int {
+      const int tile = c1 < 0 ? tile_final : 0;
       const double fl = h->timing_mask ? syrk_flops(h, d, k0, k1, r0, r0, c1) : 0.0;
       const double by = h->timing_mask ? syrk_bytes(h, d, k0, k1, r0, r0, c1) : 0.0;
-      const int kind = hdd::syrk_uses_big_tile(L, k0, k1, r0, r0, c1, mfma) ? K_SYRK128 : syrk_kind;
+      const int kind = hdd::syrk_uses_big_tile(L, k0, k1, r0, r0, c1, mfma, tile) ? K_SYRK128 : syrk_kind;
       return timed(
-          h, kind, fl, [&] { return hdd::launch_syrk(L, k0, k1, r0, r0, c1, n_samples, mfma, h->st); }, by);
+          h, kind, fl, [&] { return hdd::launch_syrk(L, k0, k1, r0, r0, c1, n_samples, mfma, tile, h->st); }, by);
     };
     // Two-level blocked right-looking partial Cholesky of the first g
     // columns: panels of kPanelNB columns inside blocks of kBlockNB columns;
@@ -834,13 +899,7 @@ int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double
       }
       if (b1 < g) HDD_TRY(syrk(b0, b1, b1, g));
     }
-    if (L.max_U > g) {  // Schur update of Gamma (and the boundary load row)
-      const double fl = h->timing_mask ? syrk_flops(h, d, 0, g, g, g, -1) : 0.0;
-      const double by = h->timing_mask ? syrk_bytes(h, d, 0, g, g, g, -1) : 0.0;
-      const int kind = hdd::syrk_uses_big_tile(L, 0, g, g, g, -1, mfma) ? K_SYRK128 : syrk_kind;
-      HDD_TRY(timed(
-          h, kind, fl, [&] { return hdd::launch_syrk(L, 0, g, g, g, -1, n_samples, mfma, h->st); }, by));
-    }
+    if (L.max_U > g) HDD_TRY(syrk(0, g, g, -1));  // Schur update of Gamma (and the boundary load row)
     return HDD_OK;
   };
   h->cur_level = D;
@@ -858,8 +917,94 @@ int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double
     HDD_TRY(timed(h, K_EXTEND, 0.0, [&] { return hdd::launch_extend_add(h->lev[d], h->lev[d + 1], n_samples, h->st); }));
     HDD_TRY(eliminate(d));
   }
-  HIP_TRY(hdd::launch_fill(h->u, (long long)n_samples * h->nn, 0.0, h->st));
+  return hip_status(hdd::launch_fill(h->u, (long long)n_samples * h->nn, 0.0, h->st));
+}
+
+// Leaves to Root on the kappa and load already in the workspace.
+int build_resident(hdd_tree* h, int n_samples) {
+  h->n_samples = n_samples;
+  h->built = false;
+  h->full = false;
+  h->deferred = HDD_OK;
+  h->last_node = 0;
+  reset_refine_state(h);
+  for (auto& v : h->solved) std::fill(v.begin(), v.end(), 0);
+  HDD_TRY(run_graph(h, h->g_build, [&] { return build_device(h); }));
   h->built = true;
+  return HDD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hdd_build(hdd_handle h, int32_t n_samples, const double* kappa, const double* f, const double* g, int32_t mem) {
+  if (!h || !kappa || !f || g != nullptr || n_samples < 1 || n_samples > h->max_samples) return HDD_EINVAL;
+  if (mem != HDD_MEM_HOST && mem != HDD_MEM_DEVICE) return HDD_EINVAL;
+  const int nc = h->plan.nc;
+  const size_t kbytes = size_t(n_samples) * nc * nc * 2 * 8;
+  const size_t fbytes = size_t(h->nn) * 8;
+  if (mem == HDD_MEM_HOST) {
+    for (size_t i = 0; i < kbytes / 8; ++i)
+      if (!(kappa[i] > 0.0) || !std::isfinite(kappa[i])) return HDD_EINVAL;
+    HIP_TRY(hipMemcpyAsync(h->kappa, kappa, kbytes, hipMemcpyHostToDevice, h->st));
+    HIP_TRY(hipMemcpyAsync(h->f, f, fbytes, hipMemcpyHostToDevice, h->st));
+  } else {
+    HIP_TRY(hipMemcpyAsync(h->kappa, kappa, kbytes, hipMemcpyDeviceToDevice, h->st));
+    HIP_TRY(hipMemcpyAsync(h->f, f, fbytes, hipMemcpyDeviceToDevice, h->st));
+  }
+  return build_resident(h, n_samples);
+}
+
+int hdd_autotune(hdd_handle h, int32_t reps, int32_t* choices) {
+  if (!h || reps < 1) return HDD_EINVAL;
+  if (!h->built) return HDD_ESTATE;
+  if (h->no_alloc) return HDD_EINVAL;  // timing events would be allocations
+  const int nd = int(h->lev.size());
+  const int ns = h->n_samples;
+  const int saved_mask = h->timing_mask;
+  // per level: event time of its Schur update of Gamma on the 64 x 64 tile,
+  // then on the 128 x 128 tile (the trailing updates inside the interface
+  // keep the built-in rule and are timed under another kind)
+  std::vector<double> ms[2];
+  const int cand[2] = {64, 128};
+  for (int c = 0; c < 2; ++c) {
+    ms[c].assign(nd, 0.0);
+    h->tile.assign(nd, cand[c]);
+    for (int r = 0; r < reps; ++r) {
+      HDD_TRY(hdd_timing_enable(h, (1 << K_SYRK) | (1 << K_SYRK64) | (1 << K_SYRK128)));
+      HDD_TRY(build_resident(h, ns));
+      for (int d = 0; d < nd; ++d)
+        for (int k : {K_SYRK, K_SYRK128}) {
+          double t = 0.0;
+          HDD_TRY(hdd_timing_get_level(h, k, d, &t, nullptr, nullptr, nullptr));
+          ms[c][d] += t;
+        }
+    }
+  }
+  std::vector<int> pick(nd, 0);
+  for (int d = 0; d < nd; ++d) {
+    const bool choice = !h->lev[d].is_double && !merge_level(h->plan, h->opt, d) && d < nd - 1 &&
+                        h->lev[d].max_U > 0 && !(h->opt.flags & HDD_FLAG_NO_MFMA);
+    if (choice && ms[0][d] + ms[1][d] > 0.0) pick[d] = ms[1][d] < ms[0][d] ? 128 : 64;
+    if (choices) choices[d] = pick[d];
+  }
+  h->tile = pick;
+  HDD_TRY(hdd_timing_enable(h, saved_mask));
+  drop_graphs(h);
+  return build_resident(h, ns);  // the handle is left built with the chosen tiles
+}
+
+int hdd_graph_info(hdd_handle h, int64_t out[4]) {
+  if (!h || !out) return HDD_EINVAL;
+  auto nodes = [&](const hdd_tree::Graphs& gs) -> int64_t {
+    auto it = gs.find(h->n_samples);
+    return it == gs.end() ? 0 : it->second.nodes;
+  };
+  out[0] = nodes(h->g_build);
+  out[1] = nodes(h->g_solve);
+  out[2] = nodes(h->g_sweep);
+  out[3] = h->graph_launches;
   return HDD_OK;
 }
 
@@ -964,8 +1109,9 @@ int hdd_sample_status(hdd_handle h, int32_t* status) {
   HIP_TRY(hipStreamSynchronize(h->st));
   const int ns = h->n_samples;
   std::vector<int> info(ns), bad(ns);
-  HIP_TRY(hipMemcpy(info.data(), h->info, sizeof(int) * ns, hipMemcpyDeviceToHost));
-  HIP_TRY(hipMemcpy(bad.data(), h->bad, sizeof(int) * ns, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpyAsync(info.data(), h->info, sizeof(int) * ns, hipMemcpyDeviceToHost, h->st));
+  HIP_TRY(hipMemcpyAsync(bad.data(), h->bad, sizeof(int) * ns, hipMemcpyDeviceToHost, h->st));
+  HIP_TRY(hipStreamSynchronize(h->st));
   for (int s = 0; s < ns; ++s)
     status[s] = bad[s] ? HDD_EINVAL : info[s] ? HDD_ENOTSPD : h->sstat.empty() ? HDD_OK : h->sstat[s];
   return HDD_OK;
@@ -1140,6 +1286,7 @@ int hdd_last_node(hdd_handle h) { return h ? h->last_node : 0; }
 int hdd_destroy(hdd_handle h) {
   if (!h) return HDD_OK;
   if (h->st) (void)hipStreamSynchronize(h->st);
+  drop_graphs(h);
   for (auto e : h->ev_pool) (void)hipEventDestroy(e);
   if (h->lists_done) (void)hipEventDestroy(h->lists_done);
   if (h->pinned_lists && !h->no_alloc) (void)hipHostFree(h->pinned_lists);

@@ -918,21 +918,24 @@ hipError_t launch_panel(const DevLevel& L, int k0, int kb, int n_samples, int* i
 // more rows go to the 64 x 64 tile: with two K chunks per tile the 128 x 128
 // tile's read-modify-write dominates (measured at 1023^2, 448-row frames,
 // K = 63: 1.5 ms instead of 2.3 ms; no gain at 320 rows).
-bool syrk_uses_big_tile(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, bool mfma) {
+bool syrk_uses_big_tile(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, bool mfma, int tile) {
+  if (!mfma || L.is_double || k1 <= k0) return false;  // the 128 x 128 tile is float32 matrix-core only
+  if (tile == 64) return false;
+  if (tile == 128) return true;
   const int rows = L.max_U + 1 - r0;
   const int cols = (c1 < 0 ? L.max_U + 1 : c1) - c0;
   if (k1 - k0 < 96) return false;
-  return mfma && !L.is_double && k1 > k0 && rows >= 192 && cols >= 128 && (k0 % 4) == 0 && L.max_U + 1 >= 64;
+  return rows >= 192 && cols >= 128 && (k0 % 4) == 0 && L.max_U + 1 >= 64;
 }
 
 hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, int n_samples, bool mfma,
-                       hipStream_t st) {
+                       int tile, hipStream_t st) {
   if (k1 <= k0) return hipSuccess;
   SyrkArgs a{k0, k1, r0, c0, c1, 0, 0, 0};
   const int rows = L.max_U + 1 - r0;
   const int cols = (c1 < 0 ? L.max_U + 1 : c1) - c0;
   if (rows <= 0 || cols <= 0) return hipSuccess;
-  const bool big = syrk_uses_big_tile(L, k0, k1, r0, c0, c1, mfma);
+  const bool big = syrk_uses_big_tile(L, k0, k1, r0, c0, c1, mfma, tile);
   const int TM = big ? 128 : 64;
   // the matrix-core tiles cover rows r0 .. U-1; the load row U is formed by
   // the idle wave of the diagonal tiles

@@ -31,6 +31,7 @@ HDD_FLAG_NO_MFMA = 1
 HDD_FLAG_KEEP_DIRICHLET = 2
 HDD_FLAG_BLOCK8 = 4
 HDD_FLAG_KEEP_FRAMES = 8
+HDD_FLAG_NO_GRAPH = 16
 
 EXPORTED = [
     "hdd_default_opts", "hdd_workspace_size", "hdd_create", "hdd_build", "hdd_query_points",
@@ -40,7 +41,7 @@ EXPORTED = [
     "hdd_timing_enable", "hdd_timing_get", "hdd_mfma_selftest", "hdd_debug_frame",
     "hdd_timing_get_level", "hdd_query_points_ragged", "hdd_loglik_ragged",
     "hdd_server_create", "hdd_server_slots", "hdd_server_submit", "hdd_server_poll", "hdd_server_result",
-    "hdd_server_stats", "hdd_server_destroy", "hdd_sample_status", "hdd_create_static",
+    "hdd_server_stats", "hdd_server_destroy", "hdd_sample_status", "hdd_create_static", "hdd_autotune", "hdd_graph_info",
 ]
 MAX_QUERY_POINTS = 4096
 STATIC_WORKSPACE_BYTES = 64 << 20
@@ -85,6 +86,8 @@ def _load() -> ctypes.CDLL:
         "hdd_workspace_size": [popts, i32, ctypes.POINTER(ctypes.c_size_t)],
         "hdd_create": [popts, i32, P, P, ctypes.c_size_t, ctypes.POINTER(P)],
         "hdd_create_static": [popts, i32, P, ctypes.POINTER(P)],
+        "hdd_autotune": [P, i32, P],
+        "hdd_graph_info": [P, P],
         "hdd_build": [P, i32, P, P, P, i32],
         "hdd_query_points": [P, i32, P, P, i32],
         "hdd_query_interface": [P, i32, i32, P, ctypes.POINTER(i32), i32],
@@ -401,6 +404,19 @@ class HDD:
 
     def sync(self) -> int:
         return _lib.hdd_sync(self.h)
+
+    def autotune(self, reps: int = 1) -> np.ndarray:
+        """Per-level Schur-update tile chosen by timing (64, 128, or 0: no choice)."""
+        levels = hdd_plan_summary(self.opts)["levels"]
+        ch = np.zeros(levels, dtype=np.int32)
+        _check(_lib.hdd_autotune(self.h, int(reps), _np_ptr(ch)), "hdd_autotune")
+        return ch
+
+    def graph_info(self) -> dict:
+        out = np.zeros(4, dtype=np.int64)
+        _check(_lib.hdd_graph_info(self.h, _np_ptr(out)), "hdd_graph_info")
+        return dict(build_nodes=int(out[0]), solve_nodes=int(out[1]), sweep_nodes=int(out[2]),
+                    launches=int(out[3]))
 
     def last_node(self) -> int:
         return _lib.hdd_last_node(self.h)
