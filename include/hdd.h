@@ -409,9 +409,16 @@ int hdd_mfma_selftest(int32_t dtype, double* out);
  * (Leaves to Root, then hdd_query_points_ragged and
  * hdd_loglik_ragged), so requests arriving while others run are admitted as
  * soon as a slot frees up, and batches of different meshes overlap on the
- * GPU.  Device workspaces for full batches are allocated at creation: slots
- * (default 32) are halved until all meshes' workspaces fit hbm_budget bytes
- * (0: no limit); ENOMEM if one slot per mesh does not fit.
+ * GPU.  Every launch sequence of a batch size is captured once and replayed
+ * (HIP graphs) when there is no HBM budget.
+ * HBM admission: a mesh's device workspace (a full batch) is allocated when
+ * its first batch is admitted and counted against hbm_budget bytes (0: no
+ * limit).  A batch whose workspace does not fit releases idle meshes'
+ * workspaces, least recently used first, or waits until running batches
+ * finish (its requests stay queued).  Slots per mesh (default 32) are halved
+ * while one mesh's full-batch workspace alone exceeds the budget; ENOMEM at
+ * creation if a single sample's does.  With a budget the handles launch
+ * eagerly (a workspace release may synchronize the device).
  * ------------------------------------------------------------------------ */
 #define HDD_SERVER_MAX_MESHES 8
 #define HDD_SERVER_MAX_POINTS 256
@@ -432,8 +439,11 @@ typedef struct {
 /* f: per mesh host float64 [(n+2)^2] nodal right-hand side copied at
  * creation, or NULL (f = 1 on every mesh); an entry may also be NULL. */
 int hdd_server_create(const hdd_server_opts* opts, const double* const* f, hdd_server_t* out);
-/* Samples per batch each mesh was given (after the budget). */
+/* Samples per batch (the smallest over the meshes, after the budget). */
 int hdd_server_slots(hdd_server_t s, int32_t* slots);
+/* HBM admission state, out int64 [4]: bytes of resident workspaces, meshes
+ * resident, workspaces released to admit another mesh, workspaces created. */
+int hdd_server_memory(hdd_server_t s, int64_t* out);
 /* Queue a request on mesh `mesh` (index into opts.n): kappa host float64
  * [n+1][n+1][2] (positive, finite), xy host float64 [n_pts][2] in the unit
  * square (1 <= n_pts <= HDD_SERVER_MAX_POINTS), y host float64 [n_pts] or

@@ -7,11 +7,17 @@
 // Leaves to Root for all of them, then the sample-specific point values and
 // Gaussian log-likelihoods (Section 1.2).  Batches of different meshes run
 // concurrently on their own streams, so requests that arrive while others
-// are on the GPU are admitted as soon as a slot frees up.  The device
-// workspaces (all factors of a full batch) are sized once, at creation, to
-// the HBM budget.
+// are on the GPU are admitted as soon as a slot frees up.
+//
+// HBM admission: a mesh's device workspace (all factors of a full batch) is
+// allocated when its first batch is admitted and counted against the
+// server's budget.  When a batch needs a workspace that does not fit, idle
+// meshes' workspaces are released, least recently used first; if that is
+// not enough the batch waits until running batches finish.  A mesh whose
+// single-sample workspace exceeds the budget is refused at creation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -47,7 +53,11 @@ struct Request {
 struct Mesh {
   int n = 0, nc = 0, slots = 0;
   hdd_opts opts{};
-  hdd_handle h = nullptr;
+  hdd_handle h = nullptr;    // resident handle (null while evicted)
+  void* ws = nullptr;        // its device workspace
+  size_t ws_bytes = 0;       // workspace of a full batch
+  bool busy = false;         // a batch is running on the handle
+  double last_used = 0.0;
   hipStream_t st = nullptr;
   double* pinned = nullptr;  // kappa of one batch, [slots][nc][nc][2]
   std::vector<double> f;     // nodal right-hand side, [(nc+1)^2]
@@ -62,13 +72,78 @@ struct hdd_server {
   int device = 0;
   std::vector<std::unique_ptr<Mesh>> meshes;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_done, cv_mem;
+  double budget = 0.0;         // bytes for all workspaces (0: no limit)
+  size_t used = 0;             // bytes of resident workspaces
+  int64_t evictions = 0, creations = 0;
   std::unordered_map<int64_t, std::shared_ptr<Request>> reqs;
   int64_t next_id = 1, submitted = 0, completed = 0;
   bool stop = false;
 };
 
 namespace {
+
+// Releases a mesh's handle and workspace (the mesh is idle).
+void release_workspace(Mesh* m) {
+  if (m->h) hdd_destroy(m->h);
+  if (m->ws) (void)hipFree(m->ws);
+  m->h = nullptr;
+  m->ws = nullptr;
+}
+
+// Makes mesh m's handle resident within the budget (lk holds S->mu):
+// evicts idle meshes, least recently used first, or waits for running
+// batches.  Returns an HDD code; on success m->h is valid and m->busy set.
+int admit(hdd_server* S, Mesh* m, std::unique_lock<std::mutex>& lk) {
+  for (;;) {
+    if (S->stop) return HDD_ESTATE;
+    if (m->h) {
+      m->busy = true;
+      return HDD_OK;
+    }
+    if (S->budget <= 0.0 || double(S->used + m->ws_bytes) <= S->budget) break;
+    Mesh* victim = nullptr;
+    for (auto& o : S->meshes)
+      if (o.get() != m && o->h && !o->busy && (!victim || o->last_used < victim->last_used)) victim = o.get();
+    if (victim) {
+      // free it outside the lock; nobody else touches an idle mesh's handle
+      // while its worker sleeps (the worker re-admits it first)
+      hdd_handle vh = victim->h;
+      void* vws = victim->ws;
+      victim->h = nullptr;
+      victim->ws = nullptr;
+      lk.unlock();
+      hdd_destroy(vh);
+      (void)hipFree(vws);
+      lk.lock();
+      S->used -= victim->ws_bytes;
+      S->evictions += 1;
+      continue;
+    }
+    S->cv_mem.wait(lk);  // every resident mesh is running a batch
+  }
+  S->used += m->ws_bytes;
+  m->busy = true;
+  lk.unlock();
+  int st = HDD_OK;
+  if (hipMalloc(&m->ws, m->ws_bytes) != hipSuccess) {
+    m->ws = nullptr;
+    st = HDD_ENOMEM;
+  }
+  if (st == HDD_OK) st = hdd_create(&m->opts, m->slots, m->st, m->ws, m->ws_bytes, &m->h);
+  lk.lock();
+  if (st != HDD_OK) {
+    if (m->ws) (void)hipFree(m->ws);
+    m->ws = nullptr;
+    m->h = nullptr;
+    m->busy = false;
+    S->used -= m->ws_bytes;
+    S->cv_mem.notify_all();
+    return st;
+  }
+  S->creations += 1;
+  return HDD_OK;
+}
 
 void run_mesh(hdd_server* S, Mesh* m) {
   if (hipSetDevice(S->device) != hipSuccess) return;
@@ -83,6 +158,21 @@ void run_mesh(hdd_server* S, Mesh* m) {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv_work.wait(lk, [&] { return S->stop || !m->queue.empty(); });
       if (S->stop) return;
+      // the handle must be resident within the HBM budget
+      const int adm = admit(S, m, lk);
+      if (adm != HDD_OK) {
+        if (S->stop) return;
+        // the batch's requests fail with the admission code
+        while (!m->queue.empty()) {
+          auto r = m->queue.front();
+          m->queue.pop_front();
+          r->status = adm;
+          r->done = true;
+          S->completed += 1;
+        }
+        S->cv_done.notify_all();
+        continue;
+      }
       // up to the slot count, and up to the handle's limit on the sites of
       // one ragged query (a request never exceeds it alone)
       int pts = 0;
@@ -139,8 +229,11 @@ void run_mesh(hdd_server* S, Mesh* m) {
       }
       S->completed += B;
       m->batches += 1;
+      m->busy = false;
+      m->last_used = now_s();
     }
     S->cv_done.notify_all();
+    S->cv_mem.notify_all();
   }
 }
 
@@ -150,6 +243,7 @@ void destroy_server(hdd_server* S) {
     S->stop = true;
   }
   S->cv_work.notify_all();
+  S->cv_mem.notify_all();
   for (auto& m : S->meshes)
     if (m->worker.joinable()) m->worker.join();
   {
@@ -162,7 +256,7 @@ void destroy_server(hdd_server* S) {
   }
   S->cv_done.notify_all();
   for (auto& m : S->meshes) {
-    if (m->h) hdd_destroy(m->h);
+    release_workspace(m.get());
     if (m->pinned) (void)hipHostFree(m->pinned);
     if (m->st) (void)hipStreamDestroy(m->st);
   }
@@ -186,52 +280,59 @@ int hdd_server_create(const hdd_server_opts* o, const double* const* f, hdd_serv
     delete S;
     return HDD_EDEVICE;
   }
-  // slots per mesh: as requested (default 32), halved until every mesh's
-  // full-batch workspace fits the HBM budget together
   std::vector<hdd_opts> opts(o->n_meshes);
   for (int i = 0; i < o->n_meshes; ++i) {
     int st = hdd_default_opts(o->n[i], o->precision, &opts[i]);
     if (st == HDD_OK && o->leaf[i] > 0) opts[i].leaf = o->leaf[i];
     if (st == HDD_OK && o->max_refine > 0) opts[i].max_refine = o->max_refine;
+    // with a finite budget workspaces are released while other meshes run:
+    // a release may synchronize the device, which must not meet another
+    // mesh's graph capture, so those handles issue their launches eagerly
+    if (st == HDD_OK && o->hbm_budget > 0.0) opts[i].flags |= HDD_FLAG_NO_GRAPH;
     if (st != HDD_OK) {
       delete S;
       return st;
     }
   }
-  int slots = o->slots > 0 ? o->slots : 32;
-  for (;;) {
-    double total = 0.0;
-    for (int i = 0; i < o->n_meshes; ++i) {
+  // slots per mesh: as requested (default 32), halved while a mesh's
+  // full-batch workspace alone exceeds the budget; a mesh whose single-sample
+  // workspace exceeds it is refused
+  const int slots0 = o->slots > 0 ? o->slots : 32;
+  std::vector<int> mslots(o->n_meshes, slots0);
+  std::vector<size_t> wbytes(o->n_meshes, 0);
+  for (int i = 0; i < o->n_meshes; ++i) {
+    for (;;) {
       size_t b = 0;
-      const int st = hdd_workspace_size(&opts[i], slots, &b);
+      const int st = hdd_workspace_size(&opts[i], mslots[i], &b);
       if (st != HDD_OK) {
         delete S;
         return st;
       }
-      total += double(b);
+      wbytes[i] = b;
+      if (o->hbm_budget <= 0.0 || double(b) <= o->hbm_budget) break;
+      if (mslots[i] == 1) {
+        delete S;
+        return HDD_ENOMEM;
+      }
+      mslots[i] /= 2;
     }
-    if (o->hbm_budget <= 0.0 || total <= o->hbm_budget) break;
-    if (slots == 1) {
-      delete S;
-      return HDD_ENOMEM;
-    }
-    slots /= 2;
   }
+  S->budget = o->hbm_budget;
   for (int i = 0; i < o->n_meshes; ++i) {
     auto m = std::make_unique<Mesh>();
     m->n = o->n[i];
     m->nc = o->n[i] + 1;
-    m->slots = slots;
+    m->slots = mslots[i];
     m->opts = opts[i];
+    m->ws_bytes = wbytes[i];
     const size_t nf = size_t(m->nc + 1) * (m->nc + 1);
     if (f && f[i]) m->f.assign(f[i], f[i] + nf);
     else m->f.assign(nf, 1.0);
     int st = HDD_OK;
     if (hipStreamCreateWithFlags(&m->st, hipStreamNonBlocking) != hipSuccess) st = HDD_EDEVICE;
     if (st == HDD_OK && hipHostMalloc(reinterpret_cast<void**>(&m->pinned),
-                                      size_t(slots) * m->nc * m->nc * 2 * sizeof(double)) != hipSuccess)
+                                      size_t(m->slots) * m->nc * m->nc * 2 * sizeof(double)) != hipSuccess)
       st = HDD_ENOMEM;
-    if (st == HDD_OK) st = hdd_create(&m->opts, slots, m->st, nullptr, 0, &m->h);
     S->meshes.push_back(std::move(m));
     if (st != HDD_OK) {
       destroy_server(S);
@@ -246,6 +347,19 @@ int hdd_server_create(const hdd_server_opts* o, const double* const* f, hdd_serv
 int hdd_server_slots(hdd_server_t S, int32_t* slots) {
   if (!S || !slots || S->meshes.empty()) return HDD_EINVAL;
   *slots = S->meshes[0]->slots;
+  for (auto& m : S->meshes) *slots = std::min(*slots, m->slots);
+  return HDD_OK;
+}
+
+int hdd_server_memory(hdd_server_t S, int64_t* out) {
+  if (!S || !out) return HDD_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  int64_t resident = 0;
+  for (auto& m : S->meshes) resident += m->h ? 1 : 0;
+  out[0] = int64_t(S->used);
+  out[1] = resident;
+  out[2] = S->evictions;
+  out[3] = S->creations;
   return HDD_OK;
 }
 

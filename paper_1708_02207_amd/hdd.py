@@ -41,7 +41,7 @@ EXPORTED = [
     "hdd_timing_enable", "hdd_timing_get", "hdd_mfma_selftest", "hdd_debug_frame",
     "hdd_timing_get_level", "hdd_query_points_ragged", "hdd_loglik_ragged",
     "hdd_server_create", "hdd_server_slots", "hdd_server_submit", "hdd_server_poll", "hdd_server_result",
-    "hdd_server_stats", "hdd_server_destroy", "hdd_sample_status", "hdd_create_static", "hdd_autotune", "hdd_graph_info",
+    "hdd_server_stats", "hdd_server_destroy", "hdd_sample_status", "hdd_create_static", "hdd_autotune", "hdd_graph_info", "hdd_server_memory",
 ]
 MAX_QUERY_POINTS = 4096
 STATIC_WORKSPACE_BYTES = 64 << 20
@@ -123,6 +123,7 @@ def _load() -> ctypes.CDLL:
         "hdd_server_poll": [P, i64, ctypes.POINTER(i32)],
         "hdd_server_result": [P, i64, P, ctypes.POINTER(dbl), P],
         "hdd_server_stats": [P, P],
+        "hdd_server_memory": [P, P],
         "hdd_server_destroy": [P],
     }
     for name, args in sig.items():
@@ -519,6 +520,11 @@ class Server:
         out = np.zeros(4, dtype=np.int64)
         _check(_lib.hdd_server_stats(self.h, _np_ptr(out)), "hdd_server_stats")
         return dict(submitted=int(out[0]), completed=int(out[1]), batches=int(out[2]), queued=int(out[3]))
+
+    def memory(self):
+        out = np.zeros(4, dtype=np.int64)
+        _check(_lib.hdd_server_memory(self.h, _np_ptr(out)), "hdd_server_memory")
+        return dict(bytes=int(out[0]), resident=int(out[1]), evictions=int(out[2]), creations=int(out[3]))
 
     def close(self):
         if getattr(self, "h", None):

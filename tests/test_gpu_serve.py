@@ -263,3 +263,36 @@ def test_server_budget(H):
         assert np.array_equal(vals[s][0], vals[s + 4][0])
     assert srv.stats()["batches"] >= 4
     srv.close()
+
+
+def test_server_hbm_admission_evicts_and_queues(H):
+    """A budget that holds one mesh's workspace at a time: batches of the two
+    meshes alternate, each admission releases the other mesh's idle
+    workspace, requests wait in the queue meanwhile, and every answer equals
+    the one from a server without a budget, bit for bit."""
+    w1 = make_workload("s_127", n_samples=4)
+    w2 = make_workload("s_255", n_samples=4)
+    o1 = H.hdd_default_opts(w1.n, H.HDD_FP32_REFINE, leaf=w1.leaf)
+    o2 = H.hdd_default_opts(w2.n, H.HDD_FP32_REFINE, leaf=w2.leaf)
+    slots = 4
+    b1, b2 = H.hdd_workspace_size(o1, slots), H.hdd_workspace_size(o2, slots)
+    budget = 1.01 * max(b1, b2)
+    assert budget < b1 + b2
+    rng = np.random.default_rng(61)
+    reqs = [(k % 2, k % 4, rng.uniform(size=(5, 2))) for k in range(16)]
+    answers = []
+    for hbm in (0.0, budget):
+        srv = H.Server([w1.n, w2.n], H.HDD_FP32_REFINE, slots=slots, hbm_budget=hbm,
+                       leaves=[w1.leaf, w2.leaf], f=[w1.f, w2.f])
+        assert srv.slots == slots
+        ids = [srv.submit(m, (w1, w2)[m].kappa[s], xy) for m, s, xy in reqs]
+        answers.append([srv.result(i, 5)[0] for i in ids])
+        mem = srv.memory()
+        say("budget", hbm, "memory", mem, "stats", srv.stats())
+        if hbm > 0:
+            assert mem["evictions"] >= 1 and mem["bytes"] <= budget
+        else:
+            assert mem["evictions"] == 0
+        srv.close()
+    for a, b in zip(*answers):
+        assert np.array_equal(a, b)
