@@ -73,10 +73,18 @@ def copy_probe(nbytes: int):
 
 
 def cpu_baseline(w, seconds: float):
-    """Oracle banded-Cholesky factorization of the first columns of the same
-    1023^2 operator on one host core, scaled to the full factorization
-    (every column away from the end costs the same), as evals/s."""
+    """The oracle on the host, one core (it is single-threaded):
+    - at 1023^2 (the headline workload, sample 0), its banded-Cholesky
+      factorization of the first columns of the operator, scaled to the full
+      factorization by column count (every column away from the end costs the
+      same); triangular solves and refinement are not included, so the figure
+      favours the CPU;
+    - complete oracle solves (factorization, solves, 2 extended-precision
+      refinement sweeps) at 255^2 and 511^2 on the same statistics.
+    value = 1023^2 evaluations/s on one core; all_cores_value = nproc x value
+    (samples are independent)."""
     from oracle import oracle as O
+    from workload import make_workload
 
     n = w.n
     ncols_total = n * n
@@ -85,11 +93,20 @@ def cpu_baseline(w, seconds: float):
     ncols = int(min(ncols_total, max(probe, probe * seconds / max(t, 1e-6))))
     t = O.factor_prefix_seconds(n, w.kappa[0], ncols)
     t_full = t * ncols_total / ncols
+    full = {}
+    for name in ("s_255", "s_511"):
+        ws = make_workload(name, n_samples=1)
+        t0 = time.perf_counter()
+        O.solve(ws.n, ws.kappa[0], ws.f)
+        full[f"{ws.n}^2"] = time.perf_counter() - t0
+    nproc = os.cpu_count() or 1
     return {"value": 1.0 / t_full, "unit": "likelihood evals/s", "cores": 1, "kind": "oracle",
             "sample": f"banded Cholesky of the first {ncols} of {ncols_total} columns of the 1023^2 operator "
                       f"(sample 0), {t:.1f} s, scaled by column count to {t_full:.0f} s per solve; "
                       f"triangular solves and refinement (O(N^3)) not included",
-            "host": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
+            "full_solve_seconds_1core": full,
+            "all_cores_value": nproc / t_full, "nproc": nproc,
+            "host": platform.processor() or platform.machine()}
 
 
 def serving_mix(H, n_req: int, seed: int = 7):
@@ -143,6 +160,41 @@ def serving_mix(H, n_req: int, seed: int = 7):
     sat = burst["throughput_rps"]
     out = {"mix": "127^2/255^2/511^2 uniform, 1-32 sites, FP32+refinement", "slots_per_mesh": srv.slots,
            "saturated_rps": sat, "rates": [run(f * sat) for f in (0.5, 0.8, 1.0)], "stats": srv.stats()}
+    srv.close()
+    out["serve_1023"] = serving_1023(H, n_req, seed)
+    return out
+
+
+def serving_1023(H, n_req: int, seed: int):
+    """Requests of the headline workload served one by one: each a fresh
+    parameter sample at 1023^2 (32 x 32 leaves) with the 64 observation
+    sites and observations; Poisson arrivals at 0.5 and 0.8 of the
+    saturated rate; per-request latency is submit-to-result."""
+    from workload import make_workload
+
+    w = make_workload("c2_1023", n_samples=16)
+    srv = H.Server([w.n], H.HDD_FP32_REFINE, slots=32, leaves=[w.leaf], f=[w.f])
+    rng = np.random.default_rng(seed + 1)
+    y = np.zeros(len(w.points))
+
+    def run(rate, n):
+        at = np.cumsum(rng.exponential(1.0 / rate, size=n)) if rate else np.zeros(n)
+        ids = []
+        t0 = time.perf_counter()
+        for k in range(n):
+            wait = t0 + at[k] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            ids.append(srv.submit(0, w.kappa[int(rng.integers(0, 16))], w.points, y, w.sigma_y))
+        lat = np.array([srv.result(i, len(w.points))[2][2] for i in ids]) * 1e3
+        dt = time.perf_counter() - t0
+        return {"target_rps": rate, "throughput_rps": n / dt, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "requests": n}
+
+    run(0, 32)
+    sat = run(0, n_req)["throughput_rps"]
+    out = {"workload": "c2_1023 requests, 64 sites each", "slots": srv.slots, "saturated_rps": sat,
+           "rates": [run(f * sat, n_req) for f in (0.5, 0.8)]}
     srv.close()
     return out
 
@@ -278,6 +330,39 @@ def main():
     t.close()
     del t
 
+    # The same step with block low-rank copies of the wide levels' maps P
+    # (H-matrix style, float32 accuracy 1e-5) applied by the refinement
+    lowrank = None
+    if not a.no_ablation and prec == H.HDD_FP32_REFINE:
+        o_lr = H.hdd_default_opts(w.n, prec, leaf=w.leaf, flags=H.HDD_FLAG_LOWRANK)
+        t = H.HDD(o_lr, a.batch, stream=stream)
+        step()
+        t.autotune(1)
+        step()
+        torch.cuda.synchronize()
+        ns_lr = max(2, a.steps // 2)
+        l0 = time.perf_counter()
+        for _ in range(ns_lr):
+            step()
+        torch.cuda.synchronize()
+        ldt = time.perf_counter() - l0
+        info = t.lowrank_info()
+        _, lr_sweeps = t.error_estimate()
+        lr_err = None
+        if gold:
+            P = pts.cpu().numpy().reshape(B, -1)
+            lr_err = max(float(np.abs(P[g["sample"]] - np.array(g["points"])).max() / np.abs(np.array(g["points"])).max())
+                         for g in gold["samples"] if g["sample"] < B)
+        lowrank = {"value": B * ns_lr / ldt, "ms_per_step": 1e3 * ldt / ns_lr, "refine_sweeps": lr_sweeps,
+                   "max_rel_err_vs_oracle": lr_err,
+                   "maps_dense_MB_per_sample": info["dense_bytes"] / 1e6,
+                   "block_store_MB_per_sample": info["store_bytes"] / 1e6,
+                   "rank_MB_per_sample": info["rank_bytes"] / 1e6,
+                   "lowrank_blocks": info["lowrank_blocks"], "dense_blocks": info["dense_blocks"],
+                   "mean_rank": info["mean_rank"]}
+        t.close()
+        del t
+
     comparator = None
     if not a.no_comparator:
         o64 = H.hdd_default_opts(w.n, H.HDD_FP64, leaf=w.leaf)
@@ -397,6 +482,7 @@ def main():
                      "note": "kernel launches per step = build + solve + sweeps x sweep graph nodes, "
                              "replayed from captured HIP graphs"},
         "autotune_tiles": tiles,
+        "lowrank": lowrank,
         "ablation": ablation,
         "node_means": node_means,
         "multi_rhs": multi_rhs,

@@ -71,6 +71,9 @@ extern "C" {
 #define HDD_FLAG_KEEP_DIRICHLET 2 /* plan only: keep outer-boundary nodes in every Gamma */
 #define HDD_FLAG_BLOCK8 4         /* eliminate leaf interiors in 8 x 8-cell blocks (default 16 x 16) */
 #define HDD_FLAG_NO_GRAPH 16      /* issue every launch eagerly instead of replaying captured HIP graphs */
+#define HDD_FLAG_LOWRANK 32       /* block low-rank (H-matrix style, Section 4) copies of the maps P of the
+                                     levels with |gamma| >= 255, applied by the refinement sweeps and further
+                                     loads; needs refinement (HDD_FP32_REFINE, or max_refine > 0) */
 #define HDD_FLAG_KEEP_FRAMES 8    /* keep every node's whole frame (its Schur complement S_omega) after the
                                      build, for hdd_debug_node_schur / hdd_debug_frame.  By default only
                                      the retained factors of every node stay (Section 3.4: the sons' Schur
@@ -314,6 +317,27 @@ int hdd_error_estimate(hdd_handle h, double* rel_est, int32_t* sweeps);
 int hdd_autotune(hdd_handle h, int32_t reps, int32_t* choices);
 
 /*
+ * Block low-rank maps (HDD_FLAG_LOWRANK; Section 4, the Proposition that the
+ * maps of every node admit H-matrix approximations).  After a build, the
+ * map P = S_Gamma,gamma L^-T of every level with |gamma| >= 255 is also kept
+ * as 64 x 64 blocks (rows in the order of the node's perimeter, columns
+ * along the cut): blocks whose boundary and interface segments lie at least
+ * their extent apart as factors U V of rank <= 16 (randomized range
+ * finder, rank by a relative tolerance of 1e-5 in float32 and 1e-8 in
+ * float64, the H-matrix accuracies of the paper's experiments), the others
+ * dense.  The refinement sweeps and further loads apply these blocks
+ * instead of the dense P; the float64 residual keeps the refined result
+ * exact.  out (host float64 [6]), per sample over the compressed levels:
+ * bytes of the dense maps, bytes of the block store (64 x 64 per dense
+ * block, 2 x 64 x 16 per low-rank block), bytes the chosen ranks need
+ * (2 x 64 x rank per low-rank block), blocks stored at low rank, blocks
+ * stored dense, mean rank of the low-rank blocks (all 0 without the flag).
+ * The dense maps stay in the retained factors (the build's Schur updates
+ * write them); the sweeps read only the block store.  Synchronizes.  Errors: HDD_ESTATE before a build.
+ */
+int hdd_lowrank_info(hdd_handle h, double out[6]);
+
+/*
  * Captured launch sequences: the build, the first full Root to Leaves and
  * each refinement sweep are captured once per sample count as HIP graphs and
  * replayed (unless HDD_FLAG_NO_GRAPH, timing is enabled, or the handle comes
@@ -376,7 +400,8 @@ int hdd_debug_frame(hdd_handle h, int32_t sample, int32_t depth, int32_t index, 
  * float64 levels, 8 the 128 x 128-tile float32 Schur update kernel (launches
  * of kind 8 are not counted in kind 0), 9 fused merge of narrow float32
  * levels (extend-add, factorization and Schur update in one launch),
- * 10 the functional and readout kernels of hdd_query_node_means.
+ * 10 the functional and readout kernels of hdd_query_node_means, 11 the
+ * compression of the block low-rank maps.
  * hdd_timing_enable(h, mask): bit k enables kind k (0 disables and clears).
  * hdd_timing_get: total milliseconds, number of launches and summed
  * algorithmic flops of the timed launches (Schur update: 2 K per lower-

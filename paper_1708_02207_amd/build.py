@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhdd.so")
-SOURCES = ["plan.cpp", "api.hip", "kernels_build.hip", "kernels_block.hip", "kernels_solve.hip", "kernels_func.hip", "serve.hip"]
+SOURCES = ["plan.cpp", "api.hip", "kernels_build.hip", "kernels_block.hip", "kernels_solve.hip", "kernels_func.hip", "kernels_lowrank.hip", "serve.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

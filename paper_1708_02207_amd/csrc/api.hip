@@ -28,10 +28,10 @@ static __device__ __align__(256) unsigned char scratch[HDD_STATIC_WORKSPACE_BYTE
 
 namespace {
 
-constexpr int kKinds = 11;
+constexpr int kKinds = 12;
 enum Kind {
   K_SYRK = 0, K_FACTOR = 1, K_EXTEND = 2, K_ASSEMBLE = 3, K_TOPDOWN = 4, K_FORWARD = 5, K_RESIDUAL = 6, K_SYRK64 = 7,
-  K_SYRK128 = 8, K_MERGE = 9, K_FUNCTIONAL = 10
+  K_SYRK128 = 8, K_MERGE = 9, K_FUNCTIONAL = 10, K_LOWRANK = 11
 };
 
 int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
@@ -49,6 +49,8 @@ int validate_opts(const hdd_opts* o) {
   if (!o) return HDD_EINVAL;
   if (o->precision != HDD_FP64 && o->precision != HDD_FP32_REFINE) return HDD_EINVAL;
   if (o->fp64_top_levels < 0 || o->max_refine < 0 || !(o->refine_tol >= 0.0)) return HDD_EINVAL;
+  // the compressed maps are only applied under refinement against the exact operator
+  if ((o->flags & HDD_FLAG_LOWRANK) && !(o->precision == HDD_FP32_REFINE || o->max_refine > 0)) return HDD_EINVAL;
   for (int i = 0; i < 8; ++i)
     if (o->reserved[i] != 0) return HDD_EINVAL;
   return HDD_OK;
@@ -68,6 +70,92 @@ bool merge_level(const Plan& p, const hdd_opts& o, int d) {
 }
 
 bool keep_frames(const hdd_opts& o) { return (o.flags & HDD_FLAG_KEEP_FRAMES) != 0; }
+
+// Levels whose maps P get a block low-rank copy: |gamma| >= 255 above the
+// blocks, with a boundary (HDD_FLAG_LOWRANK).
+constexpr int kLowRankMinGamma = 255;
+bool lowrank_level(const Plan& p, const hdd_opts& o, int d) {
+  const int D = int(p.levels.size()) - 1;
+  return (o.flags & HDD_FLAG_LOWRANK) && d < D && p.levels[d].gam >= kLowRankMinGamma &&
+         p.levels[d].max_U > p.levels[d].gam;
+}
+
+// Block tables of a low-rank level: per node the boundary positions sorted
+// along the node's perimeter (counter-clockwise from its lower-left
+// corner), and its 64 x 64 blocks row-major, each dense or low rank by the
+// admissibility of its two segments: their bounding boxes (in cells) lie at
+// least the larger box edge apart.
+struct LowRankTables {
+  std::vector<int> perm;      // parallel to the level's ids
+  std::vector<int> node;      // first block of every node, n_nodes + 1
+  std::vector<int> blk;       // 4 ints per block
+  int64_t elems = 0;          // per-sample store elements
+  int64_t dense_p = 0;        // per-sample elements of the dense maps P
+  int n_lr = 0, n_dense = 0;
+};
+
+LowRankTables lowrank_tables(const Plan& p, int d) {
+  const auto& lv = p.levels[d];
+  const int LB = hdd::kLowRankBlock, KR = hdd::kLowRankMax;
+  const int nc = p.nc;
+  LowRankTables t;
+  t.perm.assign(lv.ids.size(), 0);
+  t.node.push_back(0);
+  auto coords = [&](int id, int& i, int& j) {
+    i = id % (nc + 1);
+    j = id / (nc + 1);
+  };
+  for (size_t k = 0; k < lv.nodes.size(); ++k) {
+    const auto& nd = lv.nodes[k];
+    const int g = int(nd.gam.size()), G = int(nd.bnd.size());
+    // perimeter parameter of a boundary node of the rectangle
+    std::vector<std::pair<double, int>> key(G);
+    for (int q = 0; q < G; ++q) {
+      int i, j;
+      coords(nd.bnd[q], i, j);
+      double tp;
+      if (j == nd.y0) tp = i - nd.x0;
+      else if (i == nd.x0 + nd.w) tp = nd.w + (j - nd.y0);
+      else if (j == nd.y0 + nd.h) tp = nd.w + nd.h + (nd.x0 + nd.w - i);
+      else tp = 2.0 * nd.w + nd.h + (nd.y0 + nd.h - j);
+      key[q] = {tp, q};
+    }
+    std::sort(key.begin(), key.end());
+    for (int q = 0; q < G; ++q) t.perm[nd.ids_off + g + q] = key[q].second;
+    const int nbr = (G + LB - 1) / LB, nbc = (g + LB - 1) / LB;
+    auto box = [&](const int32_t* idv, const int* order, int b0, int n, int bb[4]) {
+      bb[0] = bb[2] = 1 << 30;
+      bb[1] = bb[3] = -1;
+      for (int q = b0; q < b0 + n; ++q) {
+        int i, j;
+        coords(idv[order ? order[q] : q], i, j);
+        bb[0] = std::min(bb[0], i); bb[1] = std::max(bb[1], i);
+        bb[2] = std::min(bb[2], j); bb[3] = std::max(bb[3], j);
+      }
+    };
+    std::vector<int> ord(G);
+    for (int q = 0; q < G; ++q) ord[q] = key[q].second;
+    for (int bi = 0; bi < nbr; ++bi)
+      for (int bj = 0; bj < nbc; ++bj) {
+        int rb[4], cb[4];
+        box(nd.bnd.data(), ord.data(), bi * LB, std::min(LB, G - bi * LB), rb);
+        box(nd.gam.data(), nullptr, bj * LB, std::min(LB, g - bj * LB), cb);
+        const int dx = std::max(0, std::max(rb[0] - cb[1], cb[0] - rb[1]));
+        const int dy = std::max(0, std::max(rb[2] - cb[3], cb[2] - rb[3]));
+        const int ext = std::max({rb[1] - rb[0], rb[3] - rb[2], cb[1] - cb[0], cb[3] - cb[2]});
+        const bool far = std::max(dx, dy) >= std::max(ext, 1);
+        t.blk.push_back(far ? 1 : 0);
+        t.blk.push_back(int(t.elems));
+        t.blk.push_back(int(k));
+        t.blk.push_back((bi << 16) | bj);
+        t.elems += far ? 2LL * LB * KR : int64_t(LB) * LB;
+        (far ? t.n_lr : t.n_dense) += 1;
+      }
+    t.node.push_back(int(t.blk.size() / 4));
+    t.dense_p += int64_t(g) * G;
+  }
+  return t;
+}
 
 // Row stride of a panel store: gamma rounded up to 4 elements (16-byte rows).
 int panel_ld(int g) { return (g + 3) / 4 * 4; }
@@ -90,6 +178,7 @@ bool make_plan(const hdd_opts& o, Plan& p) {
 // Byte offsets of everything the handle keeps in its device workspace.
 struct Layout {
   std::vector<int64_t> frames, nodes, maps, ids, vec, panel;
+  std::vector<int64_t> lr_perm, lr_node, lr_blk, lr_store, lr_rank;  // low-rank levels (-1 elsewhere)
   int64_t kappa, f, u, d, r, info, bad, act, maxbits, qout, qxy, qy, qsmp, qoff, qsig, lists, iota;
   int64_t cst, bvec, tmaps, tlids, tmicro, origin, text;
   int64_t wts, mu, nmean;  // node means: weight vector, subtree functionals, output staging
@@ -107,6 +196,7 @@ Layout make_layout(const Plan& p, const hdd_opts& o, int ms) {
   };
   const int nd = int(p.levels.size());
   L.frames.resize(nd); L.nodes.resize(nd); L.maps.resize(nd); L.ids.resize(nd); L.vec.resize(nd); L.panel.resize(nd);
+  L.lr_perm.resize(nd); L.lr_node.resize(nd); L.lr_blk.resize(nd); L.lr_store.resize(nd); L.lr_rank.resize(nd);
   const bool refine = refinement_possible(o);
   const bool keep = keep_frames(o);
   // Frames: by default two buffers, level d in buffer d % 2.  A level's
@@ -134,6 +224,16 @@ Layout make_layout(const Plan& p, const hdd_opts& o, int ms) {
     L.vec[d] = take(int64_t(lv.ids.size()) * 8 * ms);
     const bool store = d < nd - 1 && (!keep || merge_level(p, o, d));
     L.panel[d] = store ? take(panel_elems(p, d) * esz * ms) : -1;
+    if (lowrank_level(p, o, d)) {
+      const LowRankTables t = lowrank_tables(p, d);
+      L.lr_perm[d] = take(int64_t(t.perm.size()) * 4);
+      L.lr_node[d] = take(int64_t(t.node.size()) * 4);
+      L.lr_blk[d] = take(int64_t(t.blk.size()) * 4);
+      L.lr_store[d] = take(t.elems * esz * ms);
+      L.lr_rank[d] = take(int64_t(t.blk.size() / 4) * 4 * ms);
+    } else {
+      L.lr_perm[d] = L.lr_node[d] = L.lr_blk[d] = L.lr_store[d] = L.lr_rank[d] = -1;
+    }
     total_nodes += int64_t(lv.nodes.size());
     max_nodes = std::max<int64_t>(max_nodes, int64_t(lv.nodes.size()));
   }
@@ -678,6 +778,20 @@ int create_impl(const hdd_opts* o, int32_t max_samples, void* stream, void* work
     lv.panel = L.panel[d] >= 0 ? h->ws + L.panel[d] : nullptr;
     lv.panel_stride = L.panel[d] >= 0 ? panel_elems(h->plan, d) : 0;
     lv.panel_ld = panel_ld(pl.gam);
+    if (L.lr_store[d] >= 0) {
+      const LowRankTables t = lowrank_tables(h->plan, d);
+      lv.lr_perm = reinterpret_cast<const int*>(h->ws + L.lr_perm[d]);
+      lv.lr_node = reinterpret_cast<const int*>(h->ws + L.lr_node[d]);
+      lv.lr_blk = reinterpret_cast<const int4*>(h->ws + L.lr_blk[d]);
+      lv.lr_store = h->ws + L.lr_store[d];
+      lv.lr_stride = t.elems;
+      lv.lr_rank = reinterpret_cast<int*>(h->ws + L.lr_rank[d]);
+      lv.lr_nblk = int(t.blk.size() / 4);
+      if (upload(h->ws + L.lr_perm[d], t.perm.data(), t.perm.size() * 4) != hipSuccess ||
+          upload(h->ws + L.lr_node[d], t.node.data(), t.node.size() * 4) != hipSuccess ||
+          upload(h->ws + L.lr_blk[d], t.blk.data(), t.blk.size() * 4) != hipSuccess)
+        return fail(HDD_EDEVICE);
+    }
     lv.nodes = reinterpret_cast<const DevNode*>(h->ws + L.nodes[d]);
     lv.maps = reinterpret_cast<const int*>(h->ws + L.maps[d]);
     lv.ids = reinterpret_cast<const int*>(h->ws + L.ids[d]);
@@ -917,6 +1031,14 @@ int build_device(hdd_tree* h) {
     HDD_TRY(timed(h, K_EXTEND, 0.0, [&] { return hdd::launch_extend_add(h->lev[d], h->lev[d + 1], n_samples, h->st); }));
     HDD_TRY(eliminate(d));
   }
+  // block low-rank copies of the wide levels' maps P (refinement sweeps)
+  for (int d = 0; d < D; ++d)
+    if (h->lev[d].lr_store) {
+      h->cur_level = d;
+      // relative accuracy of the blocks: 1e-5 in float32, 1e-8 in float64
+      const double tol = h->lev[d].is_double ? 1e-8 : 1e-5;
+      HDD_TRY(timed(h, K_LOWRANK, 0.0, [&] { return hdd::launch_lr_compress(h->lev[d], n_samples, tol, h->st); }));
+    }
   return hip_status(hdd::launch_fill(h->u, (long long)n_samples * h->nn, 0.0, h->st));
 }
 
@@ -993,6 +1115,39 @@ int hdd_autotune(hdd_handle h, int32_t reps, int32_t* choices) {
   HDD_TRY(hdd_timing_enable(h, saved_mask));
   drop_graphs(h);
   return build_resident(h, ns);  // the handle is left built with the chosen tiles
+}
+
+int hdd_lowrank_info(hdd_handle h, double out[6]) {
+  if (!h || !out) return HDD_EINVAL;
+  for (int q = 0; q < 6; ++q) out[q] = 0.0;
+  if (!h->built) return HDD_ESTATE;
+  const int LB = hdd::kLowRankBlock, KR = hdd::kLowRankMax;
+  const int ns = h->n_samples;
+  double rank_sum = 0.0, used = 0.0, lr_count = 0.0;
+  for (size_t d = 0; d < h->lev.size(); ++d) {
+    const DevLevel& L = h->lev[d];
+    if (!L.lr_store) continue;
+    const LowRankTables t = lowrank_tables(h->plan, int(d));
+    const double esz = L.is_double ? 8.0 : 4.0;
+    std::vector<int> rk(size_t(L.lr_nblk) * ns);
+    HIP_TRY(hipMemcpyAsync(rk.data(), L.lr_rank, rk.size() * 4, hipMemcpyDeviceToHost, h->st));
+    HIP_TRY(hipStreamSynchronize(h->st));
+    out[0] += double(t.dense_p) * esz;
+    out[1] += double(t.elems) * esz;
+    for (int s = 0; s < ns; ++s)
+      for (int b = 0; b < L.lr_nblk; ++b) {
+        const int r = t.blk[4 * b] == 1 ? rk[size_t(s) * L.lr_nblk + b] : -1;  // -1: dense
+        used += (r >= 0 ? 2.0 * LB * r : double(LB) * LB) * esz / ns;
+        if (r >= 0) rank_sum += r, lr_count += 1;
+      }
+    out[4] += t.n_dense + t.n_lr;
+  }
+  out[2] = used;
+  out[3] = lr_count / ns;   // blocks stored at low rank (per sample)
+  out[4] -= out[3];         // blocks stored dense
+  out[5] = lr_count > 0 ? rank_sum / lr_count : 0.0;
+  (void)KR;
+  return HDD_OK;
 }
 
 int hdd_graph_info(hdd_handle h, int64_t out[4]) {

@@ -41,6 +41,15 @@ struct DevLevel {
   void* panel;
   long long panel_stride;  // per-sample elements of the panel store
   int panel_ld;            // row stride of the panel store: gamma rounded up to 4 (16-byte rows)
+  // Block low-rank copy of the maps P of the level (HDD_FLAG_LOWRANK), used
+  // by the refinement sweeps; lr_store is nullptr on levels without it.
+  const int* lr_perm;    // parallel to ids: at ids_off + gamma + k the Gamma position of row k (perimeter order)
+  const int* lr_node;    // [n_nodes + 1]: first block of every node (blocks row-major over 64 x 64 blocks)
+  const int4* lr_blk;    // per block: (0 dense / 1 low rank, offset in a sample's store, node, bi << 16 | bj)
+  void* lr_store;        // [sample][...] float or double: dense blocks 64 x 64, low-rank U (64 x kr) then V (kr x 64)
+  long long lr_stride;   // per-sample elements of lr_store
+  int* lr_rank;          // [sample][block] rank of the low-rank blocks
+  int lr_nblk;           // blocks of the level
   const DevNode* nodes;
   const int* maps;
   const int* ids;

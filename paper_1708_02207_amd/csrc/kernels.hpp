@@ -75,6 +75,15 @@ hipError_t launch_loglik(int n_samples, int n_y, const double* hu, const double*
                          double* out, hipStream_t st);
 hipError_t launch_mfma_selftest(int dtype, double* out, hipStream_t st);
 
+// Block low-rank maps P (kernels_lowrank.hip): blocks of kLowRankBlock x
+// kLowRankBlock, low-rank blocks with at most kLowRankMax rank slots.
+constexpr int kLowRankBlock = 64;
+constexpr int kLowRankMax = 16;
+hipError_t launch_lr_compress(const DevLevel& L, int n_samples, double tol, hipStream_t st);
+hipError_t launch_lr_topdown_gemv(const DevLevel& L, const int* list, int n_list, int n_samples, double* u,
+                                  long long ustride, bool z_from_vec, hipStream_t st);
+hipError_t launch_lr_forward_gemv(const DevLevel& L, int n_samples, hipStream_t st);
+
 // Means over every subdomain of the tree (functional propagation, or the
 // direct sum when the whole field is known).  mu / out: [sample][global node].
 hipError_t launch_block_mu(const DevBlocks& B, int n_samples, double* mu, long long mu_stride, hipStream_t st);

@@ -776,7 +776,10 @@ hipError_t launch_topdown(const DevLevel& L, const int* list, int n_list, int n_
   dim3 grid(n_list * n_samples);
   const int zv = z_from_vec ? 1 : 0;
   const int split = (L.gam >= kSplitGamma && (L.max_U - L.gam) > 0) ? 1 : 0;
-  if (split) {
+  if (split && L.lr_store) {
+    const hipError_t e = launch_lr_topdown_gemv(L, list, n_list, n_samples, u, ustride, z_from_vec, st);
+    if (e != hipSuccess) return e;
+  } else if (split) {
     dim3 g2(n_list * n_samples, ceil_div(L.gam, 64));
     const size_t lds = sizeof(double) * (size_t((L.max_U - L.gam)) + 256);
     if (L.is_double)
@@ -838,6 +841,7 @@ hipError_t launch_forward(const DevLevel& L, const DevLevel& child, int n_sample
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !split) return e;
+  if (L.lr_store) return launch_lr_forward_gemv(L, n_samples, st);
   dim3 g2(L.n_nodes * n_samples, ceil_div((L.max_U - L.gam), 128));
   const size_t lds = sizeof(double) * size_t(L.gam) + size_t(4) * 32 * 65 * (L.is_double ? 8 : 4);
   if (L.is_double)

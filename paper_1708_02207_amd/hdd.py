@@ -32,6 +32,7 @@ HDD_FLAG_KEEP_DIRICHLET = 2
 HDD_FLAG_BLOCK8 = 4
 HDD_FLAG_KEEP_FRAMES = 8
 HDD_FLAG_NO_GRAPH = 16
+HDD_FLAG_LOWRANK = 32
 
 EXPORTED = [
     "hdd_default_opts", "hdd_workspace_size", "hdd_create", "hdd_build", "hdd_query_points",
@@ -41,7 +42,7 @@ EXPORTED = [
     "hdd_timing_enable", "hdd_timing_get", "hdd_mfma_selftest", "hdd_debug_frame",
     "hdd_timing_get_level", "hdd_query_points_ragged", "hdd_loglik_ragged",
     "hdd_server_create", "hdd_server_slots", "hdd_server_submit", "hdd_server_poll", "hdd_server_result",
-    "hdd_server_stats", "hdd_server_destroy", "hdd_sample_status", "hdd_create_static", "hdd_autotune", "hdd_graph_info", "hdd_server_memory",
+    "hdd_server_stats", "hdd_server_destroy", "hdd_sample_status", "hdd_create_static", "hdd_autotune", "hdd_graph_info", "hdd_server_memory", "hdd_lowrank_info",
 ]
 MAX_QUERY_POINTS = 4096
 STATIC_WORKSPACE_BYTES = 64 << 20
@@ -88,6 +89,7 @@ def _load() -> ctypes.CDLL:
         "hdd_create_static": [popts, i32, P, ctypes.POINTER(P)],
         "hdd_autotune": [P, i32, P],
         "hdd_graph_info": [P, P],
+        "hdd_lowrank_info": [P, P],
         "hdd_build": [P, i32, P, P, P, i32],
         "hdd_query_points": [P, i32, P, P, i32],
         "hdd_query_interface": [P, i32, i32, P, ctypes.POINTER(i32), i32],
@@ -412,6 +414,12 @@ class HDD:
         ch = np.zeros(levels, dtype=np.int32)
         _check(_lib.hdd_autotune(self.h, int(reps), _np_ptr(ch)), "hdd_autotune")
         return ch
+
+    def lowrank_info(self) -> dict:
+        out = np.zeros(6)
+        _check(_lib.hdd_lowrank_info(self.h, _np_ptr(out)), "hdd_lowrank_info")
+        return dict(dense_bytes=out[0], store_bytes=out[1], rank_bytes=out[2], lowrank_blocks=int(out[3]),
+                    dense_blocks=int(out[4]), mean_rank=out[5])
 
     def graph_info(self) -> dict:
         out = np.zeros(4, dtype=np.int64)
