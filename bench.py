@@ -425,6 +425,7 @@ def main():
     # functional propagation (bottom-up functional pass, interfaces above the
     # blocks only) against the full Root to Leaves plus the direct sum.
     node_means = None
+    coarse = None
     if not a.no_ablation and prec == H.HDD_FP32_REFINE:
         o64 = H.hdd_default_opts(w.n, H.HDD_FP64, leaf=w.leaf)
         summ = H.hdd_plan_summary(o64)
@@ -444,7 +445,30 @@ def main():
                 if r > 0:
                     tot += time.perf_counter() - t0
             route_ms[route] = 1e3 * tot / reps
+        # u on the coarse mesh of interfaces above depth 4 (cells of 256 x 256)
+        # with Root to Leaves stopped there, against the full Root to Leaves
+        skel_len = sum(H.hdd_plan_level(o64, d)["nodes"] * H.hdd_plan_level(o64, d)["gam"] for d in range(4))
+        skel = torch.empty((B, skel_len), dtype=torch.float64, device=dev)
+        coarse = {}
+        for what in ("skeleton", "full"):
+            reps, tot = 3, 0.0
+            for r in range(reps + 1):
+                c.build(kd, fd)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if what == "full":
+                    c.solve_full()
+                else:
+                    c.query_skeleton(4, out=skel)
+                torch.cuda.synchronize()
+                if r > 0:
+                    tot += time.perf_counter() - t0
+            coarse[what] = 1e3 * tot / reps
         c.close()
+        coarse = {"depth": 4, "skeleton_nodes": int(skel.shape[1]), "skeleton_ms": coarse["skeleton"],
+                  "full_root_to_leaves_ms": coarse["full"], "dtype": "f64", "samples": B,
+                  "note": "u on every interface above depth 4 (Root to Leaves stopped there) against the "
+                          "full Root to Leaves, float64 batch"}
         node_means = {"nodes": summ["nodes"], "samples": B, "dtype": "f64",
                       "functional_ms": route_ms["functional"], "full_field_ms": route_ms["full_field"],
                       "means_per_s": summ["nodes"] * B / (1e-3 * route_ms["functional"]),
@@ -485,6 +509,7 @@ def main():
         "lowrank": lowrank,
         "ablation": ablation,
         "node_means": node_means,
+        "coarse_mesh": coarse,
         "multi_rhs": multi_rhs,
         "kernels_ms_per_step": {k: v["ms"] for k, v in kern.items()},
         "kernels_tflops": {k: v["tflops"] for k, v in kern.items() if v["tflops"]},

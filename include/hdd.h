@@ -185,6 +185,21 @@ int hdd_query_points(hdd_handle h, int32_t n_pts, const double* xy, double* u_ou
 int hdd_query_interface(hdd_handle h, int32_t depth, int32_t index, double* u_out, int32_t* len, int32_t mem);
 
 /*
+ * u_h on a coarse mesh made of interfaces (setup (c) of Fig. HDDidea and the
+ * remark that HDD gives u_h restricted to a coarser grid with reduced
+ * effort; Section 3.5): the fine-mesh solution at every node of the
+ * interfaces gamma of all tree nodes of depth < depth (1 <= depth <= the
+ * depth of the blocks), i.e. on the grid lines that bound the cells of
+ * `depth`.  u_out (mem) float64 [n_samples][*len], nodes in plan order (the
+ * root's gamma first, then depth by depth, each node's gamma along its cut;
+ * the ids of hdd_plan_node).  Without the full field (HDD_FP64 with
+ * max_refine = 0, before hdd_solve_full) Root to Leaves stops above
+ * `depth`: no interface below it and no block interior is solved.  Errors:
+ * HDD_EINVAL (depth), HDD_ESTATE before a build.
+ */
+int hdd_query_skeleton(hdd_handle h, int32_t depth, double* u_out, int32_t* len, int32_t mem);
+
+/*
  * Status of every built sample of the batch (host int32 [n_samples]):
  * HDD_EINVAL (its kappa was non-positive or non-finite), HDD_ENOTSPD (an
  * interface factorization of this sample met a non-positive pivot; its

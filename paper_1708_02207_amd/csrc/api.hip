@@ -1258,6 +1258,35 @@ int hdd_query_interface(hdd_handle h, int32_t depth, int32_t index, double* u_ou
   return copy_out(h, u_out, h->qout, size_t(g) * h->n_samples, HDD_MEM_HOST);
 }
 
+int hdd_query_skeleton(hdd_handle h, int32_t depth, double* u_out, int32_t* len, int32_t mem) {
+  if (!h || !u_out || (mem != HDD_MEM_HOST && mem != HDD_MEM_DEVICE)) return HDD_EINVAL;
+  if (!h->built) return HDD_ESTATE;
+  const int D = int(h->lev.size()) - 1;
+  if (depth < 1 || depth > D) return HDD_EINVAL;
+  // every interface above `depth`; without the full field only these are
+  // solved (Root to Leaves stops at the coarse cells)
+  auto need = empty_need(h);
+  std::vector<int> ids;
+  for (int d = 0; d < depth; ++d) {
+    std::fill(need[d].begin(), need[d].end(), 1);
+    for (const auto& nd : h->plan.levels[d].nodes) ids.insert(ids.end(), nd.gam.begin(), nd.gam.end());
+  }
+  HDD_TRY(prepare_values(h, need));
+  const int n = int(ids.size());
+  if (len) *len = n;
+  // the id list is staged in the residual field (free outside the sweeps)
+  int* ids_dev = reinterpret_cast<int*>(h->r);
+  HIP_TRY(hipMemcpyAsync(ids_dev, ids.data(), size_t(n) * 4, hipMemcpyHostToDevice, h->st));
+  double* dst = u_out;
+  if (mem == HDD_MEM_HOST) {
+    if (size_t(n) * h->n_samples > size_t(h->nn) * h->n_samples) return HDD_EINVAL;
+    dst = h->d;  // staging (the correction field is free outside the sweeps)
+  }
+  HIP_TRY(hdd::launch_gather(n, h->n_samples, ids_dev, h->u, h->nn, dst, h->st));
+  if (mem == HDD_MEM_DEVICE) return hip_status(hipStreamSynchronize(h->st));  // the host id list stays valid until here
+  return copy_out(h, u_out, h->d, size_t(n) * h->n_samples, HDD_MEM_HOST);
+}
+
 int hdd_sample_status(hdd_handle h, int32_t* status) {
   if (!h || !status) return HDD_EINVAL;
   if (!h->built) return HDD_ESTATE;

@@ -42,7 +42,7 @@ EXPORTED = [
     "hdd_timing_enable", "hdd_timing_get", "hdd_mfma_selftest", "hdd_debug_frame",
     "hdd_timing_get_level", "hdd_query_points_ragged", "hdd_loglik_ragged",
     "hdd_server_create", "hdd_server_slots", "hdd_server_submit", "hdd_server_poll", "hdd_server_result",
-    "hdd_server_stats", "hdd_server_destroy", "hdd_sample_status", "hdd_create_static", "hdd_autotune", "hdd_graph_info", "hdd_server_memory", "hdd_lowrank_info",
+    "hdd_server_stats", "hdd_server_destroy", "hdd_sample_status", "hdd_create_static", "hdd_autotune", "hdd_graph_info", "hdd_server_memory", "hdd_lowrank_info", "hdd_query_skeleton",
 ]
 MAX_QUERY_POINTS = 4096
 STATIC_WORKSPACE_BYTES = 64 << 20
@@ -90,6 +90,7 @@ def _load() -> ctypes.CDLL:
         "hdd_autotune": [P, i32, P],
         "hdd_graph_info": [P, P],
         "hdd_lowrank_info": [P, P],
+        "hdd_query_skeleton": [P, i32, P, ctypes.POINTER(i32), i32],
         "hdd_build": [P, i32, P, P, P, i32],
         "hdd_query_points": [P, i32, P, P, i32],
         "hdd_query_interface": [P, i32, i32, P, ctypes.POINTER(i32), i32],
@@ -300,6 +301,24 @@ class HDD:
         op, mem = _ptr(out)
         _check(_lib.hdd_query_interface(self.h, int(depth), int(index), op, ctypes.byref(ln), mem),
                "hdd_query_interface")
+        return out
+
+    def query_skeleton(self, depth: int, out=None):
+        """u on every interface of the nodes above `depth` (plan order),
+        [n_samples][len]; in float64 without the full field only those
+        interfaces are solved."""
+        ln = ctypes.c_int32(0)
+        if out is None:
+            if getattr(self, "_levels", None) is None:  # planning the tree once per handle
+                self._levels = [hdd_plan_level(self.opts, d) for d in range(hdd_plan_summary(self.opts)["levels"])]
+            total = sum(lv["nodes"] * lv["gam"] for lv in self._levels[:depth])
+            res = np.zeros((self.n_samples, total))
+            _check(_lib.hdd_query_skeleton(self.h, int(depth), _np_ptr(res), ctypes.byref(ln), HDD_MEM_HOST),
+                   "hdd_query_skeleton")
+            assert ln.value == total
+            return res
+        op, mem = _ptr(out)
+        _check(_lib.hdd_query_skeleton(self.h, int(depth), op, ctypes.byref(ln), mem), "hdd_query_skeleton")
         return out
 
     def sample_status(self) -> np.ndarray:
