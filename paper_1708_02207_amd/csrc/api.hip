@@ -14,6 +14,7 @@
 #include "hdd.h"
 #include "kernels.hpp"
 #include "plan.hpp"
+#include "trace.hpp"
 
 using hdd::DevLevel;
 using hdd::DevNode;
@@ -516,6 +517,7 @@ int correction_sweeps(hdd_tree* h, int max_it, bool test) {
   h->act_host.assign(ns, 1);
   int n_active = ns;
   for (int it = 0; it < max_it && n_active > 0; ++it) {
+    hdd::Range rg("refinement sweep %d: %d of %d samples", it + 1, n_active, ns);
     // which samples still refine; read by the update at the end of the sweep
     HIP_TRY(hipMemcpyAsync(h->act, h->act_host.data(), sizeof(int) * ns, hipMemcpyHostToDevice, h->st));
     HDD_TRY(run_graph(h, h->g_sweep, [&]() -> int {
@@ -575,6 +577,7 @@ int correction_sweeps(hdd_tree* h, int max_it, bool test) {
 
 int ensure_full(hdd_tree* h) {
   if (h->full) return HDD_OK;
+  hdd::Range rg("full Root to Leaves");
   HDD_TRY(run_graph(h, h->g_solve, [&] { return full_topdown(h, h->u, false); }));
   for (auto& v : h->solved) std::fill(v.begin(), v.end(), 1);
   h->full = true;
@@ -585,6 +588,7 @@ int ensure_full(hdd_tree* h) {
 
 // Solve, root first, the nodes marked in `need` that are not solved yet.
 int partial_topdown(hdd_tree* h, const std::vector<std::vector<uint8_t>>& need) {
+  hdd::Range rg("partial Root to Leaves");
   if (h->lists_done) HIP_TRY(hipEventSynchronize(h->lists_done));
   else HIP_TRY(hipStreamSynchronize(h->st));
   int64_t total = 0;
@@ -1017,11 +1021,13 @@ int build_device(hdd_tree* h) {
     return HDD_OK;
   };
   h->cur_level = D;
+  hdd::Range rg("Leaves to Root: blocks");
   HDD_TRY(timed(h, K_ASSEMBLE, 0.0, [&] {
     return hdd::launch_block_build(h->blk, n_samples, nc, h->kappa, h->f, h->bad, h->info, h->st);
   }));
   for (int d = D - 1; d >= 0; --d) {
     h->cur_level = d;
+    hdd::Range rg("Leaves to Root depth %d", d);
     if (merge_level(h->plan, h->opt, d)) {
       HDD_TRY(timed(h, K_MERGE, 0.0, [&] {
         return hdd::launch_merge_small(h->lev[d], h->lev[d + 1], n_samples, h->info, h->st);
@@ -1044,6 +1050,7 @@ int build_device(hdd_tree* h) {
 
 // Leaves to Root on the kappa and load already in the workspace.
 int build_resident(hdd_tree* h, int n_samples) {
+  hdd::Range rg("hdd_build n=%d samples=%d", h->opt.n, n_samples);
   h->n_samples = n_samples;
   h->built = false;
   h->full = false;
@@ -1082,6 +1089,7 @@ int hdd_autotune(hdd_handle h, int32_t reps, int32_t* choices) {
   if (!h || reps < 1) return HDD_EINVAL;
   if (!h->built) return HDD_ESTATE;
   if (h->no_alloc) return HDD_EINVAL;  // timing events would be allocations
+  hdd::Range rg("hdd_autotune");
   const int nd = int(h->lev.size());
   const int ns = h->n_samples;
   const int saved_mask = h->timing_mask;
@@ -1261,6 +1269,7 @@ int hdd_query_interface(hdd_handle h, int32_t depth, int32_t index, double* u_ou
 int hdd_query_skeleton(hdd_handle h, int32_t depth, double* u_out, int32_t* len, int32_t mem) {
   if (!h || !u_out || (mem != HDD_MEM_HOST && mem != HDD_MEM_DEVICE)) return HDD_EINVAL;
   if (!h->built) return HDD_ESTATE;
+  hdd::Range rg("hdd_query_skeleton depth=%d", depth);
   const int D = int(h->lev.size()) - 1;
   if (depth < 1 || depth > D) return HDD_EINVAL;
   // every interface above `depth`; without the full field only these are
@@ -1328,6 +1337,7 @@ int hdd_query_mean(hdd_handle h, const double rect[4], double* out, int32_t mem)
 int hdd_query_node_means(hdd_handle h, double* out, int32_t mem) {
   if (!h || !out || (mem != HDD_MEM_HOST && mem != HDD_MEM_DEVICE)) return HDD_EINVAL;
   if (!h->built) return HDD_ESTATE;
+  hdd::Range rg("hdd_query_node_means");
   if (!h->full && h->opt.max_refine > 0) HDD_TRY(ensure_full(h));
   const int ns = h->n_samples, nc = h->plan.nc;
   const int D = int(h->lev.size()) - 1;
@@ -1409,6 +1419,7 @@ int hdd_solve_full(hdd_handle h) {
 int hdd_solve_rhs(hdd_handle h, const double* f, const double* g, int32_t mem) {
   if (!h || !f || (mem != HDD_MEM_HOST && mem != HDD_MEM_DEVICE)) return HDD_EINVAL;
   if (!h->built) return HDD_ESTATE;
+  hdd::Range rg("hdd_solve_rhs");
   const size_t fbytes = size_t(h->nn) * 8;
   if (mem == HDD_MEM_HOST) {
     for (long long i = 0; i < h->nn; ++i)
@@ -1422,6 +1433,7 @@ int hdd_solve_rhs(hdd_handle h, const double* f, const double* g, int32_t mem) {
 int hdd_solve_rhs_coarse(hdd_handle h, const double* f_coarse, const double* g, int32_t mem) {
   if (!h || !f_coarse || (mem != HDD_MEM_HOST && mem != HDD_MEM_DEVICE)) return HDD_EINVAL;
   if (!h->built) return HDD_ESTATE;
+  hdd::Range rg("hdd_solve_rhs_coarse");
   const long long m1 = h->plan.nc / 2 + 1;
   if (mem == HDD_MEM_HOST) {
     for (long long i = 0; i < m1 * m1; ++i)

@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "hdd.h"
+#include "trace.hpp"
 
 namespace {
 
@@ -206,6 +207,7 @@ void run_mesh(hdd_server* S, Mesh* m) {
     // did not converge) still deliver every sample's values; each request
     // then gets its own sample's status.  Any other code fails the batch.
     auto per_sample = [](int c) { return c == HDD_OK || c == HDD_ENOTSPD || c == HDD_ENOTCONVERGED; };
+    hdd::Range rg("served batch n=%d requests=%d", m->n, B);
     int st = hdd_build(m->h, B, m->pinned, m->f.data(), nullptr, HDD_MEM_HOST);
     if (per_sample(st)) st = hdd_query_points_ragged(m->h, off.data(), xy.data(), vals.data(), HDD_MEM_HOST);
     if (per_sample(st)) st = hdd_loglik_ragged(m->h, off.data(), xy.data(), y.data(), sig.data(), 0, ll.data(), HDD_MEM_HOST);
