@@ -32,7 +32,7 @@ PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "hbm_gbs": 8000.0}
 # An entry is removed whenever its kernel changes.
 TRAFFIC = {("k_syrk128_f32", "c2_1023", 128): 6.123e9}
 KIND = {"syrk32": 0, "factor": 1, "extend": 2, "block_build": 3, "topdown": 4, "forward": 5, "residual": 6,
-        "syrk64": 7, "syrk128": 8, "merge": 9}
+        "syrk64": 7, "syrk128": 8, "merge": 9, "eliminate": 12}
 
 
 def parse():
@@ -494,7 +494,8 @@ def main():
         "config": {"workload": f"{a.config}: {w.n}^2 interior nodes, {w.leaf}x{w.leaf} leaves, log-normal kappa "
                                f"(var {w.spec['var']}, corr {w.spec['corr']}, {w.spec['n_z']} modes), f=1; "
                                f"64 points + midline + mean[0.25,0.5]^2 + loglik",
-                   "global_batch": B, "precision": a.precision, "parallelism": "1 GPU"},
+                   "global_batch": B, "precision": a.precision, "fp64_top_levels": int(opts.fp64_top_levels),
+                   "parallelism": "1 GPU"},
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "note": "per step (a batch of evaluations)"},
         "accuracy": {"max_rel_err_vs_oracle": err, "refine_sweeps": sweeps,

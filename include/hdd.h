@@ -79,12 +79,17 @@ extern "C" {
                                      the retained factors of every node stay (Section 3.4: the sons' Schur
                                      complements are not needed once the father is built) and frame memory
                                      is reused by every second level */
+#define HDD_FLAG_NO_FUSED 64      /* factor every float32 level by separate extend-add, panel and Schur-
+                                     update launches (no fused merge of gamma <= 31, no fused elimination
+                                     of 33 <= gamma <= 63): a cross-check of the fused kernels */
 
 typedef struct hdd_opts {
   int32_t n;               /* N, interior nodes per side */
   int32_t leaf;            /* leaf size in cells (tree granularity); default 2 * 2^q <= Nc */
   int32_t precision;       /* HDD_FP64 or HDD_FP32_REFINE */
-  int32_t fp64_top_levels; /* HDD_FP32_REFINE: levels (from the root) kept in float64; default 2 */
+  int32_t fp64_top_levels; /* HDD_FP32_REFINE: levels (from the root) kept in float64; default 0
+                              (float64 top levels changed neither the sweep count nor the
+                              refined error from 255^2 to 2047^2) */
   int32_t max_refine;      /* refinement sweeps allowed (HDD_FP32_REFINE default 6; HDD_FP64 default 0) */
   int32_t flags;           /* HDD_FLAG_* */
   double refine_tol;       /* stop once the predicted relative error of the field,
@@ -416,7 +421,9 @@ int hdd_debug_frame(hdd_handle h, int32_t sample, int32_t depth, int32_t index, 
  * of kind 8 are not counted in kind 0), 9 fused merge of narrow float32
  * levels (extend-add, factorization and Schur update in one launch),
  * 10 the functional and readout kernels of hdd_query_node_means, 11 the
- * compression of the block low-rank maps.
+ * compression of the block low-rank maps, 12 fused elimination of float32
+ * levels with 33 <= gamma <= 63 (factorization and Schur update in one
+ * launch after the extend-add).
  * hdd_timing_enable(h, mask): bit k enables kind k (0 disables and clears).
  * hdd_timing_get: total milliseconds, number of launches and summed
  * algorithmic flops of the timed launches (Schur update: 2 K per lower-

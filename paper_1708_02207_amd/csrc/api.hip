@@ -29,10 +29,10 @@ static __device__ __align__(256) unsigned char scratch[HDD_STATIC_WORKSPACE_BYTE
 
 namespace {
 
-constexpr int kKinds = 12;
+constexpr int kKinds = 13;
 enum Kind {
   K_SYRK = 0, K_FACTOR = 1, K_EXTEND = 2, K_ASSEMBLE = 3, K_TOPDOWN = 4, K_FORWARD = 5, K_RESIDUAL = 6, K_SYRK64 = 7,
-  K_SYRK128 = 8, K_MERGE = 9, K_FUNCTIONAL = 10, K_LOWRANK = 11
+  K_SYRK128 = 8, K_MERGE = 9, K_FUNCTIONAL = 10, K_LOWRANK = 11, K_ELIMINATE = 12
 };
 
 int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
@@ -62,7 +62,7 @@ int validate_opts(const hdd_opts* o) {
 // columns in a dense panel store.
 bool merge_level(const Plan& p, const hdd_opts& o, int d) {
   const int D = int(p.levels.size()) - 1;  // the block level
-  if (d < 0 || d >= D || (o.flags & HDD_FLAG_NO_MFMA)) return false;
+  if (d < 0 || d >= D || (o.flags & (HDD_FLAG_NO_MFMA | HDD_FLAG_NO_FUSED))) return false;
   hdd::DevLevel t{};
   t.gam = p.levels[d].gam;
   t.max_U = p.levels[d].max_U;
@@ -680,7 +680,7 @@ int hdd_default_opts(int32_t n, int32_t precision, hdd_opts* o) {
   while (leaf > 2 && (nc % leaf != 0 || leaf > nc)) leaf >>= 1;
   o->leaf = leaf;
   o->precision = precision;
-  o->fp64_top_levels = 2;
+  o->fp64_top_levels = 0;
   o->max_refine = precision == HDD_FP32_REFINE ? 6 : 0;
   o->refine_tol = 2e-9;
   return validate_opts(o);
@@ -993,6 +993,9 @@ int build_device(hdd_tree* h) {
     const int g = L.gam;
     const int syrk_kind = L.is_double ? K_SYRK64 : K_SYRK;
     const int tile_final = h->tile.empty() ? 0 : h->tile[d];
+    // interfaces of 33..63 nodes: factorization and Schur update in one launch
+    if (!(h->opt.flags & HDD_FLAG_NO_FUSED) && hdd::eliminate_mid_ok(L, mfma))
+      return timed(h, K_ELIMINATE, 0.0, [&] { return hdd::launch_eliminate_mid(L, n_samples, h->info, h->st); });
     // Rank-K update C[r0.., c0..c1) -= F[.., k0..k1) F[.., k0..k1)^T, timed;
     // the autotuned tile applies to the Schur update of Gamma, the trailing
     // updates inside the interface follow the built-in rule.

@@ -31,6 +31,11 @@ bool syrk_uses_big_tile(const DevLevel& L, int k0, int k1, int r0, int c0, int c
 // node's panel fits in LDS.
 bool merge_small_ok(const DevLevel& F, bool mfma);
 hipError_t launch_merge_small(const DevLevel& F, const DevLevel& S, int n_samples, int* info, hipStream_t st);
+// Fused factorization + Schur update of a float32 level with gamma = 63
+// (matrix cores), one workgroup per node and sample, on the frame filled by
+// the extend-add, when the node's panel fits in LDS.
+bool eliminate_mid_ok(const DevLevel& L, bool mfma);
+hipError_t launch_eliminate_mid(const DevLevel& L, int n_samples, int* info, hipStream_t st);
 
 // Blocks (in-LDS nested dissection of the leaf interior)
 size_t block_build_lds(const DevBlocks& B, bool dbl);

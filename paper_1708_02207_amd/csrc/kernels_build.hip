@@ -828,6 +828,247 @@ hipError_t launch_merge_small(const DevLevel& F, const DevLevel& S, int n_sample
   return hipGetLastError();
 }
 
+
+
+// ---------------------------------------------------------------------------
+// Fused elimination of one node with an interface of 63 nodes (float32,
+// matrix cores), one workgroup per (node, sample), on the frame that the
+// extend-add has filled (eq. Psi_sum):
+//  1. the panel (the first 63 columns of every frame row) goes to LDS, row r
+//     at P[r * 63 + k] (an odd row length: row-wise reads of one column by
+//     consecutive lanes hit distinct banks), zero above the diagonal of the
+//     interface block;
+//  2. partial Cholesky in two column blocks (eq. gamma, eq. SchurMinus1):
+//     wave 0 factors the first 32 x 32 diagonal block in registers, every
+//     thread solves panel rows against it, the other 31 columns take the
+//     rank-32 update on matrix cores, wave 0 factors the second diagonal
+//     block and every thread solves the rows below it;
+//  3. the panel [L ; P ; z] goes to the level's panel store (or the frame);
+//  4. S_omega = S~ - P P^T (eq. SchurC1) on rows / columns 63..U-1 in
+//     32 x 32 matrix-core tiles, each tile's old values loaded from the frame
+//     before its products;
+//  5. the load row, g_omega = g~ - P z, one column per thread.
+// Operand rows past U are read clamped to row U: they only feed outputs
+// that are not stored.  Each frame entry is read and written once; the
+// panel is read once.
+// ---------------------------------------------------------------------------
+constexpr int kMidGam = 63;
+
+size_t eliminate_mid_lds(int max_U) { return size_t(max_U + 1) * kMidGam * 4; }
+
+// Right-looking Cholesky of the m x m block (m <= 32) that wave 0 holds one
+// row per lane (lane i: a[k] = A_ik for k <= i, zero above); pivots and
+// multipliers by cross-lane reads.  Returns 1 + the first failing pivot (a
+// non-positive or non-finite pivot is replaced by 1), 0 if none.
+__device__ __forceinline__ int chol_block32(float (&a)[32], int m, int lane) {
+  int bp = 0;
+#pragma unroll
+  for (int j = 0; j < 32; ++j) {
+    if (j < m) {
+      float d = lane_value(a[j], j);
+      if (!(d > 0.f) || !(d < 3.0e38f)) {
+        if (!bp) bp = j + 1;
+        d = 1.f;
+      }
+      d = sqrtf(d);
+      a[j] = lane == j ? d : (lane > j ? a[j] / d : a[j]);
+#pragma unroll
+      for (int k = j + 1; k < 32; ++k) {
+        const float ck = lane_value(a[j], k);  // L_kj
+        if (k <= lane) a[k] -= a[j] * ck;
+      }
+    }
+  }
+  return bp;
+}
+
+// One panel row r against a diagonal block of width W starting at column c0
+// (rows of L at D[j * G + c0 + l]): x L^T = a for x = P[r, c0 .. c0+W).
+template <int W>
+__device__ __forceinline__ void solve_row(float* P, const float* D, int r) {
+  constexpr int G = kMidGam;
+  float x[W];
+#pragma unroll
+  for (int k = 0; k < W; ++k) x[k] = P[r * G + k];
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    float v = x[j];
+#pragma unroll
+    for (int l = 0; l < j; ++l) v -= x[l] * D[j * G + l];
+    x[j] = v / D[j * G + j];
+  }
+#pragma unroll
+  for (int k = 0; k < W; ++k) P[r * G + k] = x[k];
+}
+
+// 4 waves per SIMD: two 512-thread workgroups (or one of 1024) per CU.
+template <int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+k_eliminate_mid(DevLevel F, int n_samples, int* info) {
+  constexpr int NW = NT / 64;
+  constexpr int G = kMidGam, G2 = G - 32;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int bad_pivot;
+  const int pair = blockIdx.x;
+  const int node = pair / n_samples;
+  const int s = pair % n_samples;
+  const DevNode nd = F.nodes[node];
+  const int U = nd.U, ld = nd.ld;
+  float* P = reinterpret_cast<float*>(smem);  // [U+1][G]
+  float* Fo = frame_ptr<float>(F, node, s);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (tid == 0) bad_pivot = 0;
+  // 1. panel -> LDS: all loads of a batch issued before its stores
+  {
+    constexpr int UNR = 8;
+    const int total = (U + 1) * G;
+    for (int base = 0; base < total; base += NT * UNR) {
+      float v[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int e = min(base + u * NT + tid, total - 1);
+        const int r = e / G, k = e % G;
+        v[u] = Fo[(long long)r * ld + min(k, r)];
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int e = base + u * NT + tid;
+        const int r = e / G, k = e % G;
+        if (e < total) P[e] = (k <= r) ? v[u] : 0.f;
+      }
+    }
+  }
+  __syncthreads();
+  // 2a. first diagonal block (32 x 32) by wave 0
+  if (tid < 64) {
+    float a[32];
+    const int lc = min(lane, 31);
+#pragma unroll
+    for (int k = 0; k < 32; ++k) a[k] = (lane < 32 && k <= lane) ? P[lc * G + k] : 0.f;
+    const int bp = chol_block32(a, 32, lane);
+    if (lane < 32) {
+#pragma unroll
+      for (int k = 0; k < 32; ++k)
+        if (k <= lane) P[lane * G + k] = a[k];
+    }
+    if (lane == 0 && bp) bad_pivot = bp;
+  }
+  __syncthreads();
+  // 2b. rows 32..U, columns 0..31 (one row per thread)
+  for (int r = 32 + tid; r <= U; r += NT) solve_row<32>(P, P, r);
+  __syncthreads();
+  // 2c. columns 32..62 of rows 32..U: A(r, c) -= sum_{k<32} A(r, k) A(c, k)
+  // on matrix cores, 32-row tiles, columns 32..63 (c = 63 is not stored)
+  for (int t = wv; 32 + t * 32 <= U; t += NW) {
+    const int i0 = 32 + t * 32;
+    const int ra = min(i0 + (lane & 31), U), rb = min(32 + (lane & 31), U);
+    floatx16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 2) {
+      const int k = kk + (lane >> 5);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(P[ra * G + k], P[rb * G + k], acc, 0, 0, 0);
+    }
+    const int c = 32 + (lane & 31);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = i0 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+      if (c < G && c <= i && i <= U) P[i * G + c] -= acc[v];
+    }
+  }
+  __syncthreads();
+  // 2d. second diagonal block (31 x 31) by wave 0
+  if (tid < 64) {
+    float a[32];
+    const int lc = 32 + min(lane, G2 - 1);
+#pragma unroll
+    for (int k = 0; k < 32; ++k) a[k] = (lane < G2 && k <= lane && k < G2) ? P[lc * G + 32 + k] : 0.f;
+    const int bp = chol_block32(a, G2, lane);
+    if (lane < G2) {
+#pragma unroll
+      for (int k = 0; k < G2; ++k)
+        if (k <= lane) P[(32 + lane) * G + 32 + k] = a[k];
+    }
+    if (lane == 0 && bp && !bad_pivot) bad_pivot = 32 + bp;
+  }
+  __syncthreads();
+  // 2e. rows 63..U, columns 32..62 (one row per thread)
+  for (int r = G + tid; r <= U; r += NT) solve_row<G2>(P + 32, P + 32 * G + 32, r);
+  __syncthreads();
+  if (tid == 0 && bad_pivot && info) atomicCAS(info + s, 0, F.node_base + node + 1);
+  // 3. panel -> the level's panel store ((U+1) x G, row stride panel_ld,
+  // zero above the diagonal of L), or the frame's first G columns
+  if (F.panel) {
+    float* Po = panel_ptr<float>(F, node, s);
+    const int pld = F.panel_ld;
+    for (int e = tid; e < (U + 1) * G; e += NT) Po[(long long)(e / G) * pld + e % G] = P[e];
+  } else {
+    for (int e = tid; e < (U + 1) * G; e += NT) {
+      const int r = e / G, k = e % G;
+      if (k <= r) Fo[(long long)r * ld + k] = P[e];
+    }
+  }
+  // 4. Schur update tiles over rows / columns G..U-1 (lower tiles only)
+  const int nt = (U - G + 31) / 32;
+  for (int t = wv; t < nt * (nt + 1) / 2; t += NW) {
+    const int ti = tri_row(t), tj = t - ti * (ti + 1) / 2;
+    const int i0 = G + ti * 32, j0 = G + tj * 32;
+    const int j = j0 + (lane & 31);
+    float old[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = i0 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+      old[v] = Fo[(long long)min(i, U - 1) * ld + min(j, U - 1)];
+    }
+    const float* pa = P + min(i0 + (lane & 31), U) * G + (lane >> 5);
+    const float* pb = P + min(j, U) * G + (lane >> 5);
+    floatx16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+#pragma unroll
+    for (int kk = 0; kk < G - 1; kk += 2)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[kk], pb[kk], acc, 0, 0, 0);
+    {  // k = 62 (lanes 0..31) and the zero column 63 (lanes 32..63)
+      const int q = (lane >> 5) ? 0 : G - 1;
+      const float av = pa[q];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32((lane >> 5) ? 0.f : av, pb[q], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = i0 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+      if (i < U && j <= i) Fo[(long long)i * ld + j] = old[v] - acc[v];
+    }
+  }
+  // 5. the load row: g_omega = g~ - P z (eq. SchurC1), one column per thread
+  for (int j = G + tid; j <= U; j += NT) {
+    const float o = Fo[(long long)U * ld + j];
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < G; ++k) acc += P[U * G + k] * P[j * G + k];
+    Fo[(long long)U * ld + j] = o - acc;
+  }
+}
+
+// Interfaces of 63 nodes on float32 matrix-core levels whose panel fits in
+// LDS.  Two workgroups share a CU while the panel takes at most half of its
+// LDS; larger panels get 1024 threads.
+bool eliminate_mid_ok(const DevLevel& L, bool mfma) {
+  if (!mfma || L.is_double || L.gam != kMidGam || L.max_U <= L.gam) return false;
+  return eliminate_mid_lds(L.max_U) <= kMaxDynLds;
+}
+
+hipError_t launch_eliminate_mid(const DevLevel& L, int n_samples, int* info, hipStream_t st) {
+  if (!eliminate_mid_ok(L, true)) return hipErrorInvalidValue;
+  const size_t lds = eliminate_mid_lds(L.max_U);
+  dim3 grid(L.n_nodes * n_samples);
+  if (lds <= 80 * 1024)
+    hipLaunchKernelGGL(k_eliminate_mid<512>, grid, dim3(512), lds, st, L, n_samples, info);
+  else
+    hipLaunchKernelGGL(k_eliminate_mid<1024>, grid, dim3(1024), lds, st, L, n_samples, info);
+  return hipGetLastError();
+}
+
 // Plain FMA version of the same update (no matrix cores), kept as a
 // cross-check of the MFMA lane layouts.
 template <typename T>

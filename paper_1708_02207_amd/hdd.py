@@ -33,6 +33,7 @@ HDD_FLAG_BLOCK8 = 4
 HDD_FLAG_KEEP_FRAMES = 8
 HDD_FLAG_NO_GRAPH = 16
 HDD_FLAG_LOWRANK = 32
+HDD_FLAG_NO_FUSED = 64
 
 EXPORTED = [
     "hdd_default_opts", "hdd_workspace_size", "hdd_create", "hdd_build", "hdd_query_points",

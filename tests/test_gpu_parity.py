@@ -126,15 +126,19 @@ def test_node_schur_bruteforce(H, oracle_mod, n, leaf, flags):
     t.close()
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("n,leaf", [(63, 8), (127, 16)])
-def test_node_schur_fp32(H, oracle_mod, n, leaf):
-    """The float32 matrix-core levels (fused narrow-interface merges and the
-    panel + Schur-update path) produce S_omega and g_omega equal to the dense
-    Schur complement of the subdomain's own matrix to float32 accuracy."""
+def test_node_schur_fp32(H, oracle_mod, n, leaf, fused):
+    """The float32 matrix-core levels (fused narrow-interface merges, the fused
+    elimination of 63-node interfaces, and the separate panel + Schur-update
+    launches that HDD_FLAG_NO_FUSED selects everywhere) produce S_omega and
+    g_omega equal to the dense Schur complement of the subdomain's own matrix
+    to float32 accuracy."""
     O = oracle_mod
     kappa = np.random.default_rng(5).uniform(0.2, 5.0, size=(1, n + 1, n + 1, 2))
     f = np.random.default_rng(6).uniform(0.0, 1.0, size=(n + 2, n + 2))
-    o = H.hdd_default_opts(n, H.HDD_FP32_REFINE, leaf=leaf, flags=H.HDD_FLAG_KEEP_FRAMES)
+    flags = H.HDD_FLAG_KEEP_FRAMES | (0 if fused else H.HDD_FLAG_NO_FUSED)
+    o = H.hdd_default_opts(n, H.HDD_FP32_REFINE, leaf=leaf, flags=flags)
     t = H.HDD(o, 1)
     t.build(kappa, f)
     nc = n + 1
