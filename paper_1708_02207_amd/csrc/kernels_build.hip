@@ -834,34 +834,38 @@ hipError_t launch_merge_small(const DevLevel& F, const DevLevel& S, int n_sample
 // Fused elimination of one node with an interface of 63 nodes (float32,
 // matrix cores), one workgroup per (node, sample), on the frame that the
 // extend-add has filled (eq. Psi_sum):
-//  1. the panel (the first 63 columns of every frame row) goes to LDS, row r
-//     at P[r * 63 + k] (an odd row length: row-wise reads of one column by
-//     consecutive lanes hit distinct banks), zero above the diagonal of the
-//     interface block;
-//  2. partial Cholesky in two column blocks (eq. gamma, eq. SchurMinus1):
-//     wave 0 factors the first 32 x 32 diagonal block in registers, every
-//     thread solves panel rows against it, the other 31 columns take the
-//     rank-32 update on matrix cores, wave 0 factors the second diagonal
-//     block and every thread solves the rows below it;
-//  3. the panel [L ; P ; z] goes to the level's panel store (or the frame);
+//  1. wave 0 reads the first 32 x 32 diagonal block into registers and
+//     factors it (eq. gamma, eq. SchurMinus1) while the other waves bring
+//     the rest of the panel (the first 63 columns of every frame row) to
+//     LDS, row r at P[r * 63 + k] (an odd row length: one column read by
+//     consecutive lanes hits distinct banks), zero above the diagonal;
+//  2. every thread solves panel rows against the first block, the other 31
+//     columns take the rank-32 update on matrix cores, wave 0 factors the
+//     second diagonal block while the other waves write the finished first
+//     32 columns out, and every thread solves the rows below it;
+//  3. the rest of the panel [L ; P ; z] goes to the level's panel store (or
+//     the frame);
 //  4. S_omega = S~ - P P^T (eq. SchurC1) on rows / columns 63..U-1 in
 //     32 x 32 matrix-core tiles, each tile's old values loaded from the frame
 //     before its products;
 //  5. the load row, g_omega = g~ - P z, one column per thread.
 // Operand rows past U are read clamped to row U: they only feed outputs
 // that are not stored.  Each frame entry is read and written once; the
-// panel is read once.
+// panel is read once.  Pivots are applied as reciprocals.
 // ---------------------------------------------------------------------------
 constexpr int kMidGam = 63;
 
-size_t eliminate_mid_lds(int max_U) { return size_t(max_U + 1) * kMidGam * 4; }
+size_t eliminate_mid_lds(int max_U) { return size_t(max_U + 1) * kMidGam * 4 + 64 * 4; }
 
 // Right-looking Cholesky of the m x m block (m <= 32) that wave 0 holds one
-// row per lane (lane i: a[k] = A_ik for k <= i, zero above); pivots and
-// multipliers by cross-lane reads.  Returns 1 + the first failing pivot (a
-// non-positive or non-finite pivot is replaced by 1), 0 if none.
-__device__ __forceinline__ int chol_block32(float (&a)[32], int m, int lane) {
+// row per lane (lane i: a[k] = A_ik for k <= i); pivots and multipliers by
+// cross-lane reads.  Entries above the diagonal are updated like the others
+// but never read, so no masks are needed.  Leaves 1 / L_ii in rd of lane i;
+// returns 1 + the first failing pivot (a non-positive or non-finite pivot
+// is replaced by 1), 0 if none.
+__device__ __forceinline__ int chol_block32(float (&a)[32], int m, int lane, float& rd) {
   int bp = 0;
+  rd = 1.f;
 #pragma unroll
   for (int j = 0; j < 32; ++j) {
     if (j < m) {
@@ -871,21 +875,21 @@ __device__ __forceinline__ int chol_block32(float (&a)[32], int m, int lane) {
         d = 1.f;
       }
       d = sqrtf(d);
-      a[j] = lane == j ? d : (lane > j ? a[j] / d : a[j]);
+      const float r = 1.f / d;
+      if (lane == j) rd = r;
+      a[j] = lane == j ? d : a[j] * r;
 #pragma unroll
-      for (int k = j + 1; k < 32; ++k) {
-        const float ck = lane_value(a[j], k);  // L_kj
-        if (k <= lane) a[k] -= a[j] * ck;
-      }
+      for (int k = j + 1; k < 32; ++k) a[k] -= a[j] * lane_value(a[j], k);  // L_kj
     }
   }
   return bp;
 }
 
-// One panel row r against a diagonal block of width W starting at column c0
-// (rows of L at D[j * G + c0 + l]): x L^T = a for x = P[r, c0 .. c0+W).
+// One panel row r against a diagonal block of width W starting at column c0:
+// x L^T = a for x = P[r, c0 .. c0+W), with the rows of L at D[j * G + l] and
+// the reciprocal pivots in rd.
 template <int W>
-__device__ __forceinline__ void solve_row(float* P, const float* D, int r) {
+__device__ __forceinline__ void solve_row(float* P, const float* D, const float* rd, int r) {
   constexpr int G = kMidGam;
   float x[W];
 #pragma unroll
@@ -895,7 +899,7 @@ __device__ __forceinline__ void solve_row(float* P, const float* D, int r) {
     float v = x[j];
 #pragma unroll
     for (int l = 0; l < j; ++l) v -= x[l] * D[j * G + l];
-    x[j] = v / D[j * G + j];
+    x[j] = v * rd[j];
   }
 #pragma unroll
   for (int k = 0; k < W; ++k) P[r * G + k] = x[k];
@@ -915,49 +919,56 @@ k_eliminate_mid(DevLevel F, int n_samples, int* info) {
   const DevNode nd = F.nodes[node];
   const int U = nd.U, ld = nd.ld;
   float* P = reinterpret_cast<float*>(smem);  // [U+1][G]
+  float* rdg = P + (U + 1) * G;               // [64] reciprocal pivots
   float* Fo = frame_ptr<float>(F, node, s);
+  float* Po = F.panel ? panel_ptr<float>(F, node, s) : nullptr;
+  const int pld = F.panel_ld;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid == 0) bad_pivot = 0;
-  // 1. panel -> LDS: all loads of a batch issued before its stores
-  {
+  // panel entry (r, k) -> the panel store, or the frame's first G columns
+  auto put = [&](int r, int k, float v) {
+    if (Po) Po[(long long)r * pld + k] = v;
+    else Fo[(long long)r * ld + k] = v;
+  };
+  if (wv == 0) {
+    // 1a. first diagonal block straight from the frame, factored in registers
+    float a[32];
+    const int lc = min(lane, 31);
+#pragma unroll
+    for (int k = 0; k < 32; ++k) a[k] = Fo[(long long)lc * ld + min(k, lc)];
+    float rd;
+    const int bp = chol_block32(a, 32, lane, rd);
+    if (lane < 32) {
+#pragma unroll
+      for (int k = 0; k < 32; ++k) P[lane * G + k] = k <= lane ? a[k] : 0.f;
+      rdg[lane] = rd;
+    }
+    if (lane == 0) bad_pivot = bp;
+  } else {
+    // 1b. the rest of the panel -> LDS (all loads of a batch before its stores)
     constexpr int UNR = 8;
+    const int t0 = tid - 64;
     const int total = (U + 1) * G;
-    for (int base = 0; base < total; base += NT * UNR) {
+    for (int base = 0; base < total; base += (NT - 64) * UNR) {
       float v[UNR];
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const int e = min(base + u * NT + tid, total - 1);
+        const int e = min(base + u * (NT - 64) + t0, total - 1);
         const int r = e / G, k = e % G;
         v[u] = Fo[(long long)r * ld + min(k, r)];
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const int e = base + u * NT + tid;
+        const int e = base + u * (NT - 64) + t0;
         const int r = e / G, k = e % G;
-        if (e < total) P[e] = (k <= r) ? v[u] : 0.f;
+        if (e < total && (r >= 32 || k >= 32)) P[e] = (k <= r) ? v[u] : 0.f;
       }
     }
   }
   __syncthreads();
-  // 2a. first diagonal block (32 x 32) by wave 0
-  if (tid < 64) {
-    float a[32];
-    const int lc = min(lane, 31);
-#pragma unroll
-    for (int k = 0; k < 32; ++k) a[k] = (lane < 32 && k <= lane) ? P[lc * G + k] : 0.f;
-    const int bp = chol_block32(a, 32, lane);
-    if (lane < 32) {
-#pragma unroll
-      for (int k = 0; k < 32; ++k)
-        if (k <= lane) P[lane * G + k] = a[k];
-    }
-    if (lane == 0 && bp) bad_pivot = bp;
-  }
+  // 2a. rows 32..U, columns 0..31 (one row per thread)
+  for (int r = 32 + tid; r <= U; r += NT) solve_row<32>(P, P, rdg, r);
   __syncthreads();
-  // 2b. rows 32..U, columns 0..31 (one row per thread)
-  for (int r = 32 + tid; r <= U; r += NT) solve_row<32>(P, P, r);
-  __syncthreads();
-  // 2c. columns 32..62 of rows 32..U: A(r, c) -= sum_{k<32} A(r, k) A(c, k)
+  // 2b. columns 32..62 of rows 32..U: A(r, c) -= sum_{k<32} A(r, k) A(c, k)
   // on matrix cores, 32-row tiles, columns 32..63 (c = 63 is not stored)
   for (int t = wv; 32 + t * 32 <= U; t += NW) {
     const int i0 = 32 + t * 32;
@@ -978,36 +989,37 @@ k_eliminate_mid(DevLevel F, int n_samples, int* info) {
     }
   }
   __syncthreads();
-  // 2d. second diagonal block (31 x 31) by wave 0
-  if (tid < 64) {
+  if (wv == 0) {
+    // 2c. second diagonal block (31 x 31) by wave 0
     float a[32];
     const int lc = 32 + min(lane, G2 - 1);
 #pragma unroll
-    for (int k = 0; k < 32; ++k) a[k] = (lane < G2 && k <= lane && k < G2) ? P[lc * G + 32 + k] : 0.f;
-    const int bp = chol_block32(a, G2, lane);
+    for (int k = 0; k < 32; ++k) a[k] = k < G2 ? P[lc * G + 32 + min(k, lane)] : 0.f;
+    float rd;
+    const int bp = chol_block32(a, G2, lane, rd);
     if (lane < G2) {
 #pragma unroll
       for (int k = 0; k < G2; ++k)
         if (k <= lane) P[(32 + lane) * G + 32 + k] = a[k];
+      rdg[32 + lane] = rd;
     }
     if (lane == 0 && bp && !bad_pivot) bad_pivot = 32 + bp;
+  } else {
+    // 3a. meanwhile: the finished columns 0..31 of every row go out
+    for (int e = tid - 64; e < (U + 1) * 32; e += NT - 64) {
+      const int r = e >> 5, k = e & 31;
+      if (k <= r) put(r, k, P[r * G + k]);
+    }
   }
   __syncthreads();
-  // 2e. rows 63..U, columns 32..62 (one row per thread)
-  for (int r = G + tid; r <= U; r += NT) solve_row<G2>(P + 32, P + 32 * G + 32, r);
+  // 2d. rows 63..U, columns 32..62 (one row per thread)
+  for (int r = G + tid; r <= U; r += NT) solve_row<G2>(P + 32, P + 32 * G + 32, rdg + 32, r);
   __syncthreads();
   if (tid == 0 && bad_pivot && info) atomicCAS(info + s, 0, F.node_base + node + 1);
-  // 3. panel -> the level's panel store ((U+1) x G, row stride panel_ld,
-  // zero above the diagonal of L), or the frame's first G columns
-  if (F.panel) {
-    float* Po = panel_ptr<float>(F, node, s);
-    const int pld = F.panel_ld;
-    for (int e = tid; e < (U + 1) * G; e += NT) Po[(long long)(e / G) * pld + e % G] = P[e];
-  } else {
-    for (int e = tid; e < (U + 1) * G; e += NT) {
-      const int r = e / G, k = e % G;
-      if (k <= r) Fo[(long long)r * ld + k] = P[e];
-    }
+  // 3b. columns 32..62 of rows 32..U
+  for (int e = tid; e < (U - 31) * G2; e += NT) {
+    const int r = 32 + e / G2, k = 32 + e % G2;
+    if (k <= r) put(r, k, P[r * G + k]);
   }
   // 4. Schur update tiles over rows / columns G..U-1 (lower tiles only)
   const int nt = (U - G + 31) / 32;
