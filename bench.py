@@ -30,7 +30,7 @@ PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "hbm_gbs": 8000.0}
 # passes, each scaled by what the counter reads for a 1 GiB device copy
 # (profiles/k_syrk128_f32_c2_1023_b128.md), keyed (kernel, config, batch).
 # An entry is removed whenever its kernel changes.
-TRAFFIC = {("k_syrk128_f32", "c2_1023", 128): 6.123e9}
+TRAFFIC = {("k_syrk128_f32", "c2_1023", 128): 5.716e9}
 KIND = {"syrk32": 0, "factor": 1, "extend": 2, "block_build": 3, "topdown": 4, "forward": 5, "residual": 6,
         "syrk64": 7, "syrk128": 8, "merge": 9, "eliminate": 12}
 
@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=96, help="requests per arrival rate in the serving mix")
     ap.add_argument("--no-graph", action="store_true", help="issue every launch eagerly (no captured HIP graphs)")
     ap.add_argument("--no-autotune", action="store_true", help="built-in tile rule instead of the autotuner")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the 255^2 x 256 and 2047^2 workloads reported beside the headline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run 3 device-to-device copies of BYTES (calibrates HBM byte counters) and exit")
     return ap.parse_args()
@@ -199,6 +201,57 @@ def serving_1023(H, n_req: int, seed: int):
     return out
 
 
+def other_workloads(H, stream, steps: int):
+    """Throughput of the batched 255^2 workload (256 samples, 16 points and
+    the log-likelihood per sample) and of the 2047^2 high-contrast workload
+    (8 samples, 128 points and the root interface per sample), float32 +
+    refinement against float64, with the refined error against the float64
+    path of the same batch."""
+    import torch
+
+    from workload import make_workload
+
+    out = {}
+    for name, ns in (("c1_255", 256), ("c4_2047", 8)):
+        w = make_workload(name, n_samples=ns)
+        dev = torch.device("cuda:0")
+        kd = torch.from_numpy(w.kappa).to(dev)
+        fd = torch.from_numpy(w.f).to(dev)
+        yd = torch.zeros(len(w.points), dtype=torch.float64, device=dev)
+        pts = torch.empty(ns * len(w.points), dtype=torch.float64, device=dev)
+        ll = torch.empty(ns, dtype=torch.float64, device=dev)
+        res, vals = {}, {}
+        for prec, key in ((H.HDD_FP32_REFINE, "fp32_refine"), (H.HDD_FP64, "fp64")):
+            t = H.HDD(H.hdd_default_opts(w.n, prec, leaf=w.leaf), ns, stream=stream)
+
+            def step():
+                t.build(kd, fd)
+                t.query_points(w.points, out=pts)
+                t.loglik(w.points, yd, w.sigma_y, False, out=ll)
+                if w.spec["interface"]:
+                    t.query_interface(0, 0)
+
+            step()
+            if prec == H.HDD_FP32_REFINE:
+                t.autotune(1)
+            step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            _, sw = t.error_estimate()
+            vals[key] = pts.cpu().numpy().reshape(ns, -1)
+            res[key] = {"value": ns / dt, "ms_per_step": 1e3 * dt, "refine_sweeps": int(np.max(sw))}
+            t.close()
+        ref = vals["fp64"]
+        res["fp32_refine"]["max_rel_err_vs_fp64"] = float(
+            max(np.abs(vals["fp32_refine"][s] - ref[s]).max() / np.abs(ref[s]).max() for s in range(ns)))
+        out[name] = {"samples": ns, "unit": "likelihood evals/s", **res}
+    return out
+
+
 def main():
     a = parse()
     if a.copy_probe > 0:
@@ -280,7 +333,7 @@ def main():
         err = max(errs) if errs else None
 
     # per-kernel event timing over extra profiled steps
-    t.timing_enable((1 << len(KIND)) - 1)
+    t.timing_enable(sum(1 << k for k in KIND.values()))
     for _ in range(a.profile_steps):
         step()
     kern = {}
@@ -362,6 +415,35 @@ def main():
                    "mean_rank": info["mean_rank"]}
         t.close()
         del t
+
+    # The same step with every level in float32 (fp64_top_levels = 0)
+    all_f32 = None
+    if not a.no_ablation and prec == H.HDD_FP32_REFINE:
+        o32 = H.hdd_default_opts(w.n, prec, leaf=w.leaf)
+        o32.fp64_top_levels = 0
+        t = H.HDD(o32, a.batch, stream=stream)
+        step()
+        t.autotune(1)
+        step()
+        torch.cuda.synchronize()
+        n32 = max(2, a.steps // 2)
+        l0 = time.perf_counter()
+        for _ in range(n32):
+            step()
+        torch.cuda.synchronize()
+        d32 = time.perf_counter() - l0
+        _, sw32 = t.error_estimate()
+        err32 = None
+        if gold:
+            P = pts.cpu().numpy().reshape(B, -1)
+            err32 = max(float(np.abs(P[g["sample"]] - np.array(g["points"])).max() / np.abs(np.array(g["points"])).max())
+                        for g in gold["samples"] if g["sample"] < B)
+        all_f32 = {"fp64_top_levels": 0, "value": B * n32 / d32, "ms_per_step": 1e3 * d32 / n32,
+                   "refine_sweeps": int(np.max(sw32)), "max_rel_err_vs_oracle": err32}
+        t.close()
+        del t
+
+    others = None if (a.no_other or a.no_ablation) else other_workloads(H, stream, max(2, a.steps // 2))
 
     comparator = None
     if not a.no_comparator:
@@ -508,6 +590,8 @@ def main():
                              "replayed from captured HIP graphs"},
         "autotune_tiles": tiles,
         "lowrank": lowrank,
+        "all_float32": all_f32,
+        "other_workloads": others,
         "ablation": ablation,
         "node_means": node_means,
         "coarse_mesh": coarse,

@@ -680,7 +680,7 @@ int hdd_default_opts(int32_t n, int32_t precision, hdd_opts* o) {
   while (leaf > 2 && (nc % leaf != 0 || leaf > nc)) leaf >>= 1;
   o->leaf = leaf;
   o->precision = precision;
-  o->fp64_top_levels = 0;
+  o->fp64_top_levels = 2;
   o->max_refine = precision == HDD_FP32_REFINE ? 6 : 0;
   o->refine_tol = 2e-9;
   return validate_opts(o);

@@ -109,14 +109,15 @@ def test_plan_flops_match_dense_count(H):
 
 
 def test_precision_levels(H):
-    """float32 at every level by default in the refinement mode, the top
-    fp64_top_levels levels in float64 on request, all float64 in FP64 mode."""
+    """In the refinement mode the top fp64_top_levels levels (default 2) are
+    float64 and the others float32; 0 makes every level float32; the FP64
+    mode is float64 throughout."""
     o = H.hdd_default_opts(255, H.HDD_FP32_REFINE, leaf=16)
-    assert o.fp64_top_levels == 0
-    assert not any(H.hdd_plan_level(o, d)["fp64"] for d in range(H.hdd_plan_summary(o)["levels"]))
-    o = H.hdd_default_opts(255, H.HDD_FP32_REFINE, leaf=16, fp64_top_levels=2)
+    assert o.fp64_top_levels == 2
     assert H.hdd_plan_level(o, 0)["fp64"] and H.hdd_plan_level(o, 1)["fp64"]
     assert not H.hdd_plan_level(o, 2)["fp64"]
+    o = H.hdd_default_opts(255, H.HDD_FP32_REFINE, leaf=16, fp64_top_levels=0)
+    assert not any(H.hdd_plan_level(o, d)["fp64"] for d in range(H.hdd_plan_summary(o)["levels"]))
     o = H.hdd_default_opts(255, H.HDD_FP64, leaf=16)
     assert all(H.hdd_plan_level(o, d)["fp64"] for d in range(H.hdd_plan_summary(o)["levels"]))
 
