@@ -1021,18 +1021,30 @@ k_eliminate_mid(DevLevel F, int n_samples, int* info) {
     const int r = 32 + e / G2, k = 32 + e % G2;
     if (k <= r) put(r, k, P[r * G + k]);
   }
-  // 4. Schur update tiles over rows / columns G..U-1 (lower tiles only)
+  // 4. Schur update tiles over rows / columns G..U-1 (lower tiles only); the
+  // old values of a wave's next tile are loaded while its current tile is
+  // multiplied
   const int nt = (U - G + 31) / 32;
-  for (int t = wv; t < nt * (nt + 1) / 2; t += NW) {
+  const int ntiles = nt * (nt + 1) / 2;
+  auto load_old = [&](int t, float (&o)[16]) {
+    const int ti = tri_row(t), tj = t - ti * (ti + 1) / 2;
+    const int i0 = G + ti * 32, j = G + tj * 32 + (lane & 31);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = i0 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+      o[v] = Fo[(long long)min(i, U - 1) * ld + min(j, U - 1)];
+    }
+  };
+  float nxt[16];
+  if (wv < ntiles) load_old(wv, nxt);
+  for (int t = wv; t < ntiles; t += NW) {
     const int ti = tri_row(t), tj = t - ti * (ti + 1) / 2;
     const int i0 = G + ti * 32, j0 = G + tj * 32;
     const int j = j0 + (lane & 31);
     float old[16];
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int i = i0 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-      old[v] = Fo[(long long)min(i, U - 1) * ld + min(j, U - 1)];
-    }
+    for (int v = 0; v < 16; ++v) old[v] = nxt[v];
+    if (t + NW < ntiles) load_old(t + NW, nxt);
     const float* pa = P + min(i0 + (lane & 31), U) * G + (lane >> 5);
     const float* pb = P + min(j, U) * G + (lane >> 5);
     floatx16 acc;

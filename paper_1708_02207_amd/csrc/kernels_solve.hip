@@ -184,37 +184,6 @@ __device__ __forceinline__ void rows_dot_thread(const T* F, int ld, int r0, int 
   }
 }
 
-// Same product for nc <= 64 columns by a single wave through an LDS tile
-// (64 rows x 65): 64 rows are read with lanes over the columns (coalesced)
-// into tile[row][col], then each lane sums its own row against x, so no
-// cross-lane reduction is needed.  The tile is private to the wave (LDS
-// operations of one wave complete in order).
-template <typename T, typename Fn>
-__device__ __forceinline__ void rows_dot_wave64(const T* F, int ld, int r0, int r1, int c0, int nc, const double* x,
-                                                T* tile, Fn&& fn) {
-  const int lane = threadIdx.x & 63;
-  const int cl = min(lane, nc - 1);
-  const bool cok = lane < nc;
-  for (int rb = r0; rb < r1; rb += 64) {
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      T v[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int r = min(rb + b * 16 + q, r1 - 1);
-        v[q] = F[(long long)r * ld + c0 + cl];
-      }
-#pragma unroll
-      for (int q = 0; q < 16; ++q) tile[(b * 16 + q) * 65 + lane] = cok ? v[q] : T(0);
-    }
-    double acc = 0.0;
-    const T* row = tile + lane * 65;
-#pragma unroll 16
-    for (int c = 0; c < nc; ++c) acc += double(row[c]) * x[c];
-    if (rb + lane < r1) fn(rb + lane, acc);
-  }
-}
-
 // General form for one wave: TR rows per tile, any number of columns (in
 // chunks of 64).  tile: TR x 65 elements private to the wave.
 template <typename T, int TR, typename Fn>
@@ -421,8 +390,8 @@ __global__ void __launch_bounds__(BS) k_forward(DevLevel L, DevLevel C, int n_sa
   if (defer_gemv) {
     for (int j = tid; j < G; j += BS) out[g + j] = gt[g + j];
   } else if constexpr (BS == 64) {
-    T* tile = reinterpret_cast<T*>(dyn + (L.max_U + 1));  // 64 x 65
-    if (G > 0) rows_dot_wave64<T>(F, ld, g, g + G, 0, g, gt, tile, [&](int r, double y) { out[r] = gt[r] - y; });
+    T* tile = reinterpret_cast<T*>(dyn + (L.max_U + 1));  // 32 x 65
+    if (G > 0) rows_dot_tile<T, 32>(F, ld, g, g + G, 0, g, gt, tile, [&](int r, double y) { out[r] = gt[r] - y; });
   } else {
     rows_dot_thread<T, BS>(F, ld, g, g + G, 0, g, gt, [&](int r, double y) { out[r] = gt[r] - y; });
   }
@@ -826,7 +795,7 @@ hipError_t launch_forward(const DevLevel& L, const DevLevel& child, int n_sample
     else
       hipLaunchKernelGGL((k_forward<float, 1024>), grid, dim3(1024), lds, st, L, child, n_samples, split);
   } else if (L.gam <= 64) {
-    const size_t tile = size_t(64) * 65 * (L.is_double ? 8 : 4);
+    const size_t tile = size_t(32) * 65 * (L.is_double ? 8 : 4);
     const size_t lds = sizeof(double) * size_t(L.max_U + 1) + tile;
     if (L.is_double)
       hipLaunchKernelGGL((k_forward<double, 64>), grid, dim3(64), lds, st, L, child, n_samples, split);
