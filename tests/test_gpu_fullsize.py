@@ -119,6 +119,37 @@ def test_c2_1023(H, oracle_mod, prec):
     t.close()
 
 
+@pytest.mark.parametrize("variant", ["no_fused", "all_float32"])
+def test_c2_1023_variants(H, variant):
+    """The same stored oracle values at 1023^2 from the separate extend-add,
+    panel and Schur-update launches on every level (HDD_FLAG_NO_FUSED, the
+    cross-check of the fused merges), and with every level in float32
+    (fp64_top_levels = 0, the variant the benchmark reports beside the
+    headline)."""
+    g = gold("c2_1023")
+    w = make_workload("c2_1023")
+    ns = len(g["samples"])
+    say("c2_1023 variant", variant)
+    o = H.hdd_default_opts(w.n, H.HDD_FP32_REFINE, leaf=w.leaf)
+    if variant == "no_fused":
+        o.flags = H.HDD_FLAG_NO_FUSED
+    else:
+        o.fp64_top_levels = 0
+    t = H.HDD(o, ns)
+    t.build(torch.from_numpy(w.kappa[:ns]).cuda(), torch.from_numpy(w.f).cuda())
+    pts = t.query_points(np.array(g["points"]))
+    iface = t.query_interface()
+    mean = t.query_mean(g["mean_rect"])
+    for s in g["samples"]:
+        k = s["sample"]
+        e = (rel(pts[k], s["points"]), rel(iface[k], s["interface"]), rel([mean[k]], [s["mean"]]))
+        say(f"  sample {k}: points {e[0]:.2e} interface {e[1]:.2e} mean {e[2]:.2e}")
+        assert max(e) < TOL[1]
+    est, sweeps = t.error_estimate()
+    say("  refinement sweeps", sweeps)
+    t.close()
+
+
 def test_c2_1023_bench_batch(H, oracle_mod):
     """The bench's launch configuration (128 samples of the 1023^2 workload
     in one batch, default options).  Every sample's float64 field is certified
