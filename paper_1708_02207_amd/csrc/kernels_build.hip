@@ -158,6 +158,7 @@ __global__ void __launch_bounds__(PanelCfg<T>::RW) k_panel_rows(DevLevel L, int 
   constexpr int RW = PanelCfg<T>::RW;
   __shared__ T D[NB][NB + 1];
   __shared__ T X[RW][NB + 1];
+  __shared__ T rD[NB];  // reciprocal pivots 1 / L_jj
   const int pair = blockIdx.x;
   const int node = pair / n_samples;
   const int s = pair % n_samples;
@@ -168,11 +169,13 @@ __global__ void __launch_bounds__(PanelCfg<T>::RW) k_panel_rows(DevLevel L, int 
   T* F = frame_ptr<T>(L, node, s);
   const int tid = threadIdx.x;
   const int nrows = min(RW, U + 1 - r0);
-  const int total = nrows * kb;
+  const int total = nrows * NB;  // row e / NB, column e % NB (used where < kb)
   // every staging load of the thread is issued before any LDS store (one
   // memory latency): the diagonal block (NB x NB, valid below and on the
   // diagonal within kb) and the panel rows (nrows x kb), consecutive
-  // threads on consecutive columns; addresses are clamped into the panel
+  // threads on consecutive columns; addresses are clamped into the panel.
+  // Entries are numbered with the compile-time width NB, so no index needs
+  // a division by the run-time kb.
   constexpr int DPT = (NB * NB + RW - 1) / RW;
   T dv[DPT], xv[NB];
 #pragma unroll
@@ -184,7 +187,7 @@ __global__ void __launch_bounds__(PanelCfg<T>::RW) k_panel_rows(DevLevel L, int 
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const int e = min(tid + u * RW, total - 1);
-    xv[u] = F[(long long)(r0 + e / kb) * ld + k0 + e % kb];
+    xv[u] = F[(long long)(r0 + e / NB) * ld + k0 + min(e % NB, kb - 1)];
   }
 #pragma unroll
   for (int u = 0; u < DPT; ++u) {
@@ -195,8 +198,10 @@ __global__ void __launch_bounds__(PanelCfg<T>::RW) k_panel_rows(DevLevel L, int 
 #pragma unroll
   for (int u = 0; u < NB; ++u) {
     const int e = tid + u * RW;
-    if (e < total) X[e / kb][e % kb] = xv[u];
+    if (e < total) X[e / NB][e % NB] = xv[u];
   }
+  __syncthreads();
+  if (tid < kb) rD[tid] = T(1) / D[tid][tid];
   __syncthreads();
   if (tid < nrows) {
     T x[NB];
@@ -208,7 +213,7 @@ __global__ void __launch_bounds__(PanelCfg<T>::RW) k_panel_rows(DevLevel L, int 
         T v = x[j];
 #pragma unroll
         for (int l = 0; l < j; ++l) v -= x[l] * D[j][l];
-        x[j] = v / D[j][j];
+        x[j] = v * rD[j];
       }
     }
 #pragma unroll
@@ -216,11 +221,13 @@ __global__ void __launch_bounds__(PanelCfg<T>::RW) k_panel_rows(DevLevel L, int 
       if (k < kb) X[tid][k] = x[k];
   }
   __syncthreads();
-  for (int e = tid; e < total; e += RW) F[(long long)(r0 + e / kb) * ld + k0 + e % kb] = X[e / kb][e % kb];
+  for (int e = tid; e < total; e += RW)
+    if (e % NB < kb) F[(long long)(r0 + e / NB) * ld + k0 + e % NB] = X[e / NB][e % NB];
   if (L.panel) {  // the final columns also go to the level's panel store
     T* Pp = panel_ptr<T>(L, node, s);
     const int pld = L.panel_ld;
-    for (int e = tid; e < total; e += RW) Pp[(long long)(r0 + e / kb) * pld + k0 + e % kb] = X[e / kb][e % kb];
+    for (int e = tid; e < total; e += RW)
+      if (e % NB < kb) Pp[(long long)(r0 + e / NB) * pld + k0 + e % NB] = X[e / NB][e % NB];
   }
 }
 
@@ -631,14 +638,15 @@ __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int
 //  4. S_omega = S~ - P P^T and g_omega = g~ - P z (eq. SchurC1) for the lower
 //     triangle of rows / columns gamma..U in 32 x 32 matrix-core tiles, with
 //     S~ gathered from the sons in the tile epilogue.
-// Dynamic LDS: 2 nr ints (maps) + nr (GP + 1) floats (panel), with
+// Dynamic LDS: 2 nr ints (maps) + nr (GP + 1) floats (panel) + GP floats
+// (reciprocal pivots), with
 // nr = gamma + 32 ceil((U + 1 - gamma) / 32) rows (tile overhang is zero).
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int merge_rows(int g, int n) { return g + ((n - g + 31) / 32) * 32; }
 
 size_t merge_small_lds(int max_U, int g, int GP) {
   const int nr = merge_rows(g, max_U + 1);
-  return size_t(2) * nr * 4 + size_t(nr) * (GP + 1) * 4;
+  return size_t(2) * nr * 4 + size_t(nr) * (GP + 1) * 4 + size_t(GP) * 4;
 }
 
 template <int GP, int NT>
@@ -734,7 +742,10 @@ __global__ void __launch_bounds__(NT) k_merge_small(DevLevel F, DevLevel S, int 
   }
   __syncthreads();
   if (tid == 0 && bad_pivot && info) atomicCAS(info + s, 0, F.node_base + node + 1);
-  // 2b. panel rows below the block: x L^T = a
+  // 2b. panel rows below the block: x L^T = a, pivots applied as reciprocals
+  float* rP = P + nr * KP;  // [GP]
+  if (tid < g) rP[tid] = 1.f / P[tid * KP + tid];
+  __syncthreads();
   for (int r = g + tid; r < n; r += NT) {
     float x[GP];
 #pragma unroll
@@ -745,7 +756,7 @@ __global__ void __launch_bounds__(NT) k_merge_small(DevLevel F, DevLevel S, int 
         float v = x[j];
 #pragma unroll
         for (int l = 0; l < j; ++l) v -= x[l] * P[j * KP + l];
-        x[j] = v / P[j * KP + j];
+        x[j] = v * rP[j];
       }
     }
 #pragma unroll
@@ -757,7 +768,10 @@ __global__ void __launch_bounds__(NT) k_merge_small(DevLevel F, DevLevel S, int 
   if (F.panel) {
     float* Po = reinterpret_cast<float*>(F.panel) + (long long)s * F.panel_stride + nd.panel_off;
     const int pld = F.panel_ld;
-    for (int e = tid; e < n * g; e += NT) Po[(e / g) * pld + e % g] = P[(e / g) * KP + e % g];
+    for (int e = tid; e < n * GP; e += NT) {
+      const int r = e / GP, c = e % GP;
+      if (c < g) Po[(long long)r * pld + c] = P[r * KP + c];
+    }
   } else {
     for (int e = tid; e < n * GP; e += NT) {
       const int r = e / GP, c = e % GP;
