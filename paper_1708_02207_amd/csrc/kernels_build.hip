@@ -221,14 +221,12 @@ __global__ void __launch_bounds__(PanelCfg<T>::RW) k_panel_rows(DevLevel L, int 
       if (k < kb) X[tid][k] = x[k];
   }
   __syncthreads();
+  // the finished columns go to the level's panel store, which the Schur
+  // updates read them from (else back to the frame)
+  T* Pp = L.panel ? panel_ptr<T>(L, node, s) : F;
+  const int pld = L.panel ? L.panel_ld : ld;
   for (int e = tid; e < total; e += RW)
-    if (e % NB < kb) F[(long long)(r0 + e / NB) * ld + k0 + e % NB] = X[e / NB][e % NB];
-  if (L.panel) {  // the final columns also go to the level's panel store
-    T* Pp = panel_ptr<T>(L, node, s);
-    const int pld = L.panel_ld;
-    for (int e = tid; e < total; e += RW)
-      if (e % NB < kb) Pp[(long long)(r0 + e / NB) * pld + k0 + e % NB] = X[e / NB][e % NB];
-  }
+    if (e % NB < kb) Pp[(long long)(r0 + e / NB) * pld + k0 + e % NB] = X[e / NB][e % NB];
 }
 
 // ---------------------------------------------------------------------------
@@ -287,6 +285,19 @@ __device__ __forceinline__ void syrk_load_chunk(T (*As)[SyrkCfg<T>::KC + 1], T (
   }
   if (WZ && tid < KC) As[64][tid] = kbeg + tid < k1 ? vz : T(0);
 }
+// Rows of the operand columns [k0, k1) of a node's update: the level's panel
+// store, where the panel kernels leave the finished columns [L ; P ; z]
+// (the frame keeps only the columns still to be updated), else the frame.
+template <typename T>
+__device__ __forceinline__ const T* syrk_operands(const DevLevel& L, int node, int s, const T* F, int ld, int& pl) {
+  if (L.panel) {
+    pl = L.panel_ld;
+    return panel_ptr<T>(L, node, s);
+  }
+  pl = ld;
+  return F;
+}
+
 // Output element (i, j) of the update belongs to this call's region.
 __device__ __forceinline__ bool syrk_in(int U, int i, int j, const SyrkArgs& a, int c1e) {
   return i <= U && i >= a.r0 && j >= a.c0 && j < c1e && j <= i;
@@ -325,6 +336,8 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f32(DevLevel L, SyrkArgs a, i
   if (i0 > Ue || j0 >= c1e || i0 + 63 < j0) return;
   float* F = frame_ptr<float>(L, node, s);
   const int ld = nd.ld;
+  int pl;
+  const float* Pb = syrk_operands<float>(L, node, s, F, ld, pl);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1;
   const bool diag = i0 == j0;
@@ -335,7 +348,7 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f32(DevLevel L, SyrkArgs a, i
   float racc = 0.f;
   for (int kb = a.k0; kb < a.k1; kb += KC) {
     __syncthreads();
-    syrk_load_chunk<float, true>(As, Bs, F, ld, U, i0, j0, kb, a.k1);
+    syrk_load_chunk<float, true>(As, Bs, Pb, pl, U, i0, j0, kb, a.k1);
     __syncthreads();
     if (rhs_wave) {
 #pragma unroll
@@ -385,6 +398,8 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
   if (i0 > Ue || j0 >= c1e || i0 + 63 < j0) return;
   double* F = frame_ptr<double>(L, node, s);
   const int ld = nd.ld;
+  int pl;
+  const double* Pb = syrk_operands<double>(L, node, s, F, ld, pl);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w >> 1, wc = w & 1;
   const bool rhs_wave = i0 == j0 && wr == 0 && wc == 1;  // wave-uniform
@@ -398,7 +413,7 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
   double racc = 0.0;
   for (int kb = a.k0; kb < a.k1; kb += KC) {
     __syncthreads();
-    syrk_load_chunk<double, true>(As, Bs, F, ld, U, i0, j0, kb, a.k1);
+    syrk_load_chunk<double, true>(As, Bs, Pb, pl, U, i0, j0, kb, a.k1);
     __syncthreads();
     if (rhs_wave) {
 #pragma unroll
@@ -459,17 +474,18 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
 // so that its MFMAs overlap the epilogue's first reads.  V4: 16-byte loads
 // (ld % 4 == 0 and k0 % 4 == 0, frames with 64 or more rows).
 template <bool V4>
-__device__ __forceinline__ void syrk128_tile(float (*As)[128][33], float (*Bs)[128][33], float* F, int ld, int U,
-                                             int Ue, int i0, int j0, const SyrkArgs& a, int c1e) {
+__device__ __forceinline__ void syrk128_tile(float (*As)[128][33], float (*Bs)[128][33], float* F, int ld,
+                                             const float* Pb, int pl, int U, int Ue, int i0, int j0,
+                                             const SyrkArgs& a, int c1e) {
   constexpr int KC = 32;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;
   // loader mapping: thread -> (row lr, 16 consecutive k) for A and B.  Rows
   // past U are clamped to U: they only feed outputs that are never stored.
   const int lr = tid >> 1, lk = (tid & 1) * 16;
-  const float* rowA = F + (long long)min(i0 + lr, U) * ld;
-  const float* rowB = F + (long long)min(j0 + lr, U) * ld;
-  const float* rowZ = F + (long long)U * ld;
+  const float* rowA = Pb + (long long)min(i0 + lr, U) * pl;
+  const float* rowB = Pb + (long long)min(j0 + lr, U) * pl;
+  const float* rowZ = Pb + (long long)U * pl;
   // in a diagonal tile the upper-right wave block lies above the diagonal;
   // that wave forms the load row instead (see k_syrk_mfma_f32), with the
   // chunk of z staged as row 128 of As by the first 8 threads
@@ -480,14 +496,14 @@ __device__ __forceinline__ void syrk128_tile(float (*As)[128][33], float (*Bs)[1
     for (int q = 0; q < 4; ++q) {
       const int k = kb + lk + 4 * q;
       if constexpr (V4) {
-        const int kc = min(k, ld - 4);  // ld % 4 == 0: stays 16-byte aligned
+        const int kc = min(k, pl - 4);  // pl % 4 == 0: stays 16-byte aligned
         pa[q] = *reinterpret_cast<const float4*>(rowA + kc);
         pb[q] = *reinterpret_cast<const float4*>(rowB + kc);
       } else {
         float ta[4], tb[4];
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
-          const int kc = min(k + x, ld - 1);
+          const int kc = min(k + x, pl - 1);
           ta[x] = rowA[kc];
           tb[x] = rowB[kc];
         }
@@ -617,10 +633,12 @@ __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int
   if (i0 > Ue || j0 >= c1e || i0 + TM - 1 < j0) return;
   float* F = frame_ptr<float>(L, node, s);
   const int ld = nd.ld;
-  if ((ld % 4) == 0 && (a.k0 % 4) == 0)  // uniform per workgroup
-    syrk128_tile<true>(As, Bs, F, ld, U, Ue, i0, j0, a, c1e);
+  int pl;
+  const float* Pb = syrk_operands<float>(L, node, s, F, ld, pl);
+  if ((pl % 4) == 0 && (a.k0 % 4) == 0)  // uniform per workgroup
+    syrk128_tile<true>(As, Bs, F, ld, Pb, pl, U, Ue, i0, j0, a, c1e);
   else
-    syrk128_tile<false>(As, Bs, F, ld, U, Ue, i0, j0, a, c1e);
+    syrk128_tile<false>(As, Bs, F, ld, Pb, pl, U, Ue, i0, j0, a, c1e);
 }
 
 
@@ -1124,6 +1142,8 @@ __global__ void __launch_bounds__(256) k_syrk_simple(DevLevel L, SyrkArgs a, int
   if (i0 > U || j0 >= c1e || i0 + 63 < j0) return;
   T* F = frame_ptr<T>(L, node, s);
   const int ld = nd.ld;
+  int pl;
+  const T* Pb = syrk_operands<T>(L, node, s, F, ld, pl);
   const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
   T acc[4][4];
 #pragma unroll
@@ -1132,7 +1152,7 @@ __global__ void __launch_bounds__(256) k_syrk_simple(DevLevel L, SyrkArgs a, int
     for (int y = 0; y < 4; ++y) acc[x][y] = T(0);
   for (int kb = a.k0; kb < a.k1; kb += KC) {
     __syncthreads();
-    syrk_load_chunk<T>(As, Bs, F, ld, U, i0, j0, kb, a.k1);
+    syrk_load_chunk<T>(As, Bs, Pb, pl, U, i0, j0, kb, a.k1);
     __syncthreads();
     for (int kk = 0; kk < KC; ++kk)
 #pragma unroll
