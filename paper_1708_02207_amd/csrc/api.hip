@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <limits>
 #include <map>
 #include <mutex>
@@ -37,8 +38,6 @@ enum Kind {
 
 int64_t align256(int64_t v) { return (v + 255) / 256 * 256; }
 
-// Column block of the two-level blocked interface factorization.
-constexpr int kBlockNB = 128;
 
 bool refinement_possible(const hdd_opts& o) { return o.precision == HDD_FP32_REFINE || o.max_refine > 0; }
 
@@ -1007,19 +1006,22 @@ int build_device(hdd_tree* h) {
       return timed(
           h, kind, fl, [&] { return hdd::launch_syrk(L, k0, k1, r0, r0, c1, n_samples, mfma, tile, h->st); }, by);
     };
-    // Two-level blocked right-looking partial Cholesky of the first g
-    // columns: panels of kPanelNB columns inside blocks of kBlockNB columns;
-    // a panel's trailing update stays inside its block, and the columns
-    // right of a block are updated once per block (K = kBlockNB).
-    for (int b0 = 0; b0 < g; b0 += kBlockNB) {
-      const int b1 = std::min(g, b0 + kBlockNB);
-      for (int k0 = b0; k0 < b1; k0 += hdd::kPanelNB) {
-        const int kb = std::min(hdd::kPanelNB, b1 - k0);
-        HDD_TRY(timed(h, K_FACTOR, 0.0, [&] { return hdd::launch_panel(L, k0, kb, n_samples, h->info, h->st); }));
-        if (k0 + kb < b1) HDD_TRY(syrk(k0, k0 + kb, k0 + kb, b1));
-      }
-      if (b1 < g) HDD_TRY(syrk(b0, b1, b1, g));
-    }
+    // Recursive blocked partial Cholesky of the first g columns: the
+    // columns [c0, c1) are halved (at a multiple of kPanelNB), the left half
+    // is factored, the right half takes its update from the left half in one
+    // rank-K launch, then the right half is factored; kPanelNB-column panels
+    // at the bottom.  Every column is rewritten once per halving, with the
+    // widest K available for each update.
+    std::function<int(int, int)> factor_range = [&](int c0, int c1) -> int {
+      if (c1 - c0 <= hdd::kPanelNB)
+        return timed(h, K_FACTOR, 0.0, [&] { return hdd::launch_panel(L, c0, c1 - c0, n_samples, h->info, h->st); });
+      const int half = ((c1 - c0) / 2 + hdd::kPanelNB - 1) / hdd::kPanelNB * hdd::kPanelNB;
+      const int mid = c0 + half;
+      HDD_TRY(factor_range(c0, mid));
+      HDD_TRY(syrk(c0, mid, mid, c1));
+      return factor_range(mid, c1);
+    };
+    HDD_TRY(factor_range(0, g));
     if (L.max_U > g) HDD_TRY(syrk(0, g, g, -1));  // Schur update of Gamma (and the boundary load row)
     return HDD_OK;
   };
