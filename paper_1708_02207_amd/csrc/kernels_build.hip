@@ -1213,10 +1213,12 @@ hipError_t launch_panel(const DevLevel& L, int k0, int kb, int n_samples, int* i
 }
 
 // Large frames (16-byte aligned rows) with enough work per tile use the
-// 128 x 128 matrix-core tile.  Narrow updates (K < 96) of frames with 384 or
-// more rows go to the 64 x 64 tile: with two K chunks per tile the 128 x 128
-// tile's read-modify-write dominates (measured at 1023^2, 448-row frames,
-// K = 63: 1.5 ms instead of 2.3 ms; no gain at 320 rows).
+// 128 x 128 matrix-core tile: K >= 96 and at least 96 output columns (a
+// 127-column half of a 255-column interface fills one tile column).
+// Narrow updates (K < 96) go to the 64 x 64 tile: with two K chunks per
+// tile the 128 x 128 tile's read-modify-write dominates (measured at
+// 1023^2, 448-row frames, K = 63: 1.5 ms instead of 2.3 ms; no gain at 320
+// rows).
 bool syrk_uses_big_tile(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, bool mfma, int tile) {
   if (!mfma || L.is_double || k1 <= k0) return false;  // the 128 x 128 tile is float32 matrix-core only
   if (tile == 64) return false;
@@ -1224,7 +1226,7 @@ bool syrk_uses_big_tile(const DevLevel& L, int k0, int k1, int r0, int c0, int c
   const int rows = L.max_U + 1 - r0;
   const int cols = (c1 < 0 ? L.max_U + 1 : c1) - c0;
   if (k1 - k0 < 96) return false;
-  return rows >= 192 && cols >= 128 && (k0 % 4) == 0 && L.max_U + 1 >= 64;
+  return rows >= 192 && cols >= 96 && (k0 % 4) == 0 && L.max_U + 1 >= 64;
 }
 
 hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, int n_samples, bool mfma,
