@@ -382,6 +382,67 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f32(DevLevel L, SyrkArgs a, i
   }
 }
 
+// Tall tile for updates of at most 32 columns (the panel-to-panel updates
+// at the bottom of the recursive interface factorization): 128 rows x 32
+// columns per workgroup, wave w on rows i0 + 32 w .. + 31, one 32 x 32 x 2
+// MFMA accumulator each, K chunks of 32 through LDS.  The load row U is an
+// ordinary row here (its A operand row is z).  A 64 x 64 tile over 32
+// columns would read and multiply twice the columns it stores.
+__global__ void __launch_bounds__(256) k_syrk_tall_f32(DevLevel L, SyrkArgs a, int n_samples) {
+  constexpr int KC = 32;
+  __shared__ float As[128][KC + 1];
+  __shared__ float Bs[32][KC + 1];
+  const int pair = blockIdx.x;
+  const int node = pair / n_samples, s = pair % n_samples;
+  const DevNode nd = L.nodes[node];
+  const int U = nd.U;
+  const int c1e = a.c1 < 0 ? U + 1 : a.c1;
+  const int ti = blockIdx.y / a.tiles_c, tj = blockIdx.y % a.tiles_c;
+  const int i0 = a.r0 + ti * 128, j0 = a.c0 + tj * 32;
+  if (i0 > U || j0 >= c1e || i0 + 127 < j0) return;
+  float* F = frame_ptr<float>(L, node, s);
+  const int ld = nd.ld;
+  int pl;
+  const float* Pb = syrk_operands<float>(L, node, s, F, ld, pl);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // loaders: A row tid / 2 (16 consecutive k), B row tid / 8 (4 consecutive
+  // k); rows past U clamped to U, columns past k1 read clamped and zeroed
+  const int ar = tid >> 1, ak = (tid & 1) * 16;
+  const int br = tid >> 3, bk = (tid & 7) * 4;
+  const float* rowA = Pb + (long long)min(i0 + ar, U) * pl;
+  const float* rowB = Pb + (long long)min(j0 + br, U) * pl;
+  floatx16 acc;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  for (int kb = a.k0; kb < a.k1; kb += KC) {
+    float va[16], vb[4];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) va[q] = rowA[min(kb + ak + q, a.k1 - 1)];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) vb[q] = rowB[min(kb + bk + q, a.k1 - 1)];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) As[ar][ak + q] = kb + ak + q < a.k1 ? va[q] : 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Bs[br][bk + q] = kb + bk + q < a.k1 ? vb[q] : 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 2)
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[w * 32 + (lane & 31)][kk + (lane >> 5)],
+                                                 Bs[lane & 31][kk + (lane >> 5)], acc, 0, 0, 0);
+  }
+  const int j = j0 + (lane & 31);
+  const int ib = i0 + w * 32 + (lane >> 5) * 4;
+  float old[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) old[v] = syrk_old(F, ld, U, ib + (v >> 2) * 8 + (v & 3), j);
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int i = ib + (v >> 2) * 8 + (v & 3);
+    if (syrk_in(U, i, j, a, c1e)) F[(long long)i * ld + j] = old[v] - acc[v];
+  }
+}
+
 // float64 version of the same tile (16 x 16 x 4 MFMA, 2 x 2 per wave).
 __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, int n_samples) {
   constexpr int KC = SyrkCfg<double>::KC;
@@ -1237,6 +1298,15 @@ hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1
   const int cols = (c1 < 0 ? L.max_U + 1 : c1) - c0;
   if (rows <= 0 || cols <= 0) return hipSuccess;
   const bool big = syrk_uses_big_tile(L, k0, k1, r0, c0, c1, mfma, tile);
+  if (!big && mfma && !L.is_double && c1 >= 0 && cols <= 32 && tile != 64) {
+    // tall 128 x 32 tiles, rows r0 .. U (the load row included)
+    a.sep = 0;
+    a.tiles_r = ceil_div(rows, 128);
+    a.tiles_c = 1;
+    dim3 grid(L.n_nodes * n_samples, a.tiles_r);
+    hipLaunchKernelGGL(k_syrk_tall_f32, grid, dim3(256), 0, st, L, a, n_samples);
+    return hipGetLastError();
+  }
   const int TM = big ? 128 : 64;
   // the matrix-core tiles cover rows r0 .. U-1; the load row U is formed by
   // the idle wave of the diagonal tiles
