@@ -293,7 +293,12 @@ class HDD:
         entries in the order of hdd_plan_node's ids; (0, 0) is the root midline."""
         ln = ctypes.c_int32(0)
         if out is None:
-            g = hdd_plan_node(self.opts, depth, index)["gam"]
+            # |gamma| is uniform on a level; hdd_plan_level plans the tree on
+            # the host, so it is asked once per depth and handle
+            cache = self.__dict__.setdefault("_gam", {})
+            if depth not in cache:
+                cache[depth] = hdd_plan_level(self.opts, depth)["gam"]
+            g = cache[depth]
             res = np.zeros((self.n_samples, g))
             _check(_lib.hdd_query_interface(self.h, int(depth), int(index), _np_ptr(res), ctypes.byref(ln),
                                             HDD_MEM_HOST), "hdd_query_interface")
