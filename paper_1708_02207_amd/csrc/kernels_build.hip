@@ -546,12 +546,7 @@ __device__ __forceinline__ void syrk128_tile(float (*As)[128][33], float (*Bs)[1
   const int lr = tid >> 1, lk = (tid & 1) * 16;
   const float* rowA = Pb + (long long)min(i0 + lr, U) * pl;
   const float* rowB = Pb + (long long)min(j0 + lr, U) * pl;
-  const float* rowZ = Pb + (long long)U * pl;
-  // in a diagonal tile the upper-right wave block lies above the diagonal;
-  // that wave forms the load row instead (see k_syrk_mfma_f32), with the
-  // chunk of z staged as row 128 of As by the first 8 threads
-  const bool diag = i0 == j0;
-  float4 pa[4], pb[4], pz;
+  float4 pa[4], pb[4];
   auto load = [&](int kb) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -626,18 +621,6 @@ __device__ __forceinline__ void syrk128_tile(float (*As)[128][33], float (*Bs)[1
     for (int v = 0; v < 16; ++v) {
       const int i = ib + (v >> 2) * 8 + (v & 3);
       if (syrk_in(Ue, i, j, a, c1e)) F[(long long)i * ld + j] = o[v] - c[v];
-    }
-  };
-  // a wave whose 64 x 64 block lies strictly above the diagonal (the upper
-  // right block of a diagonal tile) stores no block: it forms the load row
-  const bool active = i0 + wr * 64 + 63 >= j0 + wc * 64;  // wave-uniform
-  float racc[2] = {0.f, 0.f};
-  auto rhs = [&](int buf) {
-#pragma unroll
-    for (int kk = 0; kk < KC; ++kk) {
-      const float zk = As[buf][128][kk];
-      racc[0] += zk * Bs[buf][lane][kk];
-      racc[1] += zk * Bs[buf][64 + lane][kk];
     }
   };
   load(a.k0);
