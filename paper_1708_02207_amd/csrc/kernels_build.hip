@@ -4,6 +4,7 @@
 // of its frame (panel factorization + triangular solve, then a symmetric
 // rank-k update on the MFMA matrix cores).
 #include <algorithm>
+#include <type_traits>
 
 #include "device.hpp"
 #include "kernels.hpp"
@@ -525,31 +526,32 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
 
 // Large-tile version for the upper levels: 128 x 128 output tile per
 // workgroup (4 waves, 64 x 64 each as 2 x 2 blocks of 32 x 32 x 2 MFMA),
-// K chunks of 32 staged through two LDS buffers, one barrier per chunk.  The
+// K chunks of KC staged through two LDS buffers, one barrier per chunk.  The
 // next chunk's global loads are in flight while the current chunk is
 // multiplied: the loop body has no branch, every chunk is read at addresses
 // clamped into the node's frame (rows past U to U, columns to the last
 // column of the row), and entries outside [k0, k1) are zeroed when the chunk
 // is stored to LDS, after the MFMAs, so no load result is waited for before
 // the MFMAs of the chunk it is prefetched behind.  The last chunk is peeled
-// so that its MFMAs overlap the epilogue's first reads.  V4: 16-byte loads
-// (ld % 4 == 0 and k0 % 4 == 0, frames with 64 or more rows).
-template <bool V4>
-__device__ __forceinline__ void syrk128_tile(float (*As)[128][33], float (*Bs)[128][33], float* F, int ld,
+// so that its MFMAs overlap the epilogue's first reads.  In diagonal tiles
+// the blocks above the diagonal issue no MFMAs.  V4: 16-byte loads (ld % 4
+// == 0 and k0 % 4 == 0, frames with 64 or more rows).
+template <bool V4, int KC>
+__device__ __forceinline__ void syrk128_tile(float (*As)[128][KC + 1], float (*Bs)[128][KC + 1], float* F, int ld,
                                              const float* Pb, int pl, int U, int Ue, int i0, int j0,
                                              const SyrkArgs& a, int c1e) {
-  constexpr int KC = 32;
+  constexpr int NQ = KC / 8;  // float4 groups per thread and operand
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wr = w >> 1, wc = w & 1;
-  // loader mapping: thread -> (row lr, 16 consecutive k) for A and B.  Rows
+  // loader mapping: thread -> (row lr, KC / 2 consecutive k) for A and B.  Rows
   // past U are clamped to U: they only feed outputs that are never stored.
-  const int lr = tid >> 1, lk = (tid & 1) * 16;
+  const int lr = tid >> 1, lk = (tid & 1) * (KC / 2);
   const float* rowA = Pb + (long long)min(i0 + lr, U) * pl;
   const float* rowB = Pb + (long long)min(j0 + lr, U) * pl;
-  float4 pa[4], pb[4];
+  float4 pa[NQ], pb[NQ];
   auto load = [&](int kb) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int k = kb + lk + 4 * q;
       if constexpr (V4) {
         const int kc = min(k, pl - 4);  // pl % 4 == 0: stays 16-byte aligned
@@ -570,7 +572,7 @@ __device__ __forceinline__ void syrk128_tile(float (*As)[128][33], float (*Bs)[1
   };
   auto store = [&](int buf, int kb) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int k = kb + lk + 4 * q;
       // select, not multiply: entries past k1 may hold any bit pattern
       const bool m0 = k + 0 < a.k1, m1 = k + 1 < a.k1, m2 = k + 2 < a.k1, m3 = k + 3 < a.k1;
@@ -591,18 +593,27 @@ __device__ __forceinline__ void syrk128_tile(float (*As)[128][33], float (*Bs)[1
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[x][y][v] = 0.f;
-  auto mma = [&](int buf) {
+  // MODE 2: all four 32 x 32 blocks of the wave; 1: not the block (x, y) =
+  // (0, 1), which lies above the diagonal in the diagonal waves of a
+  // diagonal tile; 0: none (the wave's 64 x 64 block lies above the
+  // diagonal).  Each mode is its own branch-free copy of the K loop.
+  auto mma = [&](auto mode, int buf) {
+    constexpr int MODE = decltype(mode)::value;
+    if constexpr (MODE > 0) {
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 2) {
-      float av[2], bv[2];
+      for (int kk = 0; kk < KC; kk += 2) {
+        float av[2], bv[2];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) av[x] = As[buf][wr * 64 + x * 32 + (lane & 31)][kk + (lane >> 5)];
+        for (int x = 0; x < 2; ++x) av[x] = As[buf][wr * 64 + x * 32 + (lane & 31)][kk + (lane >> 5)];
 #pragma unroll
-      for (int y = 0; y < 2; ++y) bv[y] = Bs[buf][wc * 64 + y * 32 + (lane & 31)][kk + (lane >> 5)];
+        for (int y = 0; y < 2; ++y) bv[y] = Bs[buf][wc * 64 + y * 32 + (lane & 31)][kk + (lane >> 5)];
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[x], bv[y], acc[x][y], 0, 0, 0);
+          for (int y = 0; y < 2; ++y)
+            if (MODE == 2 || x != 0 || y != 1)
+              acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[x], bv[y], acc[x][y], 0, 0, 0);
+      }
     }
   };
   // epilogue reads of accumulator tile q = 2 x + y (issued ahead of use)
@@ -623,40 +634,56 @@ __device__ __forceinline__ void syrk128_tile(float (*As)[128][33], float (*Bs)[1
       if (syrk_in(Ue, i, j, a, c1e)) F[(long long)i * ld + j] = o[v] - c[v];
     }
   };
-  load(a.k0);
-  store(0, a.k0);
-  __syncthreads();
-  int buf = 0, kb = a.k0;
-  for (; kb + KC < a.k1; kb += KC) {
-    load(kb + KC);
-    // keep the prefetch ahead of the MFMAs (the scheduler would otherwise
-    // sink the loads next to their LDS stores)
-    __builtin_amdgcn_sched_barrier(0);
-    mma(buf);
-    __builtin_amdgcn_sched_barrier(0);
-    store(buf ^ 1, kb + KC);
+  auto run = [&](auto mode) {
+    constexpr int MODE = decltype(mode)::value;
+    load(a.k0);
+    store(0, a.k0);
     __syncthreads();
-    buf ^= 1;
-  }
-  float o0[16], o1[16];
-  load_old(0, o0);  // the first epilogue reads overlap the last chunk's MFMAs
-  __builtin_amdgcn_sched_barrier(0);
-  mma(buf);
-  // epilogue, software pipelined: reads of the next accumulator tile are in
-  // flight while the current one is written
-  load_old(1, o1);
-  store_new(0, o0, acc[0][0]);
-  load_old(2, o0);
-  store_new(1, o1, acc[0][1]);
-  load_old(3, o1);
-  store_new(2, o0, acc[1][0]);
-  store_new(3, o1, acc[1][1]);
+    int buf = 0, kb = a.k0;
+    for (; kb + KC < a.k1; kb += KC) {
+      load(kb + KC);
+      // keep the prefetch ahead of the MFMAs (the scheduler would otherwise
+      // sink the loads next to their LDS stores)
+      __builtin_amdgcn_sched_barrier(0);
+      mma(mode, buf);
+      __builtin_amdgcn_sched_barrier(0);
+      store(buf ^ 1, kb + KC);
+      __syncthreads();
+      buf ^= 1;
+    }
+    if constexpr (MODE == 0) return;  // nothing of this wave's block is stored
+    float o0[16];
+    load_old(0, o0);  // the first epilogue reads overlap the last chunk's MFMAs
+    __builtin_amdgcn_sched_barrier(0);
+    mma(mode, buf);
+    store_new(0, o0, acc[0][0]);
+#pragma unroll
+    for (int q = 1; q < 4; ++q) {
+      if (MODE == 1 && q == 1) continue;
+      load_old(q, o0);
+      store_new(q, o0, acc[q >> 1][q & 1]);
+    }
+  };
+  // wave-uniform: which of the wave's 32 x 32 blocks hold stored elements
+  // (block (x, y) lies above the diagonal when its first column exceeds its
+  // last row)
+  const int ri = i0 + wr * 64, cj = j0 + wc * 64;
+  if (cj > ri + 63)
+    run(std::integral_constant<int, 0>{});
+  else if (cj >= ri && cj <= ri + 31)  // only (0, 1) above the diagonal
+    run(std::integral_constant<int, 1>{});
+  else
+    run(std::integral_constant<int, 2>{});
 }
 
-__global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int n_samples) {
-  constexpr int TM = 128;
-  __shared__ float As[2][TM][33];
-  __shared__ float Bs[2][TM][33];
+// Three workgroups per CU: K chunks of 16 (34 KiB of LDS) and at most 168
+// VGPRs per lane, so that one workgroup's epilogue and first loads overlap
+// the others' MFMAs (two per CU with 32-wide chunks: 2.3 ms per step more).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_syrk128_f32(DevLevel L, SyrkArgs a, int n_samples) {
+  constexpr int TM = 128, KC = 16;
+  __shared__ float As[2][TM][KC + 1];
+  __shared__ float Bs[2][TM][KC + 1];
   // XCD-aware order: workgroup b runs on XCD b % 8; all tiles of one (node,
   // sample) frame go to the same XCD in consecutive order, so its panel
   // columns stay in that XCD's L2 while its tiles are computed.
@@ -680,9 +707,9 @@ __global__ void __launch_bounds__(256) k_syrk128_f32(DevLevel L, SyrkArgs a, int
   int pl;
   const float* Pb = syrk_operands<float>(L, node, s, F, ld, pl);
   if ((pl % 4) == 0 && (a.k0 % 4) == 0)  // uniform per workgroup
-    syrk128_tile<true>(As, Bs, F, ld, Pb, pl, U, Ue, i0, j0, a, c1e);
+    syrk128_tile<true, KC>(As, Bs, F, ld, Pb, pl, U, Ue, i0, j0, a, c1e);
   else
-    syrk128_tile<false>(As, Bs, F, ld, Pb, pl, U, Ue, i0, j0, a, c1e);
+    syrk128_tile<false, KC>(As, Bs, F, ld, Pb, pl, U, Ue, i0, j0, a, c1e);
 }
 
 
