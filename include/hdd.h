@@ -89,7 +89,7 @@ typedef struct hdd_opts {
   int32_t precision;       /* HDD_FP64 or HDD_FP32_REFINE */
   int32_t fp64_top_levels; /* HDD_FP32_REFINE: levels (from the root) kept in float64; default 2
                               (0 changed neither the sweep count nor the refined error from
-                              255^2 to 2047^2, and is about 3% faster at 1023^2) */
+                              255^2 to 2047^2, and is about 5% faster at 1023^2) */
   int32_t max_refine;      /* refinement sweeps allowed (HDD_FP32_REFINE default 6; HDD_FP64 default 0) */
   int32_t flags;           /* HDD_FLAG_* */
   double refine_tol;       /* stop once the predicted relative error of the field,
