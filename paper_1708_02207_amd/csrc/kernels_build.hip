@@ -524,6 +524,12 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
       }
 }
 
+// Tiles (ti, tj) with tj <= ti and tj < tc of a tr x tc tile grid (the
+// tiles on or below the diagonal when r0 == c0), numbered row by row.
+__host__ __device__ inline int lower_tile_count(int tr, int tc) {
+  return tc >= tr ? tr * (tr + 1) / 2 : tc * (tc + 1) / 2 + (tr - tc) * tc;
+}
+
 // Large-tile version for the upper levels: 128 x 128 output tile per
 // workgroup (4 waves, 64 x 64 each as 2 x 2 blocks of 32 x 32 x 2 MFMA),
 // K chunks of KC staged through two LDS buffers, one barrier per chunk.  The
@@ -534,8 +540,10 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
 // is stored to LDS, after the MFMAs, so no load result is waited for before
 // the MFMAs of the chunk it is prefetched behind.  The last chunk is peeled
 // so that its MFMAs overlap the epilogue's first reads.  In diagonal tiles
-// the blocks above the diagonal issue no MFMAs.  V4: 16-byte loads (ld % 4
-// == 0 and k0 % 4 == 0, frames with 64 or more rows).
+// the blocks above the diagonal issue no MFMAs, and the wave whose block
+// lies wholly above it forms the load row U instead (the tiles stop at row
+// U - 1, so a frame of 128 m + 1 rows needs no further row of tiles).  V4:
+// 16-byte loads (ld % 4 == 0 and k0 % 4 == 0, frames with 64 or more rows).
 template <bool V4, int KC>
 __device__ __forceinline__ void syrk128_tile(float (*As)[128][KC + 1], float (*Bs)[128][KC + 1], float* F, int ld,
                                              const float* Pb, int pl, int U, int Ue, int i0, int j0,
@@ -634,24 +642,57 @@ __device__ __forceinline__ void syrk128_tile(float (*As)[128][KC + 1], float (*B
       if (syrk_in(Ue, i, j, a, c1e)) F[(long long)i * ld + j] = o[v] - c[v];
     }
   };
+  // The load row U (g_omega = g~ - P z) is not part of the tiles (rows r0 ..
+  // U - 1): the wave of a diagonal tile whose 64 x 64 block lies above the
+  // diagonal forms it for the tile's 128 columns from the B rows in LDS and
+  // z, row U of the operand, read from global memory one chunk ahead.
+  const float* zrow = Pb + (long long)U * pl;
+  // lane q < KC holds z[kb + q] (one load per chunk), read back by lane reads
+  auto zload = [&](int kb) {
+    const int k = kb + lane;
+    const float v = zrow[min(k, pl - 1)];
+    return (lane < KC && k < a.k1) ? v : 0.f;  // select: entries past k1 may hold any bit pattern
+  };
+  float rz0 = 0.f, rz1 = 0.f;
+  auto rowdot = [&](int buf, float zv) {
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const float z = lane_value(zv, kk);
+      rz0 += z * Bs[buf][lane][kk];
+      rz1 += z * Bs[buf][64 + lane][kk];
+    }
+  };
   auto run = [&](auto mode) {
     constexpr int MODE = decltype(mode)::value;
+    float zc = 0.f, zn = 0.f;
+    if constexpr (MODE == 0) zc = zload(a.k0);
     load(a.k0);
     store(0, a.k0);
     __syncthreads();
     int buf = 0, kb = a.k0;
     for (; kb + KC < a.k1; kb += KC) {
       load(kb + KC);
+      if constexpr (MODE == 0) zn = zload(kb + KC);
       // keep the prefetch ahead of the MFMAs (the scheduler would otherwise
       // sink the loads next to their LDS stores)
       __builtin_amdgcn_sched_barrier(0);
-      mma(mode, buf);
+      if constexpr (MODE == 0)
+        rowdot(buf, zc);
+      else
+        mma(mode, buf);
       __builtin_amdgcn_sched_barrier(0);
       store(buf ^ 1, kb + KC);
       __syncthreads();
       buf ^= 1;
+      if constexpr (MODE == 0) zc = zn;
     }
-    if constexpr (MODE == 0) return;  // nothing of this wave's block is stored
+    if constexpr (MODE == 0) {
+      rowdot(buf, zc);
+      const int ja = j0 + lane, jb = j0 + 64 + lane;
+      if (ja >= a.c0 && ja < c1e && ja <= U) F[(long long)U * ld + ja] -= rz0;
+      if (jb >= a.c0 && jb < c1e && jb <= U) F[(long long)U * ld + jb] -= rz1;
+      return;
+    }
     float o0[16];
     load_old(0, o0);  // the first epilogue reads overlap the last chunk's MFMAs
     __builtin_amdgcn_sched_barrier(0);
@@ -686,22 +727,28 @@ k_syrk128_f32(DevLevel L, SyrkArgs a, int n_samples) {
   __shared__ float Bs[2][TM][KC + 1];
   // XCD-aware order: workgroup b runs on XCD b % 8; all tiles of one (node,
   // sample) frame go to the same XCD in consecutive order, so its panel
-  // columns stay in that XCD's L2 while its tiles are computed.
+  // columns stay in that XCD's L2 while its tiles are computed.  Only the
+  // tiles on or below the diagonal are enumerated (row by row; rows of the
+  // tile grid past the last tile column hold tiles_c tiles): empty
+  // workgroups for the tiles above it cost 2.6 ms per step of 1023^2 x 128.
   const int n_pairs = L.n_nodes * n_samples;
-  const int n_tiles = a.tiles_r * a.tiles_c;
+  const int n_tiles = lower_tile_count(a.tiles_r, a.tiles_c);
   const int b = blockIdx.x;
   const int loc = b >> 3;
   const int pair = (loc / n_tiles) * 8 + (b & 7);
   if (pair >= n_pairs) return;
-  const int tile = loc % n_tiles;
+  int ti = 0, tj = loc % n_tiles;
+  while (tj >= min(ti + 1, a.tiles_c)) {
+    tj -= min(ti + 1, a.tiles_c);
+    ++ti;
+  }
   const int node = pair / n_samples, s = pair % n_samples;
   const DevNode nd = L.nodes[node];
   const int U = nd.U;
-  const int Ue = U;
+  const int Ue = U - 1;  // tiles cover rows r0 .. U - 1; row U is formed in the diagonal tiles
   const int c1e = a.c1 < 0 ? U + 1 : a.c1;
-  const int ti = tile / a.tiles_c, tj = tile % a.tiles_c;
   const int i0 = a.r0 + ti * TM, j0 = a.c0 + tj * TM;
-  if (i0 > Ue || j0 >= c1e || i0 + TM - 1 < j0) return;
+  if (i0 > Ue || j0 >= c1e) return;
   float* F = frame_ptr<float>(L, node, s);
   const int ld = nd.ld;
   int pl;
@@ -1292,7 +1339,7 @@ hipError_t launch_panel(const DevLevel& L, int k0, int kb, int n_samples, int* i
 // rows).
 bool syrk_uses_big_tile(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, bool mfma, int tile) {
   if (!mfma || L.is_double || k1 <= k0) return false;  // the 128 x 128 tile is float32 matrix-core only
-  if (tile == 64) return false;
+  if (tile == 64 || r0 != c0) return false;  // diagonal tiles of the 128 x 128 grid form the load row
   if (tile == 128) return true;
   const int rows = L.max_U + 1 - r0;
   const int cols = (c1 < 0 ? L.max_U + 1 : c1) - c0;
@@ -1320,7 +1367,7 @@ hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1
   const int TM = big ? 128 : 64;
   // the matrix-core tiles cover rows r0 .. U-1; the load row U is formed by
   // the idle wave of the diagonal tiles
-  a.sep = (mfma && !big) ? 1 : 0;
+  a.sep = mfma ? 1 : 0;
   const int tr = ceil_div(rows - a.sep, TM);
   a.tiles_c = ceil_div(c1 < 0 ? cols - a.sep : cols, TM);
   a.tiles_r = tr;
@@ -1328,7 +1375,7 @@ hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1
     dim3 grid(L.n_nodes * n_samples, tr * a.tiles_c), block(256);
     if (big) {
       const long long pairs8 = (long long)ceil_div(L.n_nodes * n_samples, 8) * 8;
-      const long long nwg = pairs8 * tr * a.tiles_c;
+      const long long nwg = pairs8 * lower_tile_count(tr, a.tiles_c);
       if (nwg > 0x7fffffffll) return hipErrorInvalidValue;
       hipLaunchKernelGGL(k_syrk128_f32, dim3(unsigned(nwg)), block, 0, st, L, a, n_samples);
     } else if (L.is_double) {
