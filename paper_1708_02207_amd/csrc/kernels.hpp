@@ -20,7 +20,8 @@ constexpr int kPanelNB = 32;  // panel width of the interface factorization
 hipError_t launch_extend_add(const DevLevel& F, const DevLevel& S, int n_samples, hipStream_t st);
 hipError_t launch_panel(const DevLevel& L, int k0, int kb, int n_samples, int* info, hipStream_t st);
 // Rank-K update C[r0.., c0..c1) -= F[.., k0..k1) F[.., k0..k1)^T of every
-// node's frame.  tile: 0 = the built-in rule (128 x 128 tiles for float32
+// node's frame (lower triangle; r0 == c0, else hipErrorInvalidValue).  tile:
+// 0 = the built-in rule (128 x 128 tiles for float32
 // updates with K >= 96 on large frames, else 64 x 64), 64 or 128 to force a
 // tile (128 only on float32 matrix-core levels).
 hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, int n_samples, bool mfma,

@@ -11,6 +11,25 @@
 
 namespace hdd {
 
+// Tiles (ti, tj) with tj <= ti and tj < tc of a tr x tc tile grid, numbered
+// row by row: the tiles on or below the diagonal of a Schur update whose
+// rows and columns start at the same index.  Only these are launched (empty
+// workgroups for the tiles above the diagonal cost 2.6 ms per step of the
+// 128 x 128 updates at 1023^2 x 128).
+__host__ __device__ inline int lower_tile_count(int tr, int tc) {
+  return tc >= tr ? tr * (tr + 1) / 2 : tc * (tc + 1) / 2 + (tr - tc) * tc;
+}
+__device__ __forceinline__ void lower_tile(int t, int tc, int& ti, int& tj) {
+  const int tri = tc * (tc + 1) / 2;  // rows 0 .. tc - 1 hold ti + 1 tiles
+  if (t < tri) {
+    ti = tri_row(t);
+    tj = t - ti * (ti + 1) / 2;
+  } else {
+    ti = tc + (t - tri) / tc;
+    tj = (t - tri) % tc;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Extend-add (eq. Psi_sum and the block system eq. block_equation4): the
 // father's frame is the sum of both sons' [Gamma;rhs] blocks embedded in the
@@ -332,9 +351,10 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f32(DevLevel L, SyrkArgs a, i
   const int U = nd.U;
   const int Ue = U - 1;  // last row of the tiles; row U is the load row
   const int c1e = min(a.c1 < 0 ? U + 1 : a.c1, U);
-  const int ti = blockIdx.y / a.tiles_c, tj = blockIdx.y % a.tiles_c;
+  int ti, tj;
+  lower_tile(blockIdx.y, a.tiles_c, ti, tj);
   const int i0 = a.r0 + ti * 64, j0 = a.c0 + tj * 64;
-  if (i0 > Ue || j0 >= c1e || i0 + 63 < j0) return;
+  if (i0 > Ue || j0 >= c1e) return;
   float* F = frame_ptr<float>(L, node, s);
   const int ld = nd.ld;
   int pl;
@@ -455,9 +475,10 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
   const int U = nd.U;
   const int Ue = U - 1;  // last row of the tiles; row U is the load row
   const int c1e = min(a.c1 < 0 ? U + 1 : a.c1, U);
-  const int ti = blockIdx.y / a.tiles_c, tj = blockIdx.y % a.tiles_c;
+  int ti, tj;
+  lower_tile(blockIdx.y, a.tiles_c, ti, tj);
   const int i0 = a.r0 + ti * 64, j0 = a.c0 + tj * 64;
-  if (i0 > Ue || j0 >= c1e || i0 + 63 < j0) return;
+  if (i0 > Ue || j0 >= c1e) return;
   double* F = frame_ptr<double>(L, node, s);
   const int ld = nd.ld;
   int pl;
@@ -522,12 +543,6 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
         const int j = j0 + wc * 32 + y * 16 + (lane & 15);
         if (syrk_in(Ue, i, j, a, c1e)) F[(long long)i * ld + j] = old[x][y][v] - acc[x][y][v];
       }
-}
-
-// Tiles (ti, tj) with tj <= ti and tj < tc of a tr x tc tile grid (the
-// tiles on or below the diagonal when r0 == c0), numbered row by row.
-__host__ __device__ inline int lower_tile_count(int tr, int tc) {
-  return tc >= tr ? tr * (tr + 1) / 2 : tc * (tc + 1) / 2 + (tr - tc) * tc;
 }
 
 // Large-tile version for the upper levels: 128 x 128 output tile per
@@ -727,21 +742,15 @@ k_syrk128_f32(DevLevel L, SyrkArgs a, int n_samples) {
   __shared__ float Bs[2][TM][KC + 1];
   // XCD-aware order: workgroup b runs on XCD b % 8; all tiles of one (node,
   // sample) frame go to the same XCD in consecutive order, so its panel
-  // columns stay in that XCD's L2 while its tiles are computed.  Only the
-  // tiles on or below the diagonal are enumerated (row by row; rows of the
-  // tile grid past the last tile column hold tiles_c tiles): empty
-  // workgroups for the tiles above it cost 2.6 ms per step of 1023^2 x 128.
+  // columns stay in that XCD's L2 while its tiles are computed.
   const int n_pairs = L.n_nodes * n_samples;
   const int n_tiles = lower_tile_count(a.tiles_r, a.tiles_c);
   const int b = blockIdx.x;
   const int loc = b >> 3;
   const int pair = (loc / n_tiles) * 8 + (b & 7);
   if (pair >= n_pairs) return;
-  int ti = 0, tj = loc % n_tiles;
-  while (tj >= min(ti + 1, a.tiles_c)) {
-    tj -= min(ti + 1, a.tiles_c);
-    ++ti;
-  }
+  int ti, tj;
+  lower_tile(loc % n_tiles, a.tiles_c, ti, tj);
   const int node = pair / n_samples, s = pair % n_samples;
   const DevNode nd = L.nodes[node];
   const int U = nd.U;
@@ -1255,9 +1264,10 @@ __global__ void __launch_bounds__(256) k_syrk_simple(DevLevel L, SyrkArgs a, int
   const DevNode nd = L.nodes[node];
   const int U = nd.U;
   const int c1e = a.c1 < 0 ? U + 1 : a.c1;
-  const int ti = blockIdx.y / a.tiles_c, tj = blockIdx.y % a.tiles_c;
+  int ti, tj;
+  lower_tile(blockIdx.y, a.tiles_c, ti, tj);
   const int i0 = a.r0 + ti * 64, j0 = a.c0 + tj * 64;
-  if (i0 > U || j0 >= c1e || i0 + 63 < j0) return;
+  if (i0 > U || j0 >= c1e) return;
   T* F = frame_ptr<T>(L, node, s);
   const int ld = nd.ld;
   int pl;
@@ -1349,6 +1359,7 @@ bool syrk_uses_big_tile(const DevLevel& L, int k0, int k1, int r0, int c0, int c
 
 hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1, int n_samples, bool mfma,
                        int tile, hipStream_t st) {
+  if (r0 != c0) return hipErrorInvalidValue;  // the tile grids hold the tiles on or below the diagonal
   if (k1 <= k0) return hipSuccess;
   SyrkArgs a{k0, k1, r0, c0, c1, 0, 0, 0};
   const int rows = L.max_U + 1 - r0;
@@ -1372,7 +1383,7 @@ hipError_t launch_syrk(const DevLevel& L, int k0, int k1, int r0, int c0, int c1
   a.tiles_c = ceil_div(c1 < 0 ? cols - a.sep : cols, TM);
   a.tiles_r = tr;
   if (tr > 0 && a.tiles_c > 0) {
-    dim3 grid(L.n_nodes * n_samples, tr * a.tiles_c), block(256);
+    dim3 grid(L.n_nodes * n_samples, lower_tile_count(tr, a.tiles_c)), block(256);
     if (big) {
       const long long pairs8 = (long long)ceil_div(L.n_nodes * n_samples, 8) * 8;
       const long long nwg = pairs8 * lower_tile_count(tr, a.tiles_c);
