@@ -367,6 +367,18 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f32(DevLevel L, SyrkArgs a, i
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.f;
   float racc = 0.f;
+  // the current values of the wave's 32 x 32 block are read before the K loop
+  // (their latency overlaps the first chunk's) and kept apart from the
+  // accumulators, so S~ - P P^T is still rounded once
+  float old[16];
+  if (!rhs_wave) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int i = i0 + wr * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+      const int j = j0 + wc * 32 + (lane & 31);
+      old[v] = syrk_old(F, ld, U, i, j);
+    }
+  }
   for (int kb = a.k0; kb < a.k1; kb += KC) {
     __syncthreads();
     syrk_load_chunk<float, true>(As, Bs, Pb, pl, U, i0, j0, kb, a.k1);
@@ -387,13 +399,6 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f32(DevLevel L, SyrkArgs a, i
     const int j = j0 + lane;
     if (j < c1e) F[(long long)U * ld + j] -= racc;
     return;
-  }
-  float old[16];
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-    const int i = i0 + wr * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-    const int j = j0 + wc * 32 + (lane & 31);
-    old[v] = syrk_old(F, ld, U, i, j);
   }
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
@@ -435,6 +440,12 @@ __global__ void __launch_bounds__(256) k_syrk_tall_f32(DevLevel L, SyrkArgs a, i
   floatx16 acc;
 #pragma unroll
   for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+  // current values read before the K loop, kept apart from the accumulators
+  const int j = j0 + (lane & 31);
+  const int ib = i0 + w * 32 + (lane >> 5) * 4;
+  float old[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) old[v] = syrk_old(F, ld, U, ib + (v >> 2) * 8 + (v & 3), j);
   for (int kb = a.k0; kb < a.k1; kb += KC) {
     float va[16], vb[4];
 #pragma unroll
@@ -452,11 +463,6 @@ __global__ void __launch_bounds__(256) k_syrk_tall_f32(DevLevel L, SyrkArgs a, i
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[w * 32 + (lane & 31)][kk + (lane >> 5)],
                                                  Bs[lane & 31][kk + (lane >> 5)], acc, 0, 0, 0);
   }
-  const int j = j0 + (lane & 31);
-  const int ib = i0 + w * 32 + (lane >> 5) * 4;
-  float old[16];
-#pragma unroll
-  for (int v = 0; v < 16; ++v) old[v] = syrk_old(F, ld, U, ib + (v >> 2) * 8 + (v & 3), j);
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
     const int i = ib + (v >> 2) * 8 + (v & 3);
