@@ -280,3 +280,44 @@ def test_reused_frames_match_kept_frames(H, prec):
         t.close()
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+def test_large_tile_schur_fp32_vs_fp64(H):
+    """The 128 x 128 float32 Schur-update tiles (levels with |gamma| >= 96 and
+    at least 192 rows below the interface: the three-workgroup K loop, the
+    diagonal tiles' skipped blocks and their load row, the compact tile grid)
+    give S_omega and g_omega within float32 rounding of the float64 levels.
+    The float64 path is the one certified node by node against the dense
+    Schur complement (test_node_schur_bruteforce) and end to end against the
+    oracle; the float32 frames are compared with it at 511^2, where the dense
+    brute force no longer fits, on the first, middle and last node of every
+    level that takes the large tile (measured about 3e-7 for S at 2047^2)."""
+    from workload import make_workload
+
+    w = make_workload("s_511", n_samples=1)
+    S = {}
+    for prec in (H.HDD_FP64, H.HDD_FP32_REFINE):
+        o = H.hdd_default_opts(w.n, prec, leaf=w.leaf, flags=H.HDD_FLAG_KEEP_FRAMES)
+        t = H.HDD(o, 1)
+        t.build(w.kappa, w.f)
+        assert t.sync() == 0
+        levels = H.hdd_plan_summary(o)["levels"]
+        for d in range(levels - 1):
+            lv = H.hdd_plan_level(o, d)
+            big = lv["gam"] >= 96 and lv["max_U"] + 1 - lv["gam"] >= 192
+            if prec == H.HDD_FP32_REFINE and (lv["fp64"] or not big):
+                continue
+            for k in sorted({0, lv["nodes"] // 2, lv["nodes"] - 1}):
+                S[(prec, d, k)] = t.node_schur(0, d, k)[:2]
+        t.close()
+    checked = 0
+    for (prec, d, k), (s32, g32) in S.items():
+        if prec != H.HDD_FP32_REFINE:
+            continue
+        s64, g64 = S[(H.HDD_FP64, d, k)]
+        eS = np.abs(s32 - s64).max() / np.abs(s64).max()
+        eg = np.abs(g32 - g64).max() / np.abs(g64).max()
+        say(f"  depth {d} node {k}: |Gamma| {len(g64)} S {eS:.2e} g {eg:.2e}")
+        assert eS < 1e-5 and eg < 1e-4, (d, k, eS, eg)
+        checked += 1
+    assert checked >= 6
