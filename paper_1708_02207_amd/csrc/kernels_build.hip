@@ -574,7 +574,7 @@ __global__ void __launch_bounds__(256) k_syrk_mfma_f64(DevLevel L, SyrkArgs a, i
 // the blocks above the diagonal issue no MFMAs, and the wave whose block
 // lies wholly above it forms the load row U instead (the tiles stop at row
 // U - 1, so a frame of 128 m + 1 rows needs no further row of tiles).  V4:
-// 16-byte loads (ld % 4 == 0 and k0 % 4 == 0, frames with 64 or more rows).
+// 16-byte operand loads (operand row stride pl % 4 == 0 and k0 % 4 == 0).
 template <bool V4, int KC>
 __device__ __forceinline__ void syrk128_tile(float (*As)[128][KC + 1], float (*Bs)[128][KC + 1], float* F, int ld,
                                              const float* Pb, int pl, int U, int Ue, int i0, int j0,
